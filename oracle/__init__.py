@@ -1,0 +1,230 @@
+"""ctypes binding of the plain FP64 CPU oracle (``sscn_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's
+CPU-baseline leg are the only callers.  The product path never imports this
+package, and this package imports nothing from the product.
+
+Every state crosses as a numpy array of shape ``(nz, ny, nx)`` (x fastest), of
+dtype complex128; imaginary-time states are passed with zero imaginary part and
+come back real-valued in complex storage.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+IMAG = 0
+REAL = 1
+
+TRACE_COLS = ("step", "norm", "mu", "energy", "K", "P", "I",
+              "mx", "my", "mz", "mx2", "my2", "mz2")
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int),
+        ("n", ctypes.c_int * 3),
+        ("dx", ctypes.c_double * 3),
+        ("omega", ctypes.c_double * 3),
+        ("g", ctypes.c_double),
+        ("dt", ctypes.c_double),
+        ("mode", ctypes.c_int),
+        ("renorm_every", ctypes.c_int),
+    ]
+
+
+@dataclass
+class Problem:
+    """Oracle-side problem description (unused axes: n = 1)."""
+    dim: int
+    n: tuple
+    dx: tuple
+    omega: tuple
+    g: float
+    dt: float
+    mode: int = IMAG
+    renorm_every: int = 1
+
+    def c(self) -> _Problem:
+        p = _Problem()
+        p.dim = int(self.dim)
+        n = list(self.n) + [1] * (3 - len(self.n))
+        dx = list(self.dx) + [1.0] * (3 - len(self.dx))
+        om = list(self.omega) + [0.0] * (3 - len(self.omega))
+        for a in range(3):
+            p.n[a] = int(n[a])
+            p.dx[a] = float(dx[a])
+            p.omega[a] = float(om[a])
+        p.g = float(self.g)
+        p.dt = float(self.dt)
+        p.mode = int(self.mode)
+        p.renorm_every = int(self.renorm_every)
+        return p
+
+    @property
+    def shape(self):
+        n = list(self.n) + [1] * (3 - len(self.n))
+        return (n[2], n[1], n[0])
+
+
+_lib = None
+
+
+def load():
+    """Load (never build) the oracle library; tests build it beforehand."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"oracle library missing: {LIB_PATH}; run oracle.build.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    dp = ctypes.POINTER(ctypes.c_double)
+    pp = ctypes.POINTER(_Problem)
+    lib.orc_thomas.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, dp, dp]
+    lib.orc_cn_line.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, dp, dp]
+    lib.orc_observe.argtypes = [pp, dp, dp]
+    lib.orc_potential.argtypes = [pp, dp]
+    lib.orc_substep.argtypes = [pp, dp, ctypes.c_int]
+    lib.orc_run.argtypes = [pp, dp, ctypes.c_long, ctypes.c_long, ctypes.c_int,
+                            ctypes.c_double, dp, ctypes.c_long,
+                            ctypes.POINTER(ctypes.c_long), ctypes.POINTER(ctypes.c_long)]
+    lib.orc_threads.argtypes = []
+    lib.orc_density_1d.argtypes = [pp, dp, ctypes.c_int, dp]
+    lib.orc_density_2d.argtypes = [pp, dp, ctypes.c_int, dp]
+    for f in (lib.orc_thomas, lib.orc_cn_line, lib.orc_observe, lib.orc_potential,
+              lib.orc_substep, lib.orc_run, lib.orc_threads, lib.orc_density_1d,
+              lib.orc_density_2d):
+        f.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _as_state(prob: Problem, psi) -> np.ndarray:
+    a = np.ascontiguousarray(np.asarray(psi, dtype=np.complex128).reshape(prob.shape))
+    return a.copy()
+
+
+def thomas(n: int, sigma: complex, rhs) -> np.ndarray:
+    """Solve tridiag(-sigma, 1+2 sigma, -sigma) x = rhs (Thomas, FP64)."""
+    r = np.ascontiguousarray(np.asarray(rhs, dtype=np.complex128))
+    x = np.zeros(n, dtype=np.complex128)
+    rc = load().orc_thomas(n, float(np.real(sigma)), float(np.imag(sigma)),
+                           _ptr(r.view(np.float64)), _ptr(x.view(np.float64)))
+    if rc:
+        raise ValueError(f"orc_thomas rc={rc}")
+    return x
+
+
+def cn_line(n: int, sigma: complex, u) -> np.ndarray:
+    """One CN kinetic substep (1+sT)v = (1-sT)u on a single line."""
+    uu = np.ascontiguousarray(np.asarray(u, dtype=np.complex128))
+    v = np.zeros(n, dtype=np.complex128)
+    rc = load().orc_cn_line(n, float(np.real(sigma)), float(np.imag(sigma)),
+                            _ptr(uu.view(np.float64)), _ptr(v.view(np.float64)))
+    if rc:
+        raise ValueError(f"orc_cn_line rc={rc}")
+    return v
+
+
+def potential(prob: Problem) -> np.ndarray:
+    v = np.zeros(prob.shape, dtype=np.float64)
+    pc = prob.c()
+    rc = load().orc_potential(ctypes.byref(pc), _ptr(v))
+    if rc:
+        raise ValueError(f"orc_potential rc={rc}")
+    return v
+
+
+def substep(prob: Problem, psi, which: int) -> np.ndarray:
+    """which = -1: pointwise substep; 0/1/2: CN sweep along x/y/z."""
+    a = _as_state(prob, psi)
+    pc = prob.c()
+    rc = load().orc_substep(ctypes.byref(pc), _ptr(a.view(np.float64)), int(which))
+    if rc:
+        raise ValueError(f"orc_substep rc={rc}")
+    return a
+
+
+@dataclass
+class Observables:
+    norm: float
+    mu: float
+    energy: float
+    K: float
+    P: float
+    I: float
+    mean: tuple = field(default=(0.0, 0.0, 0.0))
+    msq: tuple = field(default=(0.0, 0.0, 0.0))
+
+
+def observe(prob: Problem, psi) -> Observables:
+    a = _as_state(prob, psi)
+    out = np.zeros(12)
+    pc = prob.c()
+    rc = load().orc_observe(ctypes.byref(pc), _ptr(a.view(np.float64)), _ptr(out))
+    if rc:
+        raise ValueError(f"orc_observe rc={rc}")
+    return Observables(*out[:6], tuple(out[6:9]), tuple(out[9:12]))
+
+
+@dataclass
+class RunResult:
+    psi: np.ndarray
+    trace: np.ndarray        # rows of TRACE_COLS
+    steps: int
+    converged: bool
+
+
+def run(prob: Problem, psi, nsteps: int, observe_every: int = 0,
+        mu_tol: float = 0.0, first_step: int = 1) -> RunResult:
+    """Propagate nsteps SSCN steps (see sscn_oracle.c for the definition)."""
+    a = _as_state(prob, psi)
+    cap = (nsteps // observe_every + 2) if observe_every > 0 else 2
+    trace = np.zeros((cap, len(TRACE_COLS)))
+    rows = ctypes.c_long(0)
+    done = ctypes.c_long(0)
+    pc = prob.c()
+    rc = load().orc_run(ctypes.byref(pc), _ptr(a.view(np.float64)), int(nsteps),
+                        int(first_step), int(observe_every), float(mu_tol),
+                        _ptr(trace), cap, ctypes.byref(rows), ctypes.byref(done))
+    if rc < 0:
+        raise ValueError(f"orc_run rc={rc}")
+    return RunResult(a, trace[: rows.value].copy(), int(done.value), rc == 0)
+
+
+def density_1d(prob: Problem, psi, keep: int) -> np.ndarray:
+    a = _as_state(prob, psi)
+    n = (list(prob.n) + [1, 1])[keep]
+    out = np.zeros(n)
+    pc = prob.c()
+    rc = load().orc_density_1d(ctypes.byref(pc), _ptr(a.view(np.float64)), int(keep), _ptr(out))
+    if rc:
+        raise ValueError(f"orc_density_1d rc={rc}")
+    return out
+
+
+def density_2d(prob: Problem, psi, drop: int) -> np.ndarray:
+    a = _as_state(prob, psi)
+    n = list(prob.n)
+    keep = [ax for ax in range(3) if ax != drop]
+    out = np.zeros((n[keep[1]], n[keep[0]]))
+    pc = prob.c()
+    rc = load().orc_density_2d(ctypes.byref(pc), _ptr(a.view(np.float64)), int(drop),
+                               _ptr(out.reshape(-1)))
+    if rc:
+        raise ValueError(f"orc_density_2d rc={rc}")
+    return out
+
+
+def threads() -> int:
+    return int(load().orc_threads())

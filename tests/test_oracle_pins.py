@@ -1,0 +1,339 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle.
+
+Each test fixes the oracle to something independent of its own code: a dense
+linear-algebra solve, a closed form of the discrete or continuum problem, a
+conservation law, a physical theorem, or a brute-force dense formulation.
+Together they are chosen so that a dropped term, a wrong sign, a wrong index
+or stride, a transposed axis or a wrong coefficient in the oracle fails at
+least one of them.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import IMAG, REAL, Problem
+from paper_1605_03958_amd import inputs
+import ref_dense
+
+pytestmark = pytest.mark.filterwarnings("ignore::numpy.exceptions.ComplexWarning")
+
+
+def _tridiag(n, s):
+    return (np.diag(np.full(n, 1 + 2 * s)) + np.diag(np.full(n - 1, -s), 1)
+            + np.diag(np.full(n - 1, -s), -1))
+
+
+# ---------------------------------------------------------------------------
+# Line solver
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 8, 17, 33])
+@pytest.mark.parametrize("sigma", [0.025, 0.005j, 1.0, 10.0, 0.3 + 0.2j])
+def test_thomas_matches_dense_solve(n, sigma):
+    rng = np.random.default_rng(n)
+    r = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    x = oracle.thomas(n, sigma, r)
+    ref = np.linalg.solve(_tridiag(n, complex(sigma)), r)
+    assert np.max(np.abs(x - ref)) <= 1e-13 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("n", [1, 5, 16, 33])
+@pytest.mark.parametrize("sigma", [0.025, 0.005j, 0.7, 0.4j])
+def test_cn_line_on_sine_modes(n, sigma):
+    """Sine modes sin(pi k (i+1)/(n+1)) are eigenvectors of tridiag(-1,2,-1)
+    with eigenvalue tau_k = 2 - 2 cos(pi k/(n+1)); one CN substep multiplies
+    mode k by exactly (1 - sigma tau_k) / (1 + sigma tau_k)."""
+    i = np.arange(n)
+    for k in range(1, n + 1):
+        u = np.sin(math.pi * k * (i + 1) / (n + 1)).astype(np.complex128)
+        tau = 2.0 - 2.0 * math.cos(math.pi * k / (n + 1))
+        lam = (1 - sigma * tau) / (1 + sigma * tau)
+        v = oracle.cn_line(n, sigma, u)
+        assert np.max(np.abs(v - lam * u)) <= 1e-14 * max(1.0, np.max(np.abs(u)))
+
+
+# ---------------------------------------------------------------------------
+# Whole step against a dense Kronecker-product formulation
+# ---------------------------------------------------------------------------
+
+CASES = [
+    (3, (5, 4, 3), (0.31, 0.27, 0.22), (1.0, 1.7, 2.3)),
+    (1, (7, 1, 1), (0.4, 1.0, 1.0), (1.3, 0.0, 0.0)),
+    (2, (6, 5, 1), (0.35, 0.3, 1.0), (0.9, 2.1, 0.0)),
+    (3, (2, 3, 4), (0.5, 0.45, 0.4), (1.1, 0.6, 1.9)),
+]
+
+
+@pytest.mark.parametrize("dim,n,dx,omega", CASES)
+@pytest.mark.parametrize("mode", [IMAG, REAL])
+@pytest.mark.parametrize("renorm_every", [1, 3])
+def test_run_matches_dense_kron(dim, n, dx, omega, mode, renorm_every):
+    g, dt, steps = 3.0, 0.037, 7
+    rng = np.random.default_rng(7 + dim)
+    shape = (n[2], n[1], n[0])
+    psi0 = rng.standard_normal(shape) + (1j * rng.standard_normal(shape) if mode == REAL else 0)
+    psi0 = psi0 / np.sqrt(np.prod(dx[:dim]) * np.sum(np.abs(psi0) ** 2))
+    prob = Problem(dim, n, dx, omega, g, dt, mode, renorm_every)
+    got = oracle.run(prob, psi0, steps).psi
+    V = inputs.trap_potential(dim, n, dx, omega)
+    ref = ref_dense.dense_run(psi0, n, dx, dim, V, g, dt, mode == REAL, steps, renorm_every)
+    assert np.max(np.abs(got - ref)) <= 1e-13 * np.max(np.abs(ref))
+
+
+def test_axis_substeps_match_dense_operators():
+    """Each single-axis sweep equals the dense Kronecker factor of that axis."""
+    dim, n, dx = 3, (5, 4, 3), (0.3, 0.25, 0.2)
+    prob = Problem(dim, n, dx, (1, 1, 1), 0.0, 0.05, REAL, 0)
+    rng = np.random.default_rng(3)
+    shape = (3, 4, 5)
+    psi = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    for a in range(3):
+        C = ref_dense.cn_matrix(n[a], ref_dense.sigma_of(0.05, dx[a], True))
+        ref = np.moveaxis(np.tensordot(C, np.moveaxis(psi, 2 - a, 0), axes=(1, 0)), 0, 2 - a)
+        got = oracle.substep(prob, psi, a)
+        assert np.max(np.abs(got - ref)) <= 1e-14 * np.max(np.abs(ref))
+
+
+# ---------------------------------------------------------------------------
+# Observables
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dim,n,k", [(1, (9, 1, 1), (2, 1, 1)),
+                                     (2, (7, 6, 1), (1, 3, 1)),
+                                     (3, (5, 6, 4), (2, 1, 3))])
+def test_box_sine_mode_energy(dim, n, k):
+    """With V = 0 and g = 0, a product of box sine modes is an eigenvector of
+    -1/2 Lap_h with eigenvalue sum_a tau_{k_a} / (2 dx_a^2); mu and E equal
+    it exactly and K = mu * N.  Pins the kinetic quadrature, its ghost edges,
+    the 1/2 and the dx^2."""
+    dx = (0.3, 0.45, 0.2)
+    prob = Problem(dim, n, dx, (0, 0, 0), 0.0, 0.01, IMAG, 1)
+    axes = []
+    lam = 0.0
+    for a in range(3):
+        i = np.arange(n[a])
+        if a < dim:
+            axes.append(np.sin(math.pi * k[a] * (i + 1) / (n[a] + 1)))
+            lam += (2 - 2 * math.cos(math.pi * k[a] / (n[a] + 1))) / (2 * dx[a] ** 2)
+        else:
+            axes.append(np.ones(1))
+    psi = np.einsum("k,j,i->kji", axes[2], axes[1], axes[0])
+    ob = oracle.observe(prob, psi)
+    assert abs(ob.mu - lam) <= 1e-13 * lam
+    assert abs(ob.energy - lam) <= 1e-13 * lam
+    assert abs(ob.K - lam * ob.norm) <= 1e-13 * lam * ob.norm
+    assert ob.P == 0.0
+
+
+def test_gaussian_observable_integrals():
+    """HO Gaussian: P = sum w_a/4, I = prod sqrt(w_a/(2 pi)) (spectrally
+    accurate on a fine grid), K = sum w_a/4 up to O(dx^2)."""
+    om = (1.0, 1.5, 2.0)
+    for dx in (0.1, 0.05):
+        n = tuple(int(round(18 / math.sqrt(w) / dx)) for w in om)
+        psi = inputs.ho_gaussian(3, n, (dx,) * 3, om, noise=0.0)
+        prob = Problem(3, n, (dx,) * 3, om, 0.0, 0.01, IMAG, 1)
+        ob = oracle.observe(prob, psi)
+        assert abs(ob.norm - 1) < 1e-11
+        assert abs(ob.P - sum(om) / 4) < 1e-11
+        assert abs(ob.I - np.prod([math.sqrt(w / (2 * math.pi)) for w in om])) < 1e-11
+        # forward-difference kinetic energy of a Gaussian: sum_a w_a/4 - O(w_a^2 dx^2)
+        k_err = ob.K - sum(om) / 4
+        assert abs(k_err) < 0.05 * sum(w * w for w in om) * dx * dx
+    # moments: centred Gaussian <x> = 0, <x^2> = 1/(2 w)
+    for a in range(3):
+        assert abs(ob.mean[a]) < 1e-12
+        assert abs(ob.msq[a] - 1 / (2 * om[a])) < 1e-10
+
+
+# ---------------------------------------------------------------------------
+# Ground states (imaginary time)
+# ---------------------------------------------------------------------------
+
+def test_ho_mu_matches_dense_eigenvectors():
+    """g = 0 in 3D: the converged state is the product of the dominant
+    eigenvectors of the per-axis one-step maps, and mu is the sum of their
+    Rayleigh quotients with the dense 1D discrete Hamiltonians."""
+    om = (1.0, 1.5, 2.0)
+    dx = (0.3, 0.3, 0.3)
+    n = (30, 24, 20)
+    dt = 0.05
+    prob = Problem(3, n, dx, om, 0.0, dt, IMAG, 1)
+    psi0 = inputs.ho_gaussian(3, n, dx, om, noise=1e-3, seed=5)
+    res = oracle.run(prob, psi0, 600, observe_every=100)
+    mu_ref = 0.0
+    for a in range(3):
+        x = inputs.coords(n[a], dx[a])
+        v = ref_dense.dominant_state_1d(n[a], dx[a], om[a], dt, x)
+        H = ref_dense.hamiltonian_1d(n[a], dx[a], om[a], x)
+        mu_ref += v @ H @ v / (v @ v)
+    assert abs(res.trace[-1, 2] - mu_ref) < 1e-10
+
+
+def _ground_state(dim, n, dx, om, g, dt, steps, psi0=None):
+    prob = Problem(dim, n, dx, om, g, dt, IMAG, 1)
+    if psi0 is None:
+        psi0 = inputs.ho_gaussian(dim, n, dx, om, noise=0.0)
+    res = oracle.run(prob, psi0, steps, observe_every=max(1, steps // 10))
+    return prob, res
+
+
+def test_ho_mu_closed_form_second_order():
+    """g = 0, dt = 0.1 dx^2: mu = w/2 - w^2 dx^2/32 + O(dx^4) per axis (the
+    3-point Laplacian's leading error on the oscillator ground state), so the
+    residual after the correction is small and falls ~16x when dx halves."""
+    for w in (1.0, 1.5, 2.0):
+        res = []
+        for dx in (0.2, 0.1):
+            L = 9.0 / math.sqrt(w)
+            n = int(round(2 * L / dx))
+            dt = 0.1 * dx * dx
+            steps = int(round(5.0 / (w * dt)))
+            _, r = _ground_state(1, (n, 1, 1), (dx, 1, 1), (w, 0, 0), 0.0, dt, steps)
+            mu = r.trace[-1, 2]
+            res.append(mu - (w / 2 - w * w * dx * dx / 32))
+        assert abs(res[0]) < 1e-4
+        assert abs(res[0]) > 8 * abs(res[1])
+    # and the uncorrected continuum value (nu + lambda + kappa)/2 at C0's dx
+    dx = 0.2
+    mu3 = 0.0
+    for w in (1.0, 1.5, 2.0):
+        n = int(round(18 / math.sqrt(w) / dx))
+        _, r = _ground_state(1, (n, 1, 1), (dx, 1, 1), (w, 0, 0), 0.0, 0.004, int(5.0 / (w * 0.004)))
+        mu3 += r.trace[-1, 2]
+    assert abs(mu3 - 2.25) < 1e-2
+    assert abs(mu3 - (2.25 - (1 + 2.25 + 4) * dx * dx / 32)) < 1e-4
+
+
+def test_thomas_fermi_limit_1d():
+    """1D: mu -> (3 g w / 2)^(2/3) / 2 as g grows; relative error decreasing
+    in g and below 1e-3 at g = 1000."""
+    errs = []
+    for g in (10.0, 100.0, 1000.0):
+        mu_tf = inputs.mu_thomas_fermi(1, g, (1.0,))
+        R = math.sqrt(2 * mu_tf)
+        dx = 0.05
+        n = int(round(2 * (R + 6) / dx))
+        dt = 0.0025
+        psi0 = inputs.thomas_fermi(1, (n, 1, 1), (dx, 1, 1), (1.0, 0, 0), g).real
+        _, r = _ground_state(1, (n, 1, 1), (dx, 1, 1), (1.0, 0, 0), g, dt, 8000, psi0)
+        errs.append(abs(r.trace[-1, 2] - mu_tf) / mu_tf)
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[2] < 1e-3
+
+
+def test_virial_2d():
+    """Converged 2D ground state at g > 0: 2K - 2P + d g I / 2 = 0 up to
+    O(dx^2), falling ~4x when dx halves."""
+    resid = []
+    for dx in (0.2, 0.1):
+        n = int(round(16 / dx))
+        dt = 0.25 * dx * dx
+        prob, r = _ground_state(2, (n, n, 1), (dx, dx, 1), (1.0, 1.4, 0), 30.0, dt, int(12 / dt))
+        K, P, In = r.trace[-1, 4], r.trace[-1, 5], r.trace[-1, 6]
+        mu = r.trace[-1, 2]
+        resid.append(abs(2 * K - 2 * P + 2 * 0.5 * 30.0 * In) / mu)
+    assert resid[0] < 2e-2
+    assert resid[0] > 3 * resid[1]
+
+
+# ---------------------------------------------------------------------------
+# Real time
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dim,n", [(1, (64, 1, 1)), (2, (24, 20, 1)), (3, (16, 12, 10))])
+def test_real_time_norm_conservation(dim, n):
+    """Both factors of the real-time step are unitary in the dV inner product,
+    so the discrete norm is conserved to round-off."""
+    dx = (0.4, 0.5, 0.6)[:dim] + (1.0,) * (3 - dim)
+    om = (1.0, 1.5, 2.0)[:dim] + (0.0,) * (3 - dim)
+    psi0 = inputs.thomas_fermi(dim, n, dx, om, 40.0, phase_sigma=0.05, seed=1)
+    prob = Problem(dim, n, dx, om, 30.0, 0.02, REAL, 0)
+    r = oracle.run(prob, psi0, 1000, observe_every=250)
+    n0 = np.prod(dx[:dim]) * np.sum(np.abs(psi0) ** 2)
+    assert abs(r.trace[-1, 1] / n0 - 1) <= 1e-12
+
+
+def test_kohn_dipole_mode():
+    """In a harmonic trap with contact interaction <x>(t) = x0 cos(w t) for a
+    real initial state displaced by x0, whatever g is."""
+    w, x0, g = 1.3, 0.6, 25.0
+    res = []
+    for dx, dt in ((0.1, 0.004), (0.05, 0.001)):
+        n = int(round(20 / dx))
+        psi0 = inputs.ho_gaussian(1, (n, 1, 1), (dx, 1, 1), (w, 0, 0), noise=0.0, shift=(x0, 0, 0))
+        prob = Problem(1, (n, 1, 1), (dx, 1, 1), (w, 0, 0), g, dt, REAL, 0)
+        obs_every = int(round(0.25 / dt))
+        r = oracle.run(prob, psi0, int(round(3.0 / dt)), observe_every=obs_every)
+        t = r.trace[:, 0] * dt
+        err = np.max(np.abs(r.trace[:, 7] - x0 * np.cos(w * t)))
+        res.append(err)
+    assert res[0] < 0.02 * x0
+    assert res[1] < res[0]
+
+
+def test_ground_state_is_stationary_in_real_time():
+    """The imaginary-time ground state evolves as exp(-i mu t) psi_g: overlap
+    phase rate -mu, density unchanged; both errors shrink with dt."""
+    w, g, dx = 1.0, 10.0, 0.1
+    n = int(round(16 / dx))
+    errs = []
+    for dt in (0.002, 0.001):
+        prob, r = _ground_state(1, (n, 1, 1), (dx, 1, 1), (w, 0, 0), g, dt, int(15 / dt))
+        psi_g = r.psi
+        mu = r.trace[-1, 2]
+        T = 1.0
+        rp = Problem(1, (n, 1, 1), (dx, 1, 1), (w, 0, 0), g, dt, REAL, 0)
+        rr = oracle.run(rp, psi_g, int(round(T / dt)))
+        ov = np.sum(np.conj(psi_g) * rr.psi) * dx
+        phase_err = abs(np.angle(ov * np.exp(1j * mu * T)))
+        dens_err = np.max(np.abs(np.abs(rr.psi) ** 2 - np.abs(psi_g) ** 2))
+        errs.append((phase_err, dens_err))
+    assert errs[0][0] < 1e-2 and errs[0][1] < 1e-3
+    assert errs[1][0] < errs[0][0] and errs[1][1] < errs[0][1]
+
+
+# ---------------------------------------------------------------------------
+# Stop rule and integrated densities
+# ---------------------------------------------------------------------------
+
+def test_stop_rule_matches_stepwise_observation():
+    """The convergence stop equals stepping by hand and observing every 10
+    steps, stopping at the first |mu(s) - mu(s-10)| < tol."""
+    dim, n, dx, om = 2, (20, 16, 1), (0.5, 0.5, 1), (1.0, 2.0, 0)
+    prob = Problem(dim, n, dx, om, 5.0, 0.02, IMAG, 1)
+    psi0 = inputs.ho_gaussian(dim, n, dx, om, noise=1e-3, seed=9)
+    tol = 1e-6
+    r = oracle.run(prob, psi0, 100000, observe_every=10, mu_tol=tol)
+    assert r.converged
+    psi = psi0
+    prev = None
+    s = 0
+    while True:
+        psi = oracle.run(prob, psi, 10, first_step=s + 1).psi
+        s += 10
+        mu = oracle.observe(prob, psi).mu
+        if prev is not None and abs(mu - prev) < tol:
+            break
+        prev = mu
+    assert s == r.steps
+    assert np.array_equal(psi, r.psi)
+
+
+def test_integrated_densities_of_product_gaussian():
+    om = (1.0, 1.5, 2.0)
+    dx = (0.1, 0.1, 0.1)
+    n = tuple(int(round(16 / math.sqrt(w) / 0.1)) for w in om)
+    psi = inputs.ho_gaussian(3, n, dx, om, noise=0.0)
+    prob = Problem(3, n, dx, om, 0.0, 0.01, IMAG, 1)
+    for a in range(3):
+        d1 = oracle.density_1d(prob, psi, a)
+        x = inputs.coords(n[a], dx[a])
+        ref = math.sqrt(om[a] / math.pi) * np.exp(-om[a] * x * x)
+        assert np.max(np.abs(d1 - ref)) < 1e-10
+        assert abs(np.sum(d1) * dx[a] - 1) < 1e-12
+    d2 = oracle.density_2d(prob, psi, 2)
+    assert d2.shape == (n[1], n[0])
+    assert np.allclose(np.sum(d2, axis=0) * dx[1], oracle.density_1d(prob, psi, 0), atol=1e-13)
