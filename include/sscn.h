@@ -1,0 +1,189 @@
+/*
+ * sscn.h -- C ABI of the MI355X (gfx950) split-step Crank-Nicolson (SSCN)
+ * Gross-Pitaevskii propagator.
+ *
+ * The operation (the paper's program summary, "Nature of problem" and
+ * "Solution method"): the time-dependent GP equation for a condensate with
+ * contact interaction in a harmonic trap, in one, two or three dimensions,
+ * is discretised in space and time and propagated over small time steps by
+ * the split-step Crank-Nicolson method, in imaginary time (stationary
+ * states) or real time (dynamics).  In the dimensionless form used here
+ *
+ *     i dpsi/dt = [ -1/2 Lap + V + g |psi|^2 ] psi,
+ *     V = (omega_x^2 x^2 + omega_y^2 y^2 + omega_z^2 z^2) / 2,
+ *
+ * one step of length dt is: the pointwise substep
+ *     psi <- exp(-dt (V + g|psi|^2)) psi          (imaginary time)
+ *     psi <- exp(-i dt (V + g|psi|^2)) psi        (real time),
+ * then, along x, y, z in turn, the Crank-Nicolson kinetic substep
+ *     (1 + s T) v = (1 - s T) u,  T = tridiag(-1, 2, -1),
+ *     s = dt/(4 dx_a^2) (imaginary) or i dt/(4 dx_a^2) (real),
+ * with psi = 0 just outside the grid; in imaginary time the state is then
+ * renormalised to dV * sum |psi|^2 = 1 (every `renorm_every` steps).
+ *
+ * Grid: axis a has n_a points at x_a(i) = (i - (n_a - 1)/2) dx_a; unused axes
+ * (a >= dim) have n_a = 1.  Layout: x fastest, p = i + n_x (j + n_y k).
+ * State dtype by (mode, prec):
+ *     IMAG + F64 -> double        IMAG + F32 -> float
+ *     REAL + F64 -> double2 (re, im interleaved, like complex128)
+ *     REAL + F32 -> float2  (complex64)
+ * In the F32 forms the state, the pointwise substep and the line sweeps are
+ * FP32; the Thomas coefficient tables, the norm, the renormalisation and all
+ * observables stay FP64.
+ *
+ * Conventions.  0 is success, negative values are errors, positive values
+ * are informational.  Every argument is validated before any side effect.
+ * No C++ exception or abort crosses this boundary.  A handle is not thread
+ * safe; several handles may share one stream.  The library allocates no
+ * device memory: the caller owns the state and the workspace (device
+ * pointers) and the HIP stream (a hipStream_t passed as void*, NULL = the
+ * null stream), all of which must outlive the handle.
+ */
+#ifndef SSCN_H
+#define SSCN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SSCN_ABI_VERSION 1
+
+/* status codes */
+#define SSCN_OK              0
+#define SSCN_NOT_CONVERGED   1   /* informational: step cap reached first */
+#define SSCN_E_INVALID      -1   /* bad argument or problem */
+#define SSCN_E_HIP          -2   /* a HIP runtime call failed */
+#define SSCN_E_NONFINITE    -3   /* norm or chemical potential is NaN/Inf */
+#define SSCN_E_NOSPACE      -4   /* slot busy / buffer too small */
+#define SSCN_E_UNSUPPORTED  -5   /* valid problem outside this build's limits */
+
+/* mode and precision */
+#define SSCN_IMAG 0
+#define SSCN_REAL 1
+#define SSCN_F64  0
+#define SSCN_F32  1
+
+typedef struct {
+    int32_t dim;            /* 1, 2 or 3 */
+    int32_t n[3];           /* points per axis; axes >= dim must be 1 */
+    double  dx[3];          /* spacing per axis (> 0 for axes < dim) */
+    double  omega[3];       /* trap frequencies (>= 0) */
+    double  g;              /* nonlinearity used by the propagation */
+    double  dt;             /* time step (> 0) */
+    int32_t mode;           /* SSCN_IMAG or SSCN_REAL */
+    int32_t prec;           /* SSCN_F64 or SSCN_F32 */
+    int32_t renorm_every;   /* IMAG: >= 1 (renormalise every k steps); REAL: 0 */
+    int32_t observe_every;  /* >= 0; observation interval of sscn_run / batch */
+} sscn_problem;
+
+typedef struct {
+    int64_t step;           /* steps taken since create */
+    double  norm;           /* dV sum |psi|^2 */
+    double  mu;             /* (K + P + g I) / norm */
+    double  energy;         /* (K + P + g I / 2) / norm */
+    double  ekin;           /* K = 1/2 dV sum_a sum_edges |dpsi|^2 / dx_a^2 */
+    double  epot;           /* P = dV sum V |psi|^2 */
+    double  eint;           /* I = dV sum |psi|^4 */
+    double  mean[3];        /* <x_a> */
+    double  msq[3];         /* <x_a^2> */
+    int32_t status;         /* SSCN_OK or SSCN_E_NONFINITE */
+    int32_t pad_;
+} sscn_obs;
+
+typedef struct sscn_solver sscn_solver;
+
+/* SSCN_ABI_VERSION of the loaded library. */
+int sscn_abi_version(void);
+
+/* Static text for a status code (never NULL). */
+const char *sscn_status_string(int status);
+
+/* Host-only check of a problem (no GPU access).  SSCN_E_INVALID if dim is
+ * not 1..3, an n_a < 1, n_a != 1 on an unused axis, dx_a <= 0 or non-finite
+ * on a used axis, omega < 0 or non-finite, g non-finite, dt <= 0 or
+ * non-finite, mode/prec out of range, renorm_every < 1 in IMAG or != 0 in
+ * REAL, observe_every < 0.  SSCN_E_UNSUPPORTED if the grid exceeds this
+ * build's limits (more than 2^40 points). */
+int sscn_validate(const sscn_problem *pb);
+
+/* Bytes of the caller-owned state (points * element size) and workspace.
+ * The workspace holds the FP64 Thomas tables, reduction partials and device
+ * scalars; the two sums are what a solve keeps resident in HBM. */
+int sscn_state_bytes(const sscn_problem *pb, size_t *bytes);
+int sscn_workspace_bytes(const sscn_problem *pb, size_t *bytes);
+
+/* Bind a solver to caller memory: d_psi (state, layout above, at least
+ * sscn_state_bytes), d_ws (workspace, at least sscn_workspace_bytes, 256-byte
+ * aligned), hip_stream.  Precomputes the FP64 Thomas tables of every axis on
+ * the host and uploads them to d_ws on the stream (the call waits for that
+ * copy).  The state is not touched.  Errors: SSCN_E_INVALID (bad problem,
+ * NULL pointer, misaligned workspace), SSCN_E_HIP. */
+int sscn_create(const sscn_problem *pb, void *d_psi, void *d_ws, void *hip_stream,
+                sscn_solver **out);
+
+/* Enqueue nsteps >= 0 SSCN steps on the stream and return.  When the stream
+ * reaches the end of the call the state is complete: in imaginary time it is
+ * renormalised if the last step was a renormalisation step. */
+int sscn_step(sscn_solver *s, int64_t nsteps);
+
+/* Observables of the current state; waits for the stream.  Returns
+ * SSCN_E_NONFINITE (and fills out) if the norm or mu is NaN or Inf. */
+int sscn_observe(sscn_solver *s, sscn_obs *out);
+
+/* Propagate until |mu(t) - mu(t - observe_every)| < mu_tol at an observation
+ * step (observe_every from the problem, >= 1), or until max_steps more steps
+ * were taken.  Rows of the observation trace go to trace[0..trace_cap) and
+ * their count to *rows (either may be NULL/0).  Returns SSCN_OK on
+ * convergence, SSCN_NOT_CONVERGED at the cap, SSCN_E_NONFINITE if the state
+ * blew up.  Waits for the stream at every observation. */
+int sscn_run(sscn_solver *s, int64_t max_steps, double mu_tol, sscn_obs *trace,
+             int64_t trace_cap, int64_t *rows);
+
+/* Change the nonlinearity for later steps and observables (a quench).
+ * SSCN_E_INVALID if g is not finite. */
+int sscn_set_g(sscn_solver *s, double g);
+
+/* Enqueue nsteps steps exactly as sscn_step does, with HIP events recorded
+ * around every kernel, wait, and report the mean duration in milliseconds of
+ * each kernel class over the steps in ms[0..SSCN_NKERNELS).  Classes: 0 the
+ * pointwise + x sweep, 1 the y sweep, 2 the z sweep (+ norm partials),
+ * 3 the norm finalisation, 4 the end-of-call scale pass; a class that did not
+ * run reports 0.  Timing aid for the benchmark; results are those of
+ * sscn_step. */
+#define SSCN_NKERNELS 5
+int sscn_step_timed(sscn_solver *s, int64_t nsteps, double *ms);
+
+/* Tile hints (used by the tuner): for problems of pb's shape (dim, n, mode,
+ * prec), use chunk[0] points per thread on x lines and chunk[1], chunk[2] on
+ * y and z lines (powers of two <= 64; 0 keeps the default).  Applies to later
+ * sscn_workspace_bytes / sscn_create calls of that shape, process-wide.
+ * SSCN_E_INVALID for a bad problem or chunk, SSCN_E_UNSUPPORTED if a chunk
+ * does not fit the register-resident kernels for that shape. */
+int sscn_set_tile_hint(const sscn_problem *pb, const int32_t chunk[3]);
+int sscn_clear_tile_hints(void);
+
+/* Kernel plan of a problem, 5 ints per axis (x, y, z): kind (0 ROW: lanes
+ * along the line, 1 COL: lanes across lines, 2 one-thread-per-line
+ * fallback, -1 unused axis), points per thread, waves per line group, grid
+ * and block size.  info needs cap >= 15 entries. */
+int sscn_plan_info(const sscn_problem *pb, int32_t *info, int32_t cap);
+
+/* Free the handle's host state (the caller's device memory is untouched).
+ * Waits for the stream. */
+int sscn_destroy(sscn_solver *s);
+
+/* Integrated densities (the paper's n_1D and n_2D outputs, integrating
+ * |psi|^2 over the other axes): out is a caller-owned device buffer of
+ * n[keep] doubles (1D) or of the two remaining axes' points in layout order
+ * (2D, dim == 3 only).  Enqueued on the stream; FP64. */
+int sscn_density_1d(sscn_solver *s, int keep, void *d_out);
+int sscn_density_2d(sscn_solver *s, int drop, void *d_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SSCN_H */

@@ -1,0 +1,680 @@
+// sscn_api.cpp -- host runtime behind include/sscn.h.
+//
+// Validation, FP64 Thomas-table precompute, workspace layout, kernel
+// planning and launch of the SSCN step on a caller-owned HIP stream.  The
+// library allocates no device memory: the state and the workspace belong to
+// the caller.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "sscn.h"
+#include "sscn_launch.hpp"
+#include "sscn_plan.hpp"
+
+using namespace sscn;
+
+namespace sscn {
+
+static int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+static int pow2ceil(int64_t v)
+{
+    int p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+static size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+int elem_of(const sscn_problem &pb)
+{
+    return (pb.mode == SSCN_REAL ? 2 : 0) + (pb.prec == SSCN_F32 ? 1 : 0);
+}
+
+size_t elem_bytes(int elem)
+{
+    static const size_t b[4] = {8, 4, 16, 8};
+    return b[elem];
+}
+
+int validate(const sscn_problem *pb)
+{
+    if (!pb) return SSCN_E_INVALID;
+    if (pb->dim < 1 || pb->dim > 3) return SSCN_E_INVALID;
+    double pts = 1.0;
+    for (int a = 0; a < 3; ++a) {
+        if (pb->n[a] < 1) return SSCN_E_INVALID;
+        if (a >= pb->dim && pb->n[a] != 1) return SSCN_E_INVALID;
+        if (a < pb->dim && !(std::isfinite(pb->dx[a]) && pb->dx[a] > 0.0)) return SSCN_E_INVALID;
+        if (!(std::isfinite(pb->omega[a]) && pb->omega[a] >= 0.0)) return SSCN_E_INVALID;
+        pts *= pb->n[a];
+    }
+    if (!std::isfinite(pb->g)) return SSCN_E_INVALID;
+    if (!(std::isfinite(pb->dt) && pb->dt > 0.0)) return SSCN_E_INVALID;
+    if (pb->mode != SSCN_IMAG && pb->mode != SSCN_REAL) return SSCN_E_INVALID;
+    if (pb->prec != SSCN_F64 && pb->prec != SSCN_F32) return SSCN_E_INVALID;
+    if (pb->mode == SSCN_IMAG && pb->renorm_every < 1) return SSCN_E_INVALID;
+    if (pb->mode == SSCN_REAL && pb->renorm_every != 0) return SSCN_E_INVALID;
+    if (pb->observe_every < 0) return SSCN_E_INVALID;
+    if (pts > 1099511627776.0) return SSCN_E_UNSUPPORTED;
+    return SSCN_OK;
+}
+
+// Largest chunk length per thread kept in registers, by element size.
+static int cmax_row(size_t S) { return S >= 16 ? 8 : (S >= 8 ? 16 : 32); }
+static int cmax_col(size_t S) { return S >= 16 ? 16 : (S >= 8 ? 32 : 64); }
+
+int make_plan(const sscn_problem &pb, const TileOverride *ov, Plan &P)
+{
+    std::memset(&P, 0, sizeof(P));
+    P.elem = elem_of(pb);
+    P.S = elem_bytes(P.elem);
+    P.npts = (int64_t)pb.n[0] * pb.n[1] * pb.n[2];
+    const bool imag = pb.mode == SSCN_IMAG;
+    const int64_t nx = pb.n[0], ny = pb.n[1];
+    for (int a = 0; a < pb.dim; ++a) {
+        AxisPlan &X = P.ax[a];
+        const int64_t n = pb.n[a];
+        X.n = (int)n;
+        X.nlines = P.npts / n;
+        double s = pb.dt / (4.0 * pb.dx[a] * pb.dx[a]);
+        X.sig_re = imag ? s : 0.0;
+        X.sig_im = imag ? 0.0 : s;
+        X.kind = K_STREAM;
+        if (a == 0) {
+            X.m1 = (int)ny;
+            X.s1 = nx;
+            X.s2 = nx * ny;
+            X.stride = 1;
+            int c = pow2ceil(ceil_div(n, 64));
+            int wpl = 1;
+            if (ov && ov->row_c > 0) {
+                c = ov->row_c;
+                wpl = pow2ceil(ceil_div(n, 64 * (int64_t)c));
+            } else if (c > cmax_row(P.S)) {
+                c = cmax_row(P.S);
+                wpl = pow2ceil(ceil_div(n, 64 * (int64_t)c));
+            }
+            if (wpl <= 16 && c <= cmax_row(P.S) && (int64_t)c * 64 * wpl >= n) {
+                X.kind = K_ROW;
+                X.C = c;
+                X.wpl = wpl;
+                X.lpb = std::max(1, 4 / wpl);
+                X.block = 64 * wpl * X.lpb;
+                X.grid = (int)std::min<int64_t>(ceil_div(X.nlines, X.lpb), 1 << 20);
+                X.lds = (size_t)X.lpb * wpl * 4 * P.S;
+                X.tab_entries = (size_t)c * 64 * wpl;
+            }
+        } else {
+            X.m1 = (int)nx;
+            X.s1 = 1;
+            X.s2 = (a == 1) ? nx * ny : nx;
+            X.stride = (a == 1) ? nx : nx * ny;
+            int c = pow2ceil(ceil_div(n, 16));
+            if (ov && ov->col_c[a] > 0) c = ov->col_c[a];
+            const int64_t W = ceil_div(n, c);
+            if (c <= cmax_col(P.S) && W <= 16) {
+                X.kind = K_COL;
+                X.C = c;
+                X.W = (int)W;
+                X.block = 64 * (int)W;
+                X.grid = (int)ceil_div(X.nlines, 64);
+                X.lds = (size_t)2 * W * 64 * P.S;
+                X.tab_entries = (size_t)W * c;
+            }
+        }
+        if (X.kind == K_STREAM) {
+            X.block = 256;
+            X.grid = (int)ceil_div(X.nlines, 256);
+            X.tab_entries = (size_t)n;
+        }
+        if (X.grid > 2147483647 / 2) return SSCN_E_UNSUPPORTED;
+    }
+    const AxisPlan &L = P.ax[pb.dim - 1];
+    P.sep_pointwise = P.ax[0].kind == K_STREAM;
+    P.sep_norm = imag && L.kind == K_STREAM;
+    P.pw_grid = (int)std::min<int64_t>(ceil_div(P.npts, 256), 4096);
+    P.np_norm = P.sep_norm ? P.pw_grid : L.grid;
+    P.obs_grid = (int)std::min<int64_t>(ceil_div(P.npts, 256), 1024);
+
+    size_t off = 0;
+    P.off_scal = off;
+    off += 256;
+    P.off_obs = off;
+    off += 256;
+    for (int a = 0; a < pb.dim; ++a) {
+        P.ax[a].tab_off = off;
+        off = align256(off + P.ax[a].tab_entries * sizeof(TabEntry));
+    }
+    P.off_part = off;
+    off = align256(off + (size_t)P.np_norm * sizeof(double));
+    P.off_obspart = off;
+    off = align256(off + (size_t)P.obs_grid * 12 * sizeof(double));
+    P.ws_bytes = off;
+    return SSCN_OK;
+}
+
+// FP64 Thomas tables of axis a in the layout its kernel reads.
+void build_table(const sscn_problem &pb, const Plan &P, int a, std::vector<TabEntry> &out)
+{
+    const AxisPlan &X = P.ax[a];
+    const int n = X.n;
+    const std::complex<double> s(X.sig_re, X.sig_im);
+    const std::complex<double> b = 1.0 + 2.0 * s;
+    std::vector<std::complex<double>> m(n), al(n);
+    m[0] = 1.0 / b;
+    for (int i = 1; i < n; ++i) m[i] = 1.0 / (b - s * s * m[i - 1]);
+    for (int i = 0; i < n; ++i) al[i] = s * m[i];
+    out.assign(X.tab_entries, TabEntry{0, 0, 0, 0});
+    auto put = [&](size_t slot, int i) {
+        out[slot] = TabEntry{al[i].real(), al[i].imag(), m[i].real(), m[i].imag()};
+    };
+    if (X.kind == K_ROW) {
+        const int G = 64 * X.wpl;
+        for (int t = 0; t < G; ++t)
+            for (int k = 0; k < X.C; ++k) {
+                const int i = t * X.C + k;
+                if (i < n) put((size_t)k * G + t, i);
+            }
+    } else {
+        for (int i = 0; i < n; ++i) put((size_t)i, i);
+    }
+    (void)pb;
+}
+
+struct HintEntry {
+    int32_t dim, n[3], mode, prec;
+    TileOverride ov;
+};
+static std::mutex g_hint_mu;
+static std::vector<HintEntry> g_hints;
+
+static bool hint_match(const HintEntry &h, const sscn_problem &pb)
+{
+    return h.dim == pb.dim && h.n[0] == pb.n[0] && h.n[1] == pb.n[1] && h.n[2] == pb.n[2] &&
+           h.mode == pb.mode && h.prec == pb.prec;
+}
+
+bool tile_hint_copy(const sscn_problem &pb, TileOverride &out)
+{
+    std::lock_guard<std::mutex> lk(g_hint_mu);
+    for (const HintEntry &h : g_hints)
+        if (hint_match(h, pb)) {
+            out = h.ov;
+            return true;
+        }
+    return false;
+}
+
+}  // namespace sscn
+
+struct sscn_solver {
+    sscn_problem pb;
+    Plan P;
+    void *psi;
+    char *ws;
+    hipStream_t st;
+    int64_t step;
+    double g;
+    double host_obs[16];
+};
+
+static double *scal_ptr(sscn_solver *s) { return reinterpret_cast<double *>(s->ws + s->P.off_scal); }
+
+static PointParams point_params(const sscn_solver *s)
+{
+    PointParams pp;
+    std::memset(&pp, 0, sizeof(pp));
+    pp.dt = s->pb.dt;
+    pp.g = s->g;
+    for (int a = 0; a < 3; ++a) {
+        pp.n[a] = s->pb.n[a];
+        pp.dx[a] = (a < s->pb.dim) ? s->pb.dx[a] : 0.0;
+        pp.cen[a] = 0.5 * (s->pb.n[a] - 1);
+        pp.w2h[a] = (a < s->pb.dim) ? 0.5 * s->pb.omega[a] * s->pb.omega[a] : 0.0;
+    }
+    return pp;
+}
+
+static ColArgs col_args(sscn_solver *s, int a, bool last)
+{
+    const AxisPlan &X = s->P.ax[a];
+    ColArgs c;
+    c.psi = s->psi;
+    c.tab = reinterpret_cast<const TabEntry *>(s->ws + X.tab_off);
+    c.n = X.n;
+    c.nlines = (int32_t)X.nlines;
+    c.stride = X.stride;
+    c.m1 = X.m1;
+    c.s1 = X.s1;
+    c.s2 = X.s2;
+    c.W = X.W;
+    c.sig_re = X.sig_re;
+    c.sig_im = X.sig_im;
+    c.partial = last ? reinterpret_cast<double *>(s->ws + s->P.off_part) : nullptr;
+    return c;
+}
+
+// Kernel classes for timing: 0 x (+pointwise), 1 y, 2 z, 3 norm final, 4 scale.
+struct Timer {
+    std::vector<hipEvent_t> ev;
+    std::vector<int> cls;
+    size_t used = 0;
+    hipStream_t st;
+    hipError_t mark(int c)
+    {
+        if (used >= ev.size()) return hipSuccess;
+        cls[used] = c;
+        return hipEventRecord(ev[used++], st);
+    }
+};
+
+static hipError_t enqueue_step(sscn_solver *s, bool do_renorm, Timer *tm)
+{
+    const Plan &P = s->P;
+    const sscn_problem &pb = s->pb;
+    const bool imag = pb.mode == SSCN_IMAG;
+    const int dim = pb.dim;
+    double *scal = scal_ptr(s);
+    double *part = reinterpret_cast<double *>(s->ws + P.off_part);
+    hipError_t e;
+#define CHK(x)                          \
+    do {                                \
+        if ((e = (x)) != hipSuccess) return e; \
+    } while (0)
+    if (tm) CHK(tm->mark(-1));
+    // x sweep with the pointwise substep
+    {
+        const AxisPlan &X = P.ax[0];
+        const bool last = imag && do_renorm && dim == 1 && X.kind == K_ROW;
+        if (X.kind == K_ROW) {
+            RowArgs r;
+            r.psi = s->psi;
+            r.tab = reinterpret_cast<const TabEntry *>(s->ws + X.tab_off);
+            r.n = X.n;
+            r.nlines = (int32_t)X.nlines;
+            r.wpl = X.wpl;
+            r.lpb = X.lpb;
+            r.sig_re = X.sig_re;
+            r.sig_im = X.sig_im;
+            r.pp = point_params(s);
+            r.scale = scal;
+            r.partial = last ? part : nullptr;
+            CHK(launch_row(P.elem, X.C, last, r, X.grid, X.block, X.lds, s->st));
+        } else {
+            PointArgs pa;
+            pa.psi = s->psi;
+            pa.npts = P.npts;
+            pa.pp = point_params(s);
+            pa.scale = scal;
+            CHK(launch_pointwise(P.elem, pa, P.pw_grid, 256, s->st));
+            CHK(launch_stream(P.elem, col_args(s, 0, false), X.grid, X.block, s->st));
+        }
+        if (tm) CHK(tm->mark(0));
+    }
+    for (int a = 1; a < dim; ++a) {
+        const AxisPlan &X = P.ax[a];
+        const bool last = imag && do_renorm && a == dim - 1 && X.kind == K_COL;
+        if (X.kind == K_COL)
+            CHK(launch_col(P.elem, X.C, last, col_args(s, a, last), X.grid, X.block, X.lds, s->st));
+        else
+            CHK(launch_stream(P.elem, col_args(s, a, false), X.grid, X.block, s->st));
+        if (tm) CHK(tm->mark(a));
+    }
+    if (imag) {
+        if (do_renorm && P.sep_norm)
+            CHK(launch_norm_partials(P.elem, s->psi, P.npts, part, P.pw_grid, 256, s->st));
+        double dv = 1.0;
+        for (int a = 0; a < dim; ++a) dv *= pb.dx[a];
+        CHK(launch_norm_final(part, P.np_norm, dv, do_renorm ? 1 : 0, scal, s->st));
+        if (tm) CHK(tm->mark(3));
+    }
+#undef CHK
+    return hipSuccess;
+}
+
+static hipError_t enqueue_steps(sscn_solver *s, int64_t nsteps, Timer *tm)
+{
+    if (nsteps <= 0) return hipSuccess;
+    const bool imag = s->pb.mode == SSCN_IMAG;
+    bool last_renorm = false;
+    for (int64_t t = 0; t < nsteps; ++t) {
+        const int64_t step = s->step + 1;
+        const bool do_renorm = imag && (step % s->pb.renorm_every == 0);
+        hipError_t e = enqueue_step(s, do_renorm, tm);
+        if (e != hipSuccess) return e;
+        s->step = step;
+        last_renorm = do_renorm;
+    }
+    if (imag && last_renorm) {
+        hipError_t e = launch_scale_state(s->P.elem, s->psi, s->P.npts, scal_ptr(s), s->P.pw_grid, 256, s->st);
+        if (e != hipSuccess) return e;
+        if ((e = launch_set_unit_scale(scal_ptr(s), s->st)) != hipSuccess) return e;
+        if (tm && (e = tm->mark(4)) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int sscn_abi_version(void) { return SSCN_ABI_VERSION; }
+
+const char *sscn_status_string(int status)
+{
+    switch (status) {
+    case SSCN_OK: return "ok";
+    case SSCN_NOT_CONVERGED: return "not converged (step cap reached)";
+    case SSCN_E_INVALID: return "invalid argument";
+    case SSCN_E_HIP: return "HIP runtime error";
+    case SSCN_E_NONFINITE: return "non-finite norm or chemical potential";
+    case SSCN_E_NOSPACE: return "no space (slot busy or buffer too small)";
+    case SSCN_E_UNSUPPORTED: return "unsupported problem size";
+    default: return "unknown status";
+    }
+}
+
+int sscn_validate(const sscn_problem *pb) { return validate(pb); }
+
+int sscn_set_tile_hint(const sscn_problem *pb, const int32_t chunk[3])
+{
+    int v = validate(pb);
+    if (v != SSCN_OK) return v;
+    if (!chunk) return SSCN_E_INVALID;
+    for (int a = 0; a < 3; ++a) {
+        const int c = chunk[a];
+        if (c < 0 || c > 64 || (c & (c - 1)) != 0) return SSCN_E_INVALID;
+    }
+    HintEntry h;
+    std::memset(&h, 0, sizeof(h));
+    h.dim = pb->dim;
+    for (int a = 0; a < 3; ++a) h.n[a] = pb->n[a];
+    h.mode = pb->mode;
+    h.prec = pb->prec;
+    h.ov.row_c = chunk[0];
+    h.ov.col_c[0] = 0;
+    h.ov.col_c[1] = chunk[1];
+    h.ov.col_c[2] = chunk[2];
+    Plan P;
+    v = make_plan(*pb, &h.ov, P);
+    if (v != SSCN_OK) return v;
+    for (int a = 0; a < pb->dim; ++a)
+        if (chunk[a] != 0 && P.ax[a].kind == K_STREAM) return SSCN_E_UNSUPPORTED;
+    try {
+        std::lock_guard<std::mutex> lk(g_hint_mu);
+        for (HintEntry &e : g_hints)
+            if (hint_match(e, *pb)) {
+                e = h;
+                return SSCN_OK;
+            }
+        g_hints.push_back(h);
+    } catch (...) {
+        return SSCN_E_INVALID;
+    }
+    return SSCN_OK;
+}
+
+int sscn_clear_tile_hints(void)
+{
+    std::lock_guard<std::mutex> lk(g_hint_mu);
+    g_hints.clear();
+    return SSCN_OK;
+}
+
+int sscn_plan_info(const sscn_problem *pb, int32_t *info, int32_t cap)
+{
+    int v = validate(pb);
+    if (v != SSCN_OK) return v;
+    if (!info || cap < 15) return SSCN_E_INVALID;
+    Plan P;
+    TileOverride ov;
+    v = make_plan(*pb, tile_hint_copy(*pb, ov) ? &ov : nullptr, P);
+    if (v != SSCN_OK) return v;
+    for (int a = 0; a < 3; ++a) {
+        const AxisPlan &X = P.ax[a];
+        const bool used = a < pb->dim;
+        info[5 * a + 0] = used ? X.kind : -1;
+        info[5 * a + 1] = used ? X.C : 0;
+        info[5 * a + 2] = used ? (X.kind == K_ROW ? X.wpl : X.W) : 0;
+        info[5 * a + 3] = used ? X.grid : 0;
+        info[5 * a + 4] = used ? X.block : 0;
+    }
+    return SSCN_OK;
+}
+
+int sscn_state_bytes(const sscn_problem *pb, size_t *bytes)
+{
+    int v = validate(pb);
+    if (v != SSCN_OK) return v;
+    if (!bytes) return SSCN_E_INVALID;
+    *bytes = (size_t)pb->n[0] * pb->n[1] * pb->n[2] * elem_bytes(elem_of(*pb));
+    return SSCN_OK;
+}
+
+int sscn_workspace_bytes(const sscn_problem *pb, size_t *bytes)
+{
+    int v = validate(pb);
+    if (v != SSCN_OK) return v;
+    if (!bytes) return SSCN_E_INVALID;
+    Plan P;
+    TileOverride ov;
+    v = make_plan(*pb, tile_hint_copy(*pb, ov) ? &ov : nullptr, P);
+    if (v != SSCN_OK) return v;
+    *bytes = P.ws_bytes;
+    return SSCN_OK;
+}
+
+int sscn_create(const sscn_problem *pb, void *d_psi, void *d_ws, void *hip_stream, sscn_solver **out)
+{
+    int v = validate(pb);
+    if (v != SSCN_OK) return v;
+    if (!d_psi || !d_ws || !out) return SSCN_E_INVALID;
+    if (reinterpret_cast<uintptr_t>(d_ws) % 256 != 0) return SSCN_E_INVALID;
+    if (reinterpret_cast<uintptr_t>(d_psi) % 16 != 0) return SSCN_E_INVALID;
+    sscn_solver *s = new (std::nothrow) sscn_solver;
+    if (!s) return SSCN_E_INVALID;
+    std::memset(s, 0, sizeof(*s));
+    s->pb = *pb;
+    s->psi = d_psi;
+    s->ws = static_cast<char *>(d_ws);
+    s->st = static_cast<hipStream_t>(hip_stream);
+    s->g = pb->g;
+    TileOverride ov;
+    v = make_plan(*pb, tile_hint_copy(*pb, ov) ? &ov : nullptr, s->P);
+    if (v != SSCN_OK) {
+        delete s;
+        return v;
+    }
+    // host image of the workspace head and tables, uploaded in one pass
+    try {
+        std::vector<char> img(s->P.off_part, 0);
+        double *scal = reinterpret_cast<double *>(img.data() + s->P.off_scal);
+        scal[0] = 1.0;
+        scal[1] = 1.0;
+        std::vector<TabEntry> tab;
+        for (int a = 0; a < pb->dim; ++a) {
+            build_table(*pb, s->P, a, tab);
+            std::memcpy(img.data() + s->P.ax[a].tab_off, tab.data(), tab.size() * sizeof(TabEntry));
+        }
+        if (hipMemcpyAsync(s->ws, img.data(), img.size(), hipMemcpyHostToDevice, s->st) != hipSuccess ||
+            hipStreamSynchronize(s->st) != hipSuccess) {
+            delete s;
+            return SSCN_E_HIP;
+        }
+    } catch (...) {
+        delete s;
+        return SSCN_E_INVALID;
+    }
+    *out = s;
+    return SSCN_OK;
+}
+
+int sscn_step(sscn_solver *s, int64_t nsteps)
+{
+    if (!s || nsteps < 0) return SSCN_E_INVALID;
+    return enqueue_steps(s, nsteps, nullptr) == hipSuccess ? SSCN_OK : SSCN_E_HIP;
+}
+
+int sscn_step_timed(sscn_solver *s, int64_t nsteps, double *ms)
+{
+    if (!s || nsteps < 0 || !ms) return SSCN_E_INVALID;
+    Timer tm;
+    tm.st = s->st;
+    const size_t need = (size_t)nsteps * 6 + 4;
+    try {
+        tm.ev.resize(need);
+        tm.cls.resize(need, -1);
+    } catch (...) {
+        return SSCN_E_INVALID;
+    }
+    size_t made = 0;
+    for (; made < need; ++made)
+        if (hipEventCreate(&tm.ev[made]) != hipSuccess) break;
+    int rc = SSCN_OK;
+    if (made < need) rc = SSCN_E_HIP;
+    if (rc == SSCN_OK && enqueue_steps(s, nsteps, &tm) != hipSuccess) rc = SSCN_E_HIP;
+    if (rc == SSCN_OK && hipStreamSynchronize(s->st) != hipSuccess) rc = SSCN_E_HIP;
+    double tot[SSCN_NKERNELS] = {0};
+    int cnt[SSCN_NKERNELS] = {0};
+    if (rc == SSCN_OK) {
+        for (size_t i = 1; i < tm.used; ++i) {
+            const int c = tm.cls[i];
+            if (c < 0 || c >= SSCN_NKERNELS) continue;
+            float f = 0.f;
+            if (hipEventElapsedTime(&f, tm.ev[i - 1], tm.ev[i]) != hipSuccess) {
+                rc = SSCN_E_HIP;
+                break;
+            }
+            tot[c] += f;
+            cnt[c] += 1;
+        }
+    }
+    for (int c = 0; c < SSCN_NKERNELS; ++c) ms[c] = cnt[c] ? tot[c] / cnt[c] : 0.0;
+    for (size_t i = 0; i < made; ++i) (void)hipEventDestroy(tm.ev[i]);
+    return rc;
+}
+
+int sscn_observe(sscn_solver *s, sscn_obs *out)
+{
+    if (!s || !out) return SSCN_E_INVALID;
+    const Plan &P = s->P;
+    ObsArgs oa;
+    std::memset(&oa, 0, sizeof(oa));
+    oa.psi = s->psi;
+    oa.dim = s->pb.dim;
+    double dv = 1.0;
+    for (int a = 0; a < 3; ++a) {
+        oa.n[a] = s->pb.n[a];
+        oa.dx[a] = (a < s->pb.dim) ? s->pb.dx[a] : 0.0;
+        oa.cen[a] = 0.5 * (s->pb.n[a] - 1);
+        oa.w2h[a] = (a < s->pb.dim) ? 0.5 * s->pb.omega[a] * s->pb.omega[a] : 0.0;
+        if (a < s->pb.dim) dv *= s->pb.dx[a];
+    }
+    oa.npts = P.npts;
+    oa.partial = reinterpret_cast<double *>(s->ws + P.off_obspart);
+    double *dobs = reinterpret_cast<double *>(s->ws + P.off_obs);
+    if (launch_obs_partials(P.elem, oa, P.obs_grid, 256, s->st) != hipSuccess) return SSCN_E_HIP;
+    if (launch_obs_final(oa.partial, P.obs_grid, dv, s->g, dobs, s->st) != hipSuccess) return SSCN_E_HIP;
+    if (hipMemcpyAsync(s->host_obs, dobs, 13 * sizeof(double), hipMemcpyDeviceToHost, s->st) != hipSuccess)
+        return SSCN_E_HIP;
+    if (hipStreamSynchronize(s->st) != hipSuccess) return SSCN_E_HIP;
+    const double *h = s->host_obs;
+    out->step = s->step;
+    out->norm = h[0];
+    out->mu = h[1];
+    out->energy = h[2];
+    out->ekin = h[3];
+    out->epot = h[4];
+    out->eint = h[5];
+    for (int a = 0; a < 3; ++a) {
+        out->mean[a] = h[6 + a];
+        out->msq[a] = h[9 + a];
+    }
+    out->status = (h[12] != 0.0) ? SSCN_OK : SSCN_E_NONFINITE;
+    out->pad_ = 0;
+    return out->status;
+}
+
+int sscn_run(sscn_solver *s, int64_t max_steps, double mu_tol, sscn_obs *trace, int64_t trace_cap,
+             int64_t *rows)
+{
+    if (!s || max_steps < 0 || !(mu_tol >= 0.0) || s->pb.observe_every < 1) return SSCN_E_INVALID;
+    if (trace_cap < 0 || (trace_cap > 0 && !trace)) return SSCN_E_INVALID;
+    const int64_t every = s->pb.observe_every;
+    int64_t nrow = 0, done = 0;
+    bool have_prev = false;
+    double prev = 0.0;
+    int rc = SSCN_NOT_CONVERGED;
+    while (done < max_steps) {
+        // advance to the next observation step (global step multiple of `every`)
+        int64_t k = every - (s->step % every);
+        if (k > max_steps - done) k = max_steps - done;
+        if (sscn_step(s, k) != SSCN_OK) return SSCN_E_HIP;
+        done += k;
+        sscn_obs o;
+        int r = sscn_observe(s, &o);
+        if (r == SSCN_E_HIP) return r;
+        if (trace && nrow < trace_cap) trace[nrow] = o;
+        ++nrow;
+        if (r == SSCN_E_NONFINITE) {
+            rc = r;
+            break;
+        }
+        if (s->step % every != 0) break;  // cap reached between observations
+        if (have_prev && std::fabs(o.mu - prev) < mu_tol) {
+            rc = SSCN_OK;
+            break;
+        }
+        prev = o.mu;
+        have_prev = true;
+    }
+    if (rows) *rows = std::min(nrow, trace_cap);
+    return rc;
+}
+
+int sscn_set_g(sscn_solver *s, double g)
+{
+    if (!s || !std::isfinite(g)) return SSCN_E_INVALID;
+    s->g = g;
+    return SSCN_OK;
+}
+
+int sscn_destroy(sscn_solver *s)
+{
+    if (!s) return SSCN_E_INVALID;
+    (void)hipStreamSynchronize(s->st);
+    delete s;
+    return SSCN_OK;
+}
+
+int sscn_density_1d(sscn_solver *s, int keep, void *d_out)
+{
+    if (!s || !d_out || keep < 0 || keep >= s->pb.dim) return SSCN_E_INVALID;
+    double w = 1.0;
+    for (int a = 0; a < s->pb.dim; ++a)
+        if (a != keep) w *= s->pb.dx[a];
+    return launch_density_1d(s->P.elem, s->psi, s->pb.n, keep, w, static_cast<double *>(d_out), s->st) ==
+                   hipSuccess
+               ? SSCN_OK
+               : SSCN_E_HIP;
+}
+
+int sscn_density_2d(sscn_solver *s, int drop, void *d_out)
+{
+    if (!s || !d_out || s->pb.dim != 3 || drop < 0 || drop > 2) return SSCN_E_INVALID;
+    return launch_density_2d(s->P.elem, s->psi, s->pb.n, drop, s->pb.dx[drop], static_cast<double *>(d_out),
+                             s->st) == hipSuccess
+               ? SSCN_OK
+               : SSCN_E_HIP;
+}
+
+}  // extern "C"

@@ -1,0 +1,157 @@
+// sscn_dev.hpp -- device-side building blocks of the gfx950 SSCN propagator.
+//
+// One SSCN step (the paper's split-step Crank-Nicolson scheme, see sscn.h for
+// the equations) is, per axis, a family of independent constant-coefficient
+// tridiagonal systems
+//     -s v_{i-1} + (1 + 2s) v_i - s v_{i+1} = r_i,   r = (1 - sT) u,
+// one per grid line.  Thomas elimination with the FP64 tables computed on the
+// host,
+//     m_0 = 1/(1+2s),  m_i = 1/(1 + 2s - s^2 m_{i-1}),  alpha_i = s m_i,
+// turns each line into two first-order linear recurrences that share alpha:
+//     forward   d_i = alpha_i d_{i-1} + m_i r_i         (d_{-1} = 0)
+//     backward  v_i = alpha_i v_{i+1} + d_i             (v_n = 0)
+// A line is split into contiguous chunks held in registers by a group of
+// threads.  Each thread composes its chunk into an affine map x -> A x + B
+// (A = product of alpha over the chunk), an exclusive scan of those maps
+// across the group gives every chunk its exact incoming value, and the chunk
+// recurrences are re-run with it.  Nothing is truncated: the result is the
+// Thomas solution up to the order of rounding.
+//
+// Two geometries use the same chunk algebra:
+//   ROW  (x lines, stride 1): the G = 64*WPL threads of a line group hold
+//        consecutive chunks of one line; the scan runs over lanes with
+//        cross-lane shuffles and, for WPL > 1, across waves through LDS.
+//   COL  (y and z lines): the 64 lanes of a wave hold 64 different lines
+//        (adjacent line indices, so every load and store of a wave is
+//        contiguous); the W waves of a block hold consecutive chunks; the
+//        scan runs across waves through LDS and the table entries are
+//        wave-uniform.
+// Padding beyond the line end uses zero tables and zero data, which makes
+// every padded value exactly zero and leaves the real points untouched.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sscn {
+
+__device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+// ---------------------------------------------------------------------------
+// value algebra: real (imaginary time) or complex (real time)
+// ---------------------------------------------------------------------------
+template <class T>
+struct alignas(2 * sizeof(T)) cpx {
+    T re, im;
+};
+
+template <class T, bool CPLX>
+struct Alg;
+
+template <class T>
+struct Alg<T, false> {
+    using V = T;
+    __device__ __forceinline__ static V zero() { return T(0); }
+    __device__ __forceinline__ static V one() { return T(1); }
+    __device__ __forceinline__ static V mul(V a, V b) { return a * b; }
+    __device__ __forceinline__ static V fma(V a, V b, V c) { return fmaT(a, b, c); }
+    __device__ __forceinline__ static V add(V a, V b) { return a + b; }
+    __device__ __forceinline__ static V sub(V a, V b) { return a - b; }
+    __device__ __forceinline__ static V scal(T s, V a) { return s * a; }
+    __device__ __forceinline__ static double norm2(V a) { return double(a) * double(a); }
+    __device__ __forceinline__ static T norm2t(V a) { return a * a; }
+    // coefficient from an FP64 (re, im) table entry
+    __device__ __forceinline__ static V coef(double re, double) { return T(re); }
+    __device__ __forceinline__ static V shfl_up(V a, int d) { return __shfl_up(a, d, 64); }
+    __device__ __forceinline__ static V shfl_down(V a, int d) { return __shfl_down(a, d, 64); }
+    __device__ __forceinline__ static bool finite(V a) { return __builtin_isfinite(a); }
+};
+
+template <class T>
+struct Alg<T, true> {
+    using V = cpx<T>;
+    __device__ __forceinline__ static V zero() { return V{T(0), T(0)}; }
+    __device__ __forceinline__ static V one() { return V{T(1), T(0)}; }
+    __device__ __forceinline__ static V mul(V a, V b) {
+        return V{fmaT(a.re, b.re, -a.im * b.im), fmaT(a.re, b.im, a.im * b.re)};
+    }
+    __device__ __forceinline__ static V fma(V a, V b, V c) {
+        return V{fmaT(a.re, b.re, fmaT(-a.im, b.im, c.re)),
+                 fmaT(a.re, b.im, fmaT(a.im, b.re, c.im))};
+    }
+    __device__ __forceinline__ static V add(V a, V b) { return V{a.re + b.re, a.im + b.im}; }
+    __device__ __forceinline__ static V sub(V a, V b) { return V{a.re - b.re, a.im - b.im}; }
+    __device__ __forceinline__ static V scal(T s, V a) { return V{s * a.re, s * a.im}; }
+    __device__ __forceinline__ static double norm2(V a) {
+        return double(a.re) * double(a.re) + double(a.im) * double(a.im);
+    }
+    __device__ __forceinline__ static T norm2t(V a) { return a.re * a.re + a.im * a.im; }
+    __device__ __forceinline__ static V coef(double re, double im) { return V{T(re), T(im)}; }
+    __device__ __forceinline__ static V shfl_up(V a, int d) {
+        return V{__shfl_up(a.re, d, 64), __shfl_up(a.im, d, 64)};
+    }
+    __device__ __forceinline__ static V shfl_down(V a, int d) {
+        return V{__shfl_down(a.re, d, 64), __shfl_down(a.im, d, 64)};
+    }
+    __device__ __forceinline__ static bool finite(V a) {
+        return __builtin_isfinite(a.re) && __builtin_isfinite(a.im);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// tables and parameters
+// ---------------------------------------------------------------------------
+
+// One Thomas table entry (FP64 always): alpha_i = s m_i and m_i, as (re, im).
+struct TabEntry {
+    double ar, ai, mr, mi;
+};
+
+// Pointwise-substep parameters for the x sweep (the first sweep of a step).
+struct PointParams {
+    double dt, g;
+    double dx[3];
+    double cen[3];   // (n_a - 1) / 2
+    double w2h[3];   // omega_a^2 / 2 (0 on unused axes)
+    int32_t n[3];
+};
+
+// r = (1 - sT) u at one point given its two neighbours (zero past the ends).
+template <class T, bool CPLX>
+__device__ __forceinline__ typename Alg<T, CPLX>::V
+cn_rhs(typename Alg<T, CPLX>::V um, typename Alg<T, CPLX>::V u0, typename Alg<T, CPLX>::V up,
+       typename Alg<T, CPLX>::V sig)
+{
+    using A = Alg<T, CPLX>;
+    // u + s (u_{i-1} + u_{i+1} - 2 u_i)
+    typename A::V lap = A::sub(A::add(um, up), A::add(u0, u0));
+    return A::fma(sig, lap, u0);
+}
+
+// ---------------------------------------------------------------------------
+// block reductions (FP64, fixed order)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    return v;  // lane 0 holds the sum
+}
+
+// Sum of v over the block, returned to thread 0; red needs blockDim/64 doubles.
+__device__ __forceinline__ double block_sum(double v, double *red)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    v = wave_sum(v);
+    __syncthreads();
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int w = 0; w < nw; ++w) s += red[w];
+    }
+    return s;
+}
+
+}  // namespace sscn

@@ -1,0 +1,765 @@
+// sscn_kernels.hip -- gfx950 kernels of one SSCN step and its reductions.
+//
+// Per step (the paper's split-step Crank-Nicolson propagation; equations in
+// sscn.h):
+//   k_row   x lines: pending renormalisation scale + pointwise potential and
+//           nonlinear substep fused into the load, then the CN x solve
+//           (ROW geometry, see sscn_dev.hpp).  One read and one write of psi.
+//   k_col   y and z lines (COL geometry); the last sweep of the step also
+//           emits one FP64 partial of sum |psi|^2 per block.
+//   k_norm_final  fixed-order sum of those partials -> renormalisation
+//           factor kept on the device and applied by the next k_row load.
+// Fallbacks for lines too long to keep in registers: k_pointwise (separate
+// pointwise substep), k_stream (one thread per line, exact Thomas with the
+// forward intermediates stored in place) and k_norm_partials.
+#include "sscn_launch.hpp"
+
+namespace sscn {
+
+template <class T>
+__device__ __forceinline__ T dev_exp(T x)
+{
+    if constexpr (sizeof(T) == 8) return exp(x); else return expf(x);
+}
+
+template <class T>
+__device__ __forceinline__ void dev_sincos(T x, T *s, T *c)
+{
+    if constexpr (sizeof(T) == 8) sincos(x, s, c); else sincosf(x, s, c);
+}
+
+// Pointwise substep on one value (imaginary time: scale first; real time: phase).
+template <class T, bool CPLX>
+__device__ __forceinline__ typename Alg<T, CPLX>::V
+apply_point(typename Alg<T, CPLX>::V u, T scale, T vpot, T dt, T g)
+{
+    using A = Alg<T, CPLX>;
+    if constexpr (!CPLX) {
+        u = A::scal(scale, u);
+        T phi = dt * fmaT(g, A::norm2t(u), vpot);
+        return dev_exp<T>(-phi) * u;
+    } else {
+        (void)scale;
+        T phi = dt * fmaT(g, A::norm2t(u), vpot);
+        T sn, cs;
+        dev_sincos<T>(phi, &sn, &cs);
+        return typename A::V{fmaT(cs, u.re, sn * u.im), fmaT(cs, u.im, -sn * u.re)};
+    }
+}
+
+template <class T>
+__device__ __forceinline__ T coord(int i, double cen, double dx)
+{
+    return T((double(i) - cen) * dx);
+}
+
+// ===========================================================================
+// ROW: x lines, G = 64 * wpl threads per line, C points per thread
+// ===========================================================================
+template <class T, bool CPLX, int C, bool LAST>
+__global__ void __launch_bounds__(1024) k_row(RowArgs a)
+{
+    using A = Alg<T, CPLX>;
+    using V = typename A::V;
+    extern __shared__ unsigned char lds_raw[];
+    __shared__ double red[16];
+
+    const int G = 64 * a.wpl;
+    const int tid = threadIdx.x;
+    const int lb = tid / G;
+    const int t = tid - lb * G;
+    const int lane = tid & 63;
+    const int wl = t >> 6;
+    V *xs = reinterpret_cast<V *>(lds_raw) + lb * a.wpl * 4;
+
+    const V sig = A::coef(a.sig_re, a.sig_im);
+    const T scale = CPLX ? T(1) : T(*a.scale);
+    const T dt = T(a.pp.dt), g = T(a.pp.g);
+    V *psi = reinterpret_cast<V *>(a.psi);
+    const int n = a.n;
+    const int i0 = t * C;
+    double nacc = 0.0;
+
+    for (long long gb = (long long)blockIdx.x * a.lpb; gb < a.nlines;
+         gb += (long long)gridDim.x * a.lpb) {
+        const long long line = gb + lb;
+        const bool active = line < a.nlines;
+        const long long base = line * (long long)n;
+
+        // ---- load + pointwise substep ----
+        T vyz = T(0);
+        if (active) {
+            const int j = (int)(line % a.pp.n[1]);
+            const int k = (int)(line / a.pp.n[1]);
+            const T y = coord<T>(j, a.pp.cen[1], a.pp.dx[1]);
+            const T z = coord<T>(k, a.pp.cen[2], a.pp.dx[2]);
+            vyz = T(a.pp.w2h[1]) * y * y + T(a.pp.w2h[2]) * z * z;
+        }
+        V u[C];
+#pragma unroll
+        for (int k = 0; k < C; ++k) {
+            const int i = i0 + k;
+            V v = A::zero();
+            if (active && i < n) {
+                v = psi[base + i];
+                const T x = coord<T>(i, a.pp.cen[0], a.pp.dx[0]);
+                v = apply_point<T, CPLX>(v, scale, T(a.pp.w2h[0]) * x * x + vyz, dt, g);
+            }
+            u[k] = v;
+        }
+
+        // ---- neighbours across chunk boundaries ----
+        V left = A::shfl_up(u[C - 1], 1);
+        V right = A::shfl_down(u[0], 1);
+        if (lane == 0) left = A::zero();
+        if (lane == 63) right = A::zero();
+        if (a.wpl > 1) {
+            if (lane == 0) xs[wl * 4 + 0] = u[0];
+            if (lane == 63) xs[wl * 4 + 1] = u[C - 1];
+            __syncthreads();
+            if (lane == 0 && wl > 0) left = xs[(wl - 1) * 4 + 1];
+            if (lane == 63 && wl < a.wpl - 1) right = xs[(wl + 1) * 4 + 0];
+            __syncthreads();
+        }
+
+        // ---- right-hand side, tables ----
+        V al[C], be[C];
+        {
+            V prev = left;
+#pragma unroll
+            for (int k = 0; k < C; ++k) {
+                const V nxt = (k + 1 < C) ? u[k + 1] : right;
+                const V r = cn_rhs<T, CPLX>(prev, u[k], nxt, sig);
+                prev = u[k];
+                const TabEntry e = a.tab[(size_t)k * G + t];
+                al[k] = A::coef(e.ar, e.ai);
+                be[k] = A::mul(A::coef(e.mr, e.mi), r);
+            }
+        }
+
+        // ---- forward recurrence: local map, scan, exact pass ----
+        V Ac = A::one(), d = A::zero();
+#pragma unroll
+        for (int k = 0; k < C; ++k) {
+            d = A::fma(al[k], d, be[k]);
+            Ac = A::mul(al[k], Ac);
+        }
+        V din;
+        {
+            V PA = Ac, PB = d;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const V a2 = A::shfl_up(PA, o), b2 = A::shfl_up(PB, o);
+                if (lane >= o) {
+                    PB = A::fma(PA, b2, PB);
+                    PA = A::mul(PA, a2);
+                }
+            }
+            V EA = A::shfl_up(PA, 1), EB = A::shfl_up(PB, 1);
+            if (lane == 0) {
+                EA = A::one();
+                EB = A::zero();
+            }
+            if (a.wpl > 1) {
+                if (lane == 63) {
+                    xs[wl * 4 + 2] = PA;
+                    xs[wl * 4 + 3] = PB;
+                }
+                __syncthreads();
+                V Dw = A::zero();
+                for (int q = 0; q < wl; ++q) Dw = A::fma(xs[q * 4 + 2], Dw, xs[q * 4 + 3]);
+                __syncthreads();
+                din = A::fma(EA, Dw, EB);
+            } else {
+                din = EB;
+            }
+        }
+        d = din;
+#pragma unroll
+        for (int k = 0; k < C; ++k) {
+            d = A::fma(al[k], d, be[k]);
+            be[k] = d;
+        }
+
+        // ---- backward recurrence ----
+        V v = A::zero();
+#pragma unroll
+        for (int k = C - 1; k >= 0; --k) v = A::fma(al[k], v, be[k]);
+        V vin;
+        {
+            V PA = Ac, PB = v;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const V a2 = A::shfl_down(PA, o), b2 = A::shfl_down(PB, o);
+                if (lane + o < 64) {
+                    PB = A::fma(PA, b2, PB);
+                    PA = A::mul(PA, a2);
+                }
+            }
+            V EA = A::shfl_down(PA, 1), EB = A::shfl_down(PB, 1);
+            if (lane == 63) {
+                EA = A::one();
+                EB = A::zero();
+            }
+            if (a.wpl > 1) {
+                if (lane == 0) {
+                    xs[wl * 4 + 2] = PA;
+                    xs[wl * 4 + 3] = PB;
+                }
+                __syncthreads();
+                V Vw = A::zero();
+                for (int q = a.wpl - 1; q > wl; --q) Vw = A::fma(xs[q * 4 + 2], Vw, xs[q * 4 + 3]);
+                __syncthreads();
+                vin = A::fma(EA, Vw, EB);
+            } else {
+                vin = EB;
+            }
+        }
+        v = vin;
+#pragma unroll
+        for (int k = C - 1; k >= 0; --k) {
+            v = A::fma(al[k], v, be[k]);
+            be[k] = v;
+        }
+
+        // ---- store ----
+#pragma unroll
+        for (int k = 0; k < C; ++k) {
+            const int i = i0 + k;
+            if (active && i < n) {
+                psi[base + i] = be[k];
+                if constexpr (LAST) nacc += A::norm2(be[k]);
+            }
+        }
+    }
+    if constexpr (LAST) {
+        const double s = block_sum(nacc, red);
+        if (threadIdx.x == 0) a.partial[blockIdx.x] = s;
+    }
+}
+
+// ===========================================================================
+// COL: 64 lines per block (lanes), W chunks of C points per line (waves)
+// ===========================================================================
+template <class T, bool CPLX, int C, bool LAST>
+__global__ void __launch_bounds__(1024) k_col(ColArgs a)
+{
+    using A = Alg<T, CPLX>;
+    using V = typename A::V;
+    extern __shared__ unsigned char lds_raw[];
+    __shared__ double red[16];
+    V *xs0 = reinterpret_cast<V *>(lds_raw);
+    V *xs1 = xs0 + a.W * 64;
+
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const long long line = (long long)blockIdx.x * 64 + lane;
+    const bool active = line < a.nlines;
+    long long base = 0;
+    if (active) base = (line % a.m1) * a.s1 + (line / a.m1) * a.s2;
+    V *psi = reinterpret_cast<V *>(a.psi);
+    const V sig = A::coef(a.sig_re, a.sig_im);
+    const int n = a.n;
+    const int i0 = w * C;
+    const long long st = a.stride;
+
+    V u[C];
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+        const int i = i0 + k;
+        u[k] = (active && i < n) ? psi[base + (long long)i * st] : A::zero();
+    }
+
+    // neighbours from the adjacent chunks (waves)
+    xs0[w * 64 + lane] = u[0];
+    xs1[w * 64 + lane] = u[C - 1];
+    __syncthreads();
+    const V left = (w > 0) ? xs1[(w - 1) * 64 + lane] : A::zero();
+    const V right = (w + 1 < a.W) ? xs0[(w + 1) * 64 + lane] : A::zero();
+    __syncthreads();
+
+    V be[C];
+    {
+        V prev = left;
+#pragma unroll
+        for (int k = 0; k < C; ++k) {
+            const V nxt = (k + 1 < C) ? u[k + 1] : right;
+            const V r = cn_rhs<T, CPLX>(prev, u[k], nxt, sig);
+            prev = u[k];
+            const TabEntry e = a.tab[i0 + k];
+            be[k] = A::mul(A::coef(e.mr, e.mi), r);
+        }
+    }
+
+    // forward
+    V Ac = A::one(), d = A::zero();
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+        const TabEntry e = a.tab[i0 + k];
+        const V al = A::coef(e.ar, e.ai);
+        d = A::fma(al, d, be[k]);
+        Ac = A::mul(al, Ac);
+    }
+    xs0[w * 64 + lane] = Ac;
+    xs1[w * 64 + lane] = d;
+    __syncthreads();
+    V din = A::zero();
+    for (int q = 0; q < w; ++q) din = A::fma(xs0[q * 64 + lane], din, xs1[q * 64 + lane]);
+    __syncthreads();
+    d = din;
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+        const TabEntry e = a.tab[i0 + k];
+        d = A::fma(A::coef(e.ar, e.ai), d, be[k]);
+        be[k] = d;
+    }
+
+    // backward
+    V v = A::zero();
+#pragma unroll
+    for (int k = C - 1; k >= 0; --k) {
+        const TabEntry e = a.tab[i0 + k];
+        v = A::fma(A::coef(e.ar, e.ai), v, be[k]);
+    }
+    xs1[w * 64 + lane] = v;
+    __syncthreads();
+    V vin = A::zero();
+    for (int q = a.W - 1; q > w; --q) vin = A::fma(xs0[q * 64 + lane], vin, xs1[q * 64 + lane]);
+    v = vin;
+    double nacc = 0.0;
+#pragma unroll
+    for (int k = C - 1; k >= 0; --k) {
+        const TabEntry e = a.tab[i0 + k];
+        v = A::fma(A::coef(e.ar, e.ai), v, be[k]);
+        const int i = i0 + k;
+        if (active && i < n) {
+            psi[base + (long long)i * st] = v;
+            if constexpr (LAST) nacc += A::norm2(v);
+        }
+    }
+    if constexpr (LAST) {
+        const double s = block_sum(nacc, red);
+        if (threadIdx.x == 0) a.partial[blockIdx.x] = s;
+    }
+}
+
+// ===========================================================================
+// Fallbacks
+// ===========================================================================
+template <class T, bool CPLX>
+__global__ void __launch_bounds__(256) k_stream(ColArgs a)
+{
+    using A = Alg<T, CPLX>;
+    using V = typename A::V;
+    const long long line = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (line >= a.nlines) return;
+    const long long base = (line % a.m1) * a.s1 + (line / a.m1) * a.s2;
+    V *p = reinterpret_cast<V *>(a.psi) + base;
+    const long long st = a.stride;
+    const int n = a.n;
+    const V sig = A::coef(a.sig_re, a.sig_im);
+    // forward: d_i stored in place of psi_i; the original u_{i-1}, u_i kept
+    V um = A::zero(), u0 = p[0];
+    V d = A::zero();
+    for (int i = 0; i < n; ++i) {
+        const V up = (i + 1 < n) ? p[(long long)(i + 1) * st] : A::zero();
+        const V r = cn_rhs<T, CPLX>(um, u0, up, sig);
+        const TabEntry e = a.tab[i];
+        d = A::fma(A::coef(e.ar, e.ai), d, A::mul(A::coef(e.mr, e.mi), r));
+        p[(long long)i * st] = d;
+        um = u0;
+        u0 = up;
+    }
+    V v = A::zero();
+    for (int i = n - 1; i >= 0; --i) {
+        const TabEntry e = a.tab[i];
+        v = A::fma(A::coef(e.ar, e.ai), v, p[(long long)i * st]);
+        p[(long long)i * st] = v;
+    }
+}
+
+template <class T, bool CPLX>
+__global__ void __launch_bounds__(256) k_pointwise(PointArgs a)
+{
+    using A = Alg<T, CPLX>;
+    using V = typename A::V;
+    V *psi = reinterpret_cast<V *>(a.psi);
+    const T scale = CPLX ? T(1) : T(*a.scale);
+    const T dt = T(a.pp.dt), g = T(a.pp.g);
+    const long long nx = a.pp.n[0], ny = a.pp.n[1];
+    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < a.npts;
+         p += (long long)gridDim.x * blockDim.x) {
+        const int i = (int)(p % nx);
+        const int j = (int)((p / nx) % ny);
+        const int k = (int)(p / (nx * ny));
+        const T x = coord<T>(i, a.pp.cen[0], a.pp.dx[0]);
+        const T y = coord<T>(j, a.pp.cen[1], a.pp.dx[1]);
+        const T z = coord<T>(k, a.pp.cen[2], a.pp.dx[2]);
+        const T vp = T(a.pp.w2h[0]) * x * x + (T(a.pp.w2h[1]) * y * y + T(a.pp.w2h[2]) * z * z);
+        psi[p] = apply_point<T, CPLX>(psi[p], scale, vp, dt, g);
+    }
+}
+
+template <class T, bool CPLX>
+__global__ void __launch_bounds__(256) k_norm_partials(const void *psi_, long long npts, double *partial)
+{
+    using A = Alg<T, CPLX>;
+    using V = typename A::V;
+    __shared__ double red[16];
+    const V *psi = reinterpret_cast<const V *>(psi_);
+    double acc = 0.0;
+    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < npts;
+         p += (long long)gridDim.x * blockDim.x)
+        acc += A::norm2(psi[p]);
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// scalars[0] = pending scale, scalars[1] = last norm
+__global__ void __launch_bounds__(1024) k_norm_final(const double *partial, int np, double dvol,
+                                                     int do_renorm, double *scalars)
+{
+    __shared__ double red[16];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < np; i += blockDim.x) acc += partial[i];
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) {
+        if (do_renorm) {
+            const double N = dvol * s;
+            scalars[1] = N;
+            scalars[0] = 1.0 / sqrt(N);
+        } else {
+            scalars[0] = 1.0;
+        }
+    }
+}
+
+template <class T, bool CPLX>
+__global__ void __launch_bounds__(256) k_scale_state(void *psi_, long long npts, const double *scalars)
+{
+    using A = Alg<T, CPLX>;
+    using V = typename A::V;
+    V *psi = reinterpret_cast<V *>(psi_);
+    const T s = T(scalars[0]);
+    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < npts;
+         p += (long long)gridDim.x * blockDim.x)
+        psi[p] = A::scal(s, psi[p]);
+}
+
+__global__ void k_set_unit_scale(double *scalars)
+{
+    if (threadIdx.x == 0) scalars[0] = 1.0;
+}
+
+// ===========================================================================
+// Observables
+// ===========================================================================
+#define SSCN_NOBS 12
+
+template <class T, bool CPLX>
+__global__ void __launch_bounds__(256) k_obs_partials(ObsArgs a)
+{
+    using A = Alg<T, CPLX>;
+    using V = typename A::V;
+    __shared__ double red[SSCN_NOBS][4];
+    const V *psi = reinterpret_cast<const V *>(a.psi);
+    const long long nx = a.n[0], ny = a.n[1], nz = a.n[2];
+    const long long sx[3] = {1, nx, nx * ny};
+    double acc[SSCN_NOBS];
+#pragma unroll
+    for (int q = 0; q < SSCN_NOBS; ++q) acc[q] = 0.0;
+    // acc: 0 sum q, 1 sum kinetic edges, 2 sum V q, 3 sum q^2, 4..6 x_a q, 7..9 x_a^2 q
+    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < a.npts;
+         p += (long long)gridDim.x * blockDim.x) {
+        const int idx[3] = {(int)(p % nx), (int)((p / nx) % ny), (int)(p / (nx * ny))};
+        (void)nz;
+        const V v = psi[p];
+        const double q = A::norm2(v);
+        double vp = 0.0, kin = 0.0;
+        for (int ax = 0; ax < 3; ++ax) {
+            if (ax >= a.dim) break;
+            const double x = (double(idx[ax]) - a.cen[ax]) * a.dx[ax];
+            vp += a.w2h[ax] * x * x;
+            acc[4 + ax] += x * q;
+            acc[7 + ax] += x * x * q;
+            const V nb = (idx[ax] + 1 < a.n[ax]) ? psi[p + sx[ax]] : A::zero();
+            double e = A::norm2(A::sub(nb, v));
+            if (idx[ax] == 0) e += q;
+            kin += e / (a.dx[ax] * a.dx[ax]);
+        }
+        acc[0] += q;
+        acc[1] += kin;
+        acc[2] += vp * q;
+        acc[3] += q * q;
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < SSCN_NOBS - 2; ++q) {
+        const double s = wave_sum(acc[q]);
+        if (lane == 0) red[q][wid] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < SSCN_NOBS - 2) {
+        const int q = threadIdx.x;
+        double s = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[q][w];
+        a.partial[(size_t)blockIdx.x * SSCN_NOBS + q] = s;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_obs_final(const double *partial, int np, double dvol,
+                                                   double g, double *out)
+{
+    __shared__ double red[16];
+    double tot[SSCN_NOBS - 2];
+    for (int q = 0; q < SSCN_NOBS - 2; ++q) {
+        double acc = 0.0;
+        for (int i = threadIdx.x; i < np; i += blockDim.x) acc += partial[(size_t)i * SSCN_NOBS + q];
+        tot[q] = block_sum(acc, red);
+    }
+    if (threadIdx.x == 0) {
+        const double N = dvol * tot[0];
+        const double K = 0.5 * dvol * tot[1];
+        const double P = dvol * tot[2];
+        const double I = dvol * tot[3];
+        out[0] = N;
+        out[1] = (K + P + g * I) / N;
+        out[2] = (K + P + 0.5 * g * I) / N;
+        out[3] = K;
+        out[4] = P;
+        out[5] = I;
+        for (int ax = 0; ax < 3; ++ax) {
+            out[6 + ax] = dvol * tot[4 + ax] / N;
+            out[9 + ax] = dvol * tot[7 + ax] / N;
+        }
+        out[12] = (__builtin_isfinite(out[0]) && __builtin_isfinite(out[1])) ? 1.0 : 0.0;
+    }
+}
+
+// ===========================================================================
+// Integrated densities
+// ===========================================================================
+template <class T, bool CPLX>
+__global__ void __launch_bounds__(256) k_density_1d(const void *psi_, int nx, int ny, int nz,
+                                                    int keep, double w, double *out)
+{
+    using A = Alg<T, CPLX>;
+    using V = typename A::V;
+    __shared__ double red[16];
+    const V *psi = reinterpret_cast<const V *>(psi_);
+    const int c = blockIdx.x;  // index along `keep`
+    const long long n3[3] = {nx, ny, nz};
+    const long long sx[3] = {1, nx, (long long)nx * ny};
+    const int u = (keep == 0) ? 1 : 0, v = (keep == 2) ? 1 : 2;
+    const long long cnt = n3[u] * n3[v];
+    double acc = 0.0;
+    for (long long q = threadIdx.x; q < cnt; q += blockDim.x) {
+        const long long iu = q % n3[u], iv = q / n3[u];
+        acc += A::norm2(psi[c * sx[keep] + iu * sx[u] + iv * sx[v]]);
+    }
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) out[c] = w * s;
+}
+
+template <class T, bool CPLX>
+__global__ void __launch_bounds__(256) k_density_2d(const void *psi_, int nx, int ny, int nz,
+                                                    int drop, double w, double *out)
+{
+    using A = Alg<T, CPLX>;
+    using V = typename A::V;
+    const V *psi = reinterpret_cast<const V *>(psi_);
+    const long long n3[3] = {nx, ny, nz};
+    const long long sx[3] = {1, nx, (long long)nx * ny};
+    const int u = (drop == 0) ? 1 : 0, v = (drop == 2) ? 1 : 2;
+    const long long cnt = n3[u] * n3[v];
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= cnt) return;
+    const long long iu = q % n3[u], iv = q / n3[u];
+    double acc = 0.0;
+    for (long long k = 0; k < n3[drop]; ++k) acc += A::norm2(psi[iu * sx[u] + iv * sx[v] + k * sx[drop]]);
+    out[q] = w * acc;
+}
+
+// ===========================================================================
+// launchers
+// ===========================================================================
+#define SSCN_ELEM_DISPATCH(elem, MACRO)           \
+    switch (elem) {                               \
+    case 0: MACRO(double, false); break;          \
+    case 1: MACRO(float, false); break;           \
+    case 2: MACRO(double, true); break;           \
+    case 3: MACRO(float, true); break;            \
+    default: return hipErrorInvalidValue;         \
+    }
+
+template <class T, bool CPLX, int C>
+static void row_launch_c(bool last, const RowArgs &a, int grid, int block, size_t lds, hipStream_t st)
+{
+    if (last) hipLaunchKernelGGL((k_row<T, CPLX, C, true>), dim3(grid), dim3(block), lds, st, a);
+    else hipLaunchKernelGGL((k_row<T, CPLX, C, false>), dim3(grid), dim3(block), lds, st, a);
+}
+
+template <class T, bool CPLX>
+static hipError_t row_launch(int C, bool last, const RowArgs &a, int grid, int block, size_t lds,
+                             hipStream_t st)
+{
+    switch (C) {
+    case 1: row_launch_c<T, CPLX, 1>(last, a, grid, block, lds, st); break;
+    case 2: row_launch_c<T, CPLX, 2>(last, a, grid, block, lds, st); break;
+    case 4: row_launch_c<T, CPLX, 4>(last, a, grid, block, lds, st); break;
+    case 8: row_launch_c<T, CPLX, 8>(last, a, grid, block, lds, st); break;
+    case 16:
+        if constexpr (sizeof(typename Alg<T, CPLX>::V) <= 8) {
+            row_launch_c<T, CPLX, 16>(last, a, grid, block, lds, st);
+            break;
+        }
+        return hipErrorInvalidValue;
+    case 32:
+        if constexpr (sizeof(typename Alg<T, CPLX>::V) <= 4) {
+            row_launch_c<T, CPLX, 32>(last, a, grid, block, lds, st);
+            break;
+        }
+        return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_row(int elem, int C, bool last, const RowArgs &a, int grid, int block, size_t lds,
+                      hipStream_t st)
+{
+#define ROW_CASE(T, CP) return row_launch<T, CP>(C, last, a, grid, block, lds, st)
+    SSCN_ELEM_DISPATCH(elem, ROW_CASE)
+#undef ROW_CASE
+}
+
+template <class T, bool CPLX, int C>
+static void col_launch_c(bool last, const ColArgs &a, int grid, int block, size_t lds, hipStream_t st)
+{
+    if (last) hipLaunchKernelGGL((k_col<T, CPLX, C, true>), dim3(grid), dim3(block), lds, st, a);
+    else hipLaunchKernelGGL((k_col<T, CPLX, C, false>), dim3(grid), dim3(block), lds, st, a);
+}
+
+template <class T, bool CPLX>
+static hipError_t col_launch(int C, bool last, const ColArgs &a, int grid, int block, size_t lds,
+                             hipStream_t st)
+{
+    switch (C) {
+    case 1: col_launch_c<T, CPLX, 1>(last, a, grid, block, lds, st); break;
+    case 2: col_launch_c<T, CPLX, 2>(last, a, grid, block, lds, st); break;
+    case 4: col_launch_c<T, CPLX, 4>(last, a, grid, block, lds, st); break;
+    case 8: col_launch_c<T, CPLX, 8>(last, a, grid, block, lds, st); break;
+    case 16: col_launch_c<T, CPLX, 16>(last, a, grid, block, lds, st); break;
+    case 32:
+        if constexpr (sizeof(typename Alg<T, CPLX>::V) <= 8) {
+            col_launch_c<T, CPLX, 32>(last, a, grid, block, lds, st);
+            break;
+        }
+        return hipErrorInvalidValue;
+    case 64:
+        if constexpr (sizeof(typename Alg<T, CPLX>::V) <= 4) {
+            col_launch_c<T, CPLX, 64>(last, a, grid, block, lds, st);
+            break;
+        }
+        return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_col(int elem, int C, bool last, const ColArgs &a, int grid, int block, size_t lds,
+                      hipStream_t st)
+{
+#define COL_CASE(T, CP) return col_launch<T, CP>(C, last, a, grid, block, lds, st)
+    SSCN_ELEM_DISPATCH(elem, COL_CASE)
+#undef COL_CASE
+}
+
+hipError_t launch_stream(int elem, const ColArgs &a, int grid, int block, hipStream_t st)
+{
+#define ST_CASE(T, CP) hipLaunchKernelGGL((k_stream<T, CP>), dim3(grid), dim3(block), 0, st, a)
+    SSCN_ELEM_DISPATCH(elem, ST_CASE)
+#undef ST_CASE
+    return hipGetLastError();
+}
+
+hipError_t launch_pointwise(int elem, const PointArgs &a, int grid, int block, hipStream_t st)
+{
+#define PW_CASE(T, CP) hipLaunchKernelGGL((k_pointwise<T, CP>), dim3(grid), dim3(block), 0, st, a)
+    SSCN_ELEM_DISPATCH(elem, PW_CASE)
+#undef PW_CASE
+    return hipGetLastError();
+}
+
+hipError_t launch_norm_partials(int elem, const void *psi, int64_t npts, double *partial, int grid,
+                                int block, hipStream_t st)
+{
+#define NP_CASE(T, CP) \
+    hipLaunchKernelGGL((k_norm_partials<T, CP>), dim3(grid), dim3(block), 0, st, psi, (long long)npts, partial)
+    SSCN_ELEM_DISPATCH(elem, NP_CASE)
+#undef NP_CASE
+    return hipGetLastError();
+}
+
+hipError_t launch_norm_final(const double *partial, int np, double dvol, int do_renorm, double *scalars,
+                             hipStream_t st)
+{
+    hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(1024), 0, st, partial, np, dvol, do_renorm, scalars);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_state(int elem, void *psi, int64_t npts, const double *scalars, int grid,
+                              int block, hipStream_t st)
+{
+#define SC_CASE(T, CP) \
+    hipLaunchKernelGGL((k_scale_state<T, CP>), dim3(grid), dim3(block), 0, st, psi, (long long)npts, scalars)
+    SSCN_ELEM_DISPATCH(elem, SC_CASE)
+#undef SC_CASE
+    return hipGetLastError();
+}
+
+hipError_t launch_set_unit_scale(double *scalars, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_set_unit_scale, dim3(1), dim3(64), 0, st, scalars);
+    return hipGetLastError();
+}
+
+hipError_t launch_obs_partials(int elem, const ObsArgs &a, int grid, int block, hipStream_t st)
+{
+#define OB_CASE(T, CP) hipLaunchKernelGGL((k_obs_partials<T, CP>), dim3(grid), dim3(block), 0, st, a)
+    SSCN_ELEM_DISPATCH(elem, OB_CASE)
+#undef OB_CASE
+    return hipGetLastError();
+}
+
+hipError_t launch_obs_final(const double *partial, int np, double dvol, double g, double *out,
+                            hipStream_t st)
+{
+    hipLaunchKernelGGL(k_obs_final, dim3(1), dim3(256), 0, st, partial, np, dvol, g, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_density_1d(int elem, const void *psi, const int32_t *n, int keep, double w, double *out,
+                             hipStream_t st)
+{
+#define D1_CASE(T, CP) \
+    hipLaunchKernelGGL((k_density_1d<T, CP>), dim3(n[keep]), dim3(256), 0, st, psi, n[0], n[1], n[2], keep, w, out)
+    SSCN_ELEM_DISPATCH(elem, D1_CASE)
+#undef D1_CASE
+    return hipGetLastError();
+}
+
+hipError_t launch_density_2d(int elem, const void *psi, const int32_t *n, int drop, double w, double *out,
+                             hipStream_t st)
+{
+    const int u = (drop == 0) ? 1 : 0, v = (drop == 2) ? 1 : 2;
+    const long long cnt = (long long)n[u] * n[v];
+    const int grid = (int)((cnt + 255) / 256);
+#define D2_CASE(T, CP) \
+    hipLaunchKernelGGL((k_density_2d<T, CP>), dim3(grid), dim3(256), 0, st, psi, n[0], n[1], n[2], drop, w, out)
+    SSCN_ELEM_DISPATCH(elem, D2_CASE)
+#undef D2_CASE
+    return hipGetLastError();
+}
+
+}  // namespace sscn

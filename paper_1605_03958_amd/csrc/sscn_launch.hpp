@@ -1,0 +1,82 @@
+// sscn_launch.hpp -- host-side launch interface between the runtime
+// (sscn_api.cpp) and the kernels (sscn_kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sscn_dev.hpp"
+
+namespace sscn {
+
+// x sweep with the pointwise substep fused into its load (ROW geometry).
+struct RowArgs {
+    void *psi;
+    const TabEntry *tab;   // lane-major: entry (k, t) at [k * 64 * wpl + t]
+    int32_t n;             // line length n_x
+    int32_t nlines;        // n_y * n_z
+    int32_t wpl;           // waves per line (power of two, <= 16)
+    int32_t lpb;           // lines per block
+    double sig_re, sig_im; // CN coefficient s
+    PointParams pp;
+    const double *scale;   // pending renormalisation factor (imaginary time)
+    double *partial;       // norm partial per block when this is the last sweep
+};
+
+// y or z sweep (COL geometry) and the one-thread-per-line fallback.
+// Line l starts at (l % m1) * s1 + (l / m1) * s2; its points are `stride`
+// apart.
+struct ColArgs {
+    void *psi;
+    const TabEntry *tab;   // entry i at [i], zero past the line end
+    int32_t n;
+    int32_t nlines;
+    int64_t stride;
+    int32_t m1;
+    int64_t s1, s2;
+    int32_t W;             // waves per block = chunks per line (COL)
+    double sig_re, sig_im;
+    double *partial;
+};
+
+struct PointArgs {
+    void *psi;
+    int64_t npts;
+    PointParams pp;
+    const double *scale;
+};
+
+// Kernel launchers.  elem: 0 double, 1 float, 2 complex<double>, 3 complex<float>.
+hipError_t launch_row(int elem, int C, bool last, const RowArgs &a, int grid, int block,
+                      size_t lds, hipStream_t st);
+hipError_t launch_col(int elem, int C, bool last, const ColArgs &a, int grid, int block,
+                      size_t lds, hipStream_t st);
+hipError_t launch_stream(int elem, const ColArgs &a, int grid, int block, hipStream_t st);
+hipError_t launch_pointwise(int elem, const PointArgs &a, int grid, int block, hipStream_t st);
+hipError_t launch_norm_partials(int elem, const void *psi, int64_t npts, double *partial,
+                                int grid, int block, hipStream_t st);
+hipError_t launch_norm_final(const double *partial, int np, double dvol, int do_renorm,
+                             double *scalars, hipStream_t st);
+hipError_t launch_scale_state(int elem, void *psi, int64_t npts, const double *scalars,
+                              int grid, int block, hipStream_t st);
+hipError_t launch_set_unit_scale(double *scalars, hipStream_t st);
+
+struct ObsArgs {
+    const void *psi;
+    int32_t dim;
+    int32_t n[3];
+    double dx[3], cen[3], w2h[3];
+    int64_t npts;
+    double *partial;       // 12 doubles per block
+};
+hipError_t launch_obs_partials(int elem, const ObsArgs &a, int grid, int block, hipStream_t st);
+// out[0..15]: norm, mu, E, K, P, I, <x>, <y>, <z>, <x^2>, <y^2>, <z^2>, finite flag
+hipError_t launch_obs_final(const double *partial, int np, double dvol, double g, double *out,
+                            hipStream_t st);
+
+hipError_t launch_density_1d(int elem, const void *psi, const int32_t *n, int keep, double w,
+                             double *out, hipStream_t st);
+hipError_t launch_density_2d(int elem, const void *psi, const int32_t *n, int drop, double w,
+                             double *out, hipStream_t st);
+
+}  // namespace sscn

@@ -1,0 +1,61 @@
+// sscn_plan.hpp -- kernel plan of one problem: geometry per axis and the
+// workspace layout.  Deterministic in the problem (and any tile hint for its
+// shape), so the workspace size reported before create matches the plan
+// used by create.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "sscn.h"
+#include "sscn_dev.hpp"
+
+namespace sscn {
+
+enum { K_ROW = 0, K_COL = 1, K_STREAM = 2 };
+
+struct AxisPlan {
+    int kind;
+    int n;
+    int C;        // points per thread
+    int wpl;      // ROW: waves per line
+    int lpb;      // ROW: lines per block
+    int W;        // COL: waves (chunks) per block
+    int grid, block;
+    size_t lds;
+    size_t tab_off, tab_entries;
+    int64_t nlines;
+    int m1;
+    int64_t s1, s2, stride;
+    double sig_re, sig_im;
+};
+
+struct Plan {
+    int elem;
+    size_t S;
+    int64_t npts;
+    AxisPlan ax[3];
+    bool sep_pointwise, sep_norm;
+    int pw_grid, np_norm, obs_grid;
+    size_t off_scal, off_obs, off_part, off_obspart, ws_bytes;
+};
+
+// Chunk lengths chosen by the tuner for one shape (0 = default choice).
+struct TileOverride {
+    int row_c;
+    int col_c[3];
+};
+
+int elem_of(const sscn_problem &pb);
+size_t elem_bytes(int elem);
+int validate(const sscn_problem *pb);
+int make_plan(const sscn_problem &pb, const TileOverride *ov, Plan &P);
+void build_table(const sscn_problem &pb, const Plan &P, int a, std::vector<TabEntry> &out);
+
+// Tile hints registered through the ABI, keyed by (dim, n, mode, prec):
+// copies the hint for pb's shape into out and returns true if there is one.
+bool tile_hint_copy(const sscn_problem &pb, TileOverride &out);
+
+}  // namespace sscn

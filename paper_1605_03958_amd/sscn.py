@@ -1,0 +1,331 @@
+"""Thin ctypes binding of libsscn.so (include/sscn.h).
+
+Argument marshalling only: every step of the propagation runs in the HIP
+kernels behind the C ABI.  PyTorch supplies device memory (the state and the
+workspace are torch tensors the binding owns) and the current HIP stream.
+The library must be built (``paper_1605_03958_amd/build.py``); importing
+this module without it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsscn.so")
+
+OK, NOT_CONVERGED = 0, 1
+E_INVALID, E_HIP, E_NONFINITE, E_NOSPACE, E_UNSUPPORTED = -1, -2, -3, -4, -5
+IMAG, REAL = 0, 1
+F64, F32 = 0, 1
+NKERNELS = 5
+KERNEL_CLASSES = ("x_sweep_pointwise", "y_sweep", "z_sweep_norm", "norm_final", "scale_pass")
+
+
+class SSCNError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: {status_string(code)} ({code})")
+        self.code = code
+
+
+class CProblem(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int32),
+        ("n", ctypes.c_int32 * 3),
+        ("dx", ctypes.c_double * 3),
+        ("omega", ctypes.c_double * 3),
+        ("g", ctypes.c_double),
+        ("dt", ctypes.c_double),
+        ("mode", ctypes.c_int32),
+        ("prec", ctypes.c_int32),
+        ("renorm_every", ctypes.c_int32),
+        ("observe_every", ctypes.c_int32),
+    ]
+
+
+class CObs(ctypes.Structure):
+    _fields_ = [
+        ("step", ctypes.c_int64),
+        ("norm", ctypes.c_double),
+        ("mu", ctypes.c_double),
+        ("energy", ctypes.c_double),
+        ("ekin", ctypes.c_double),
+        ("epot", ctypes.c_double),
+        ("eint", ctypes.c_double),
+        ("mean", ctypes.c_double * 3),
+        ("msq", ctypes.c_double * 3),
+        ("status", ctypes.c_int32),
+        ("pad_", ctypes.c_int32),
+    ]
+
+
+EXPORTS = {
+    "sscn_abi_version": ([], ctypes.c_int),
+    "sscn_status_string": ([ctypes.c_int], ctypes.c_char_p),
+    "sscn_validate": ([ctypes.POINTER(CProblem)], ctypes.c_int),
+    "sscn_state_bytes": ([ctypes.POINTER(CProblem), ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "sscn_workspace_bytes": ([ctypes.POINTER(CProblem), ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "sscn_create": ([ctypes.POINTER(CProblem), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                     ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
+    "sscn_step": ([ctypes.c_void_p, ctypes.c_int64], ctypes.c_int),
+    "sscn_observe": ([ctypes.c_void_p, ctypes.POINTER(CObs)], ctypes.c_int),
+    "sscn_run": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.POINTER(CObs),
+                  ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+    "sscn_set_g": ([ctypes.c_void_p, ctypes.c_double], ctypes.c_int),
+    "sscn_step_timed": ([ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "sscn_set_tile_hint": ([ctypes.POINTER(CProblem), ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+    "sscn_clear_tile_hints": ([], ctypes.c_int),
+    "sscn_plan_info": ([ctypes.POINTER(CProblem), ctypes.POINTER(ctypes.c_int32), ctypes.c_int32],
+                       ctypes.c_int),
+    "sscn_destroy": ([ctypes.c_void_p], ctypes.c_int),
+    "sscn_density_1d": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
+    "sscn_density_2d": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libsscn.so (never builds it); raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"libsscn.so is not built ({LIB_PATH}); run paper_1605_03958_amd/build.py")
+    L = ctypes.CDLL(LIB_PATH)
+    for name, (args, res) in EXPORTS.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def status_string(code: int) -> str:
+    try:
+        return lib().sscn_status_string(int(code)).decode()
+    except Exception:  # pragma: no cover - only when the library is absent
+        return "unknown"
+
+
+def _check(rc: int, what: str, allow=(OK,)):
+    if rc not in allow:
+        raise SSCNError(rc, what)
+    return rc
+
+
+@dataclass
+class Problem:
+    dim: int
+    n: tuple
+    dx: tuple
+    omega: tuple
+    g: float
+    dt: float
+    mode: int = IMAG
+    prec: int = F64
+    renorm_every: int = 1
+    observe_every: int = 0
+
+    def __post_init__(self):
+        self.n = tuple(int(v) for v in (list(self.n) + [1, 1, 1])[:3])
+        self.dx = tuple(float(v) for v in (list(self.dx) + [1.0, 1.0, 1.0])[:3])
+        self.omega = tuple(float(v) for v in (list(self.omega) + [0.0, 0.0, 0.0])[:3])
+
+    def c(self) -> CProblem:
+        p = CProblem()
+        p.dim = int(self.dim)
+        for a in range(3):
+            p.n[a] = self.n[a]
+            p.dx[a] = self.dx[a]
+            p.omega[a] = self.omega[a]
+        p.g = float(self.g)
+        p.dt = float(self.dt)
+        p.mode = int(self.mode)
+        p.prec = int(self.prec)
+        p.renorm_every = int(self.renorm_every)
+        p.observe_every = int(self.observe_every)
+        return p
+
+    @property
+    def shape(self):
+        return (self.n[2], self.n[1], self.n[0])
+
+    @property
+    def points(self) -> int:
+        return self.n[0] * self.n[1] * self.n[2]
+
+    @property
+    def dvol(self) -> float:
+        return float(np.prod(self.dx[: self.dim]))
+
+    def torch_dtype(self):
+        import torch
+        if self.mode == IMAG:
+            return torch.float64 if self.prec == F64 else torch.float32
+        return torch.complex128 if self.prec == F64 else torch.complex64
+
+    def numpy_dtype(self):
+        if self.mode == IMAG:
+            return np.float64 if self.prec == F64 else np.float32
+        return np.complex128 if self.prec == F64 else np.complex64
+
+
+def validate(prob: Problem) -> int:
+    pc = prob.c()
+    return lib().sscn_validate(ctypes.byref(pc))
+
+
+def state_bytes(prob: Problem) -> int:
+    pc = prob.c()
+    v = ctypes.c_size_t(0)
+    _check(lib().sscn_state_bytes(ctypes.byref(pc), ctypes.byref(v)), "sscn_state_bytes")
+    return int(v.value)
+
+
+def workspace_bytes(prob: Problem) -> int:
+    pc = prob.c()
+    v = ctypes.c_size_t(0)
+    _check(lib().sscn_workspace_bytes(ctypes.byref(pc), ctypes.byref(v)), "sscn_workspace_bytes")
+    return int(v.value)
+
+
+def plan_info(prob: Problem):
+    pc = prob.c()
+    info = (ctypes.c_int32 * 15)()
+    _check(lib().sscn_plan_info(ctypes.byref(pc), info, 15), "sscn_plan_info")
+    kinds = {0: "row", 1: "col", 2: "stream", -1: None}
+    out = []
+    for a in range(3):
+        k = info[5 * a]
+        out.append(None if k < 0 else dict(kind=kinds[k], chunk=info[5 * a + 1], waves=info[5 * a + 2],
+                                           grid=info[5 * a + 3], block=info[5 * a + 4]))
+    return out
+
+
+def set_tile_hint(prob: Problem, chunks) -> None:
+    pc = prob.c()
+    arr = (ctypes.c_int32 * 3)(*[int(c) for c in chunks])
+    _check(lib().sscn_set_tile_hint(ctypes.byref(pc), arr), "sscn_set_tile_hint")
+
+
+def clear_tile_hints() -> None:
+    lib().sscn_clear_tile_hints()
+
+
+@dataclass
+class Obs:
+    step: int
+    norm: float
+    mu: float
+    energy: float
+    ekin: float
+    epot: float
+    eint: float
+    mean: tuple = field(default=(0.0, 0.0, 0.0))
+    msq: tuple = field(default=(0.0, 0.0, 0.0))
+    status: int = OK
+
+    @staticmethod
+    def from_c(o: CObs) -> "Obs":
+        return Obs(int(o.step), o.norm, o.mu, o.energy, o.ekin, o.epot, o.eint,
+                   tuple(o.mean), tuple(o.msq), int(o.status))
+
+
+class Solver:
+    """One SSCN problem bound to torch-owned device memory on a stream."""
+
+    def __init__(self, prob: Problem, psi0=None, device: str = "cuda", stream=None):
+        import torch
+        L = lib()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device available")
+        self.prob = prob
+        self._pc = prob.c()
+        _check(L.sscn_validate(ctypes.byref(self._pc)), "sscn_validate")
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.psi = torch.zeros(prob.shape, dtype=prob.torch_dtype(), device=self.device)
+        wsb = workspace_bytes(prob)
+        self.ws = torch.zeros(wsb // 8 + 32, dtype=torch.float64, device=self.device)
+        ws_ptr = self.ws.data_ptr()
+        if ws_ptr % 256:
+            raise RuntimeError("workspace tensor is not 256-byte aligned")
+        if psi0 is not None:
+            self.set_state(psi0)
+        h = ctypes.c_void_p(0)
+        torch.cuda.synchronize(self.device)
+        _check(L.sscn_create(ctypes.byref(self._pc), ctypes.c_void_p(self.psi.data_ptr()),
+                             ctypes.c_void_p(ws_ptr), ctypes.c_void_p(self.stream.cuda_stream),
+                             ctypes.byref(h)), "sscn_create")
+        self._h = h
+
+    # -- state ---------------------------------------------------------------
+    def set_state(self, psi0) -> None:
+        import torch
+        a = np.ascontiguousarray(np.asarray(psi0).reshape(self.prob.shape))
+        if self.prob.mode == IMAG and np.iscomplexobj(a):
+            a = a.real
+        a = a.astype(self.prob.numpy_dtype())
+        with torch.cuda.stream(self.stream):
+            self.psi.copy_(torch.from_numpy(a))
+        self.stream.synchronize()
+
+    def state(self) -> np.ndarray:
+        self.stream.synchronize()
+        return self.psi.cpu().numpy()
+
+    # -- propagation ---------------------------------------------------------
+    def step(self, nsteps: int) -> None:
+        _check(lib().sscn_step(self._h, int(nsteps)), "sscn_step")
+
+    def step_timed(self, nsteps: int):
+        ms = (ctypes.c_double * NKERNELS)()
+        _check(lib().sscn_step_timed(self._h, int(nsteps), ms), "sscn_step_timed")
+        return dict(zip(KERNEL_CLASSES, list(ms)))
+
+    def observe(self) -> Obs:
+        o = CObs()
+        rc = lib().sscn_observe(self._h, ctypes.byref(o))
+        _check(rc, "sscn_observe", allow=(OK, E_NONFINITE))
+        return Obs.from_c(o)
+
+    def run(self, max_steps: int, mu_tol: float, trace_cap: int = 100000):
+        cap = int(trace_cap)
+        buf = (CObs * max(cap, 1))()
+        rows = ctypes.c_int64(0)
+        rc = lib().sscn_run(self._h, int(max_steps), float(mu_tol), buf, cap, ctypes.byref(rows))
+        _check(rc, "sscn_run", allow=(OK, NOT_CONVERGED, E_NONFINITE))
+        return rc, [Obs.from_c(buf[i]) for i in range(rows.value)]
+
+    def set_g(self, g: float) -> None:
+        _check(lib().sscn_set_g(self._h, float(g)), "sscn_set_g")
+
+    def density_1d(self, keep: int) -> np.ndarray:
+        import torch
+        out = torch.zeros(self.prob.n[keep], dtype=torch.float64, device=self.device)
+        _check(lib().sscn_density_1d(self._h, int(keep), ctypes.c_void_p(out.data_ptr())), "sscn_density_1d")
+        self.stream.synchronize()
+        return out.cpu().numpy()
+
+    def density_2d(self, drop: int) -> np.ndarray:
+        import torch
+        keep = [a for a in range(3) if a != drop]
+        out = torch.zeros((self.prob.n[keep[1]], self.prob.n[keep[0]]), dtype=torch.float64, device=self.device)
+        _check(lib().sscn_density_2d(self._h, int(drop), ctypes.c_void_p(out.data_ptr())), "sscn_density_2d")
+        self.stream.synchronize()
+        return out.cpu().numpy()
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib().sscn_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,117 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/sscn.h declares, validates problems before any side
+effect, sizes the state and workspace, and plans kernel geometries."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1605_03958_amd import sscn
+from paper_1605_03958_amd.sscn import Problem, IMAG, REAL, F64, F32
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared(header):
+    text = open(os.path.join(ROOT, "include", header)).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sscn_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = sscn.lib()
+    names = _declared("sscn.h")
+    assert "sscn_create" in names and "sscn_step" in names
+    for name in names:
+        assert hasattr(L, name), name
+    # and the binding declares a signature for each of them
+    missing = [n for n in names if n not in sscn.EXPORTS and not n.startswith("sscn_batch")]
+    assert not missing, missing
+
+
+def test_abi_version_and_status_strings():
+    L = sscn.lib()
+    assert L.sscn_abi_version() == 1
+    for code in (0, 1, -1, -2, -3, -4, -5, 99):
+        assert isinstance(sscn.status_string(code), str) and sscn.status_string(code)
+
+
+def _good():
+    return Problem(3, (8, 6, 5), (0.2, 0.2, 0.2), (1, 1.5, 2), 22.0, 0.004, IMAG, F64, 1, 10)
+
+
+@pytest.mark.parametrize("field,value", [
+    ("dim", 0), ("dim", 4), ("n", (0, 6, 5)), ("dx", (0.0, 0.2, 0.2)), ("dx", (float("nan"), 0.2, 0.2)),
+    ("omega", (-1.0, 1, 1)), ("omega", (float("inf"), 1, 1)), ("g", float("nan")), ("dt", 0.0),
+    ("dt", -1.0), ("mode", 2), ("prec", 5), ("renorm_every", 0), ("observe_every", -1),
+])
+def test_validate_rejects(field, value):
+    p = _good()
+    setattr(p, field, value)
+    p.__post_init__()
+    assert sscn.validate(p) == sscn.E_INVALID
+
+
+def test_validate_unused_axis_and_real_renorm():
+    p = Problem(2, (8, 6, 2), (0.2, 0.2, 1), (1, 1, 0), 1.0, 0.01, IMAG, F64, 1)
+    assert sscn.validate(p) == sscn.E_INVALID        # n_z must be 1 in 2D
+    p = Problem(2, (8, 6, 1), (0.2, 0.2, 1), (1, 1, 0), 1.0, 0.01, REAL, F64, 1)
+    assert sscn.validate(p) == sscn.E_INVALID        # no renormalisation in real time
+    p.renorm_every = 0
+    assert sscn.validate(p) == sscn.OK
+    huge = Problem(3, (20000, 20000, 20000), (0.1,) * 3, (1, 1, 1), 1.0, 0.01, IMAG, F64, 1)
+    assert sscn.validate(huge) == sscn.E_UNSUPPORTED
+
+
+def test_state_bytes_by_dtype():
+    for mode, prec, size in ((IMAG, F64, 8), (IMAG, F32, 4), (REAL, F64, 16), (REAL, F32, 8)):
+        p = Problem(3, (7, 5, 3), (0.2,) * 3, (1, 1, 1), 1.0, 0.01, mode, prec, 1 if mode == IMAG else 0)
+        assert sscn.state_bytes(p) == 7 * 5 * 3 * size
+        assert sscn.workspace_bytes(p) % 256 == 0 and sscn.workspace_bytes(p) > 0
+
+
+def test_null_arguments_rejected_without_side_effects():
+    L = sscn.lib()
+    pc = _good().c()
+    h = ctypes.c_void_p(0)
+    assert L.sscn_create(ctypes.byref(pc), None, None, None, ctypes.byref(h)) == sscn.E_INVALID
+    assert h.value is None
+    assert L.sscn_create(ctypes.byref(pc), ctypes.c_void_p(256), ctypes.c_void_p(260), None,
+                         ctypes.byref(h)) == sscn.E_INVALID   # misaligned workspace
+    assert L.sscn_step(None, 1) == sscn.E_INVALID
+    assert L.sscn_set_g(None, 1.0) == sscn.E_INVALID
+    assert L.sscn_destroy(None) == sscn.E_INVALID
+    assert L.sscn_validate(None) == sscn.E_INVALID
+
+
+def test_plan_geometries():
+    # 256^3 complex128: x lines in registers (4 points per lane), y/z 16 x 16
+    p = Problem(3, (256, 256, 256), (0.1,) * 3, (1, 1.5, 2), 80.0, 2e-4, REAL, F64, 0)
+    info = sscn.plan_info(p)
+    assert info[0]["kind"] == "row" and info[0]["chunk"] == 4 and info[0]["waves"] == 1
+    assert info[1]["kind"] == "col" and info[1]["chunk"] * info[1]["waves"] >= 256
+    assert info[2]["kind"] == "col"
+    # long x lines use several waves per line; too long falls back
+    p = Problem(1, (5000, 1, 1), (0.1,), (1,), 1.0, 1e-3, IMAG, F64, 1)
+    info = sscn.plan_info(p)
+    assert info[0]["kind"] == "row" and info[0]["waves"] == 8
+    assert info[1] is None
+    p = Problem(1, (300000, 1, 1), (0.1,), (1,), 1.0, 1e-3, IMAG, F64, 1)
+    assert sscn.plan_info(p)[0]["kind"] == "stream"
+    p = Problem(2, (64, 700, 1), (0.1, 0.1), (1, 1), 1.0, 1e-3, REAL, F64, 0)
+    assert sscn.plan_info(p)[1]["kind"] == "stream"
+
+
+def test_tile_hints_change_the_plan():
+    p = Problem(3, (64, 64, 64), (0.2,) * 3, (1, 1.5, 2), 22.0, 0.004, IMAG, F64, 1)
+    try:
+        sscn.set_tile_hint(p, (2, 8, 16))
+        info = sscn.plan_info(p)
+        assert info[0]["chunk"] == 2 and info[1]["chunk"] == 8 and info[2]["chunk"] == 16
+        assert info[1]["waves"] == 8 and info[2]["waves"] == 4
+        with pytest.raises(sscn.SSCNError):
+            sscn.set_tile_hint(p, (3, 0, 0))
+    finally:
+        sscn.clear_tile_hints()
+    assert sscn.plan_info(p)[1]["chunk"] == 4
