@@ -64,6 +64,25 @@ def time_steps(solver, steps, warmup):
     return time.perf_counter() - t0
 
 
+def copy_bandwidth(nbytes: int, reps: int = 20):
+    """Device-to-device copy rate (GB/s, read + write counted) of a plain
+    torch copy kernel over nbytes, as a measured ceiling beside the peak."""
+    import torch
+    x = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    del x, y
+    torch.cuda.empty_cache()
+    return 2 * nbytes / dt / 1e9
+
+
 def cpu_baseline(target_s: float = 12.0):
     """The FP64 oracle on a bounded sample of the same workload: the full
     256^3 grid for as many steps as fit in about target_s seconds."""
@@ -73,16 +92,16 @@ def cpu_baseline(target_s: float = 12.0):
     op = oracle.Problem(p.dim, p.n, p.dx, p.omega, p.g, p.dt, p.mode, p.renorm_every)
     psi0 = inputs.thomas_fermi(3, p.n, p.dx, p.omega, 100.0, phase_sigma=0.05, seed=1)
     t0 = time.perf_counter()
-    r = oracle.run(op, psi0, 1)
-    t1 = time.perf_counter() - t0
-    steps = max(1, int(target_s / max(t1, 1e-3)) - 1)
+    r = oracle.run(op, psi0, 2)
+    t2 = time.perf_counter() - t0
+    steps = max(1, int(2 * target_s / max(t2, 1e-3)) - 2)
     t0 = time.perf_counter()
-    oracle.run(op, r.psi, steps, first_step=2)
+    oracle.run(op, r.psi, steps, first_step=3)
     dt = time.perf_counter() - t0
-    total = steps + 1
-    return {"value": p.points * total / (dt + t1), "unit": "grid-point-steps/s", "cores": oracle.threads(),
+    total = steps + 2
+    return {"value": p.points * total / (dt + t2), "unit": "grid-point-steps/s", "cores": oracle.threads(),
             "kind": "oracle",
-            "sample": f"256^3 complex128 real-time workload, first {total} steps ({dt + t1:.1f} s), "
+            "sample": f"256^3 complex128 real-time workload, first {total} steps ({dt + t2:.1f} s), "
                       f"FP64 C oracle with OpenMP over lines"}
 
 
@@ -160,6 +179,7 @@ def main():
         res["fp32"] = {"value": f["pts"], "ms_per_step": 1e3 * f["elapsed"] / args.steps,
                        "speedup_vs_fp64": f["pts"] / m["pts"], "kernel_ms": {k: round(v, 5) for k, v in f["kernels"].items()},
                        "state": "complex64"}
+    res["copy_gbs"] = copy_bandwidth(m["S"] * m["points"])
     if not args.no_cpu and args.only is None:
         res["cpu_baseline"] = cpu_baseline()
     print(json.dumps(res), flush=True)

@@ -165,10 +165,13 @@ int sscn_step_timed(sscn_solver *s, int64_t nsteps, double *ms);
 int sscn_set_tile_hint(const sscn_problem *pb, const int32_t chunk[3]);
 int sscn_clear_tile_hints(void);
 
-/* Kernel plan of a problem, 5 ints per axis (x, y, z): kind (0 ROW: lanes
+/* Kernel plan of a problem, 8 ints per axis (x, y, z): kind (0 ROW: lanes
  * along the line, 1 COL: lanes across lines, 2 one-thread-per-line
- * fallback, -1 unused axis), points per thread, waves per line group, grid
- * and block size.  info needs cap >= 15 entries. */
+ * fallback, -1 unused axis), points per thread, waves per line group (ROW)
+ * or per block (COL), lanes per line (COL; 1 otherwise), grid size, block
+ * size, first index of the constant tail of the Thomas table, and the scan
+ * depth (ROW: shuffle steps; COL: preceding chunks folded).  info needs
+ * cap >= 24 entries. */
 int sscn_plan_info(const sscn_problem *pb, int32_t *info, int32_t cap);
 
 /* Free the handle's host state (the caller's device memory is untouched).

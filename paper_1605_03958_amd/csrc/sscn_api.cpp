@@ -67,6 +67,66 @@ int validate(const sscn_problem *pb)
     return SSCN_OK;
 }
 
+void thomas_coefs(double s_re, double s_im, int n, std::vector<double> &m_re, std::vector<double> &m_im,
+                  std::vector<double> &a_re, std::vector<double> &a_im)
+{
+    const std::complex<double> s(s_re, s_im);
+    const std::complex<double> b = 1.0 + 2.0 * s;
+    m_re.resize(n);
+    m_im.resize(n);
+    a_re.resize(n);
+    a_im.resize(n);
+    std::complex<double> m = 1.0 / b;
+    for (int i = 0; i < n; ++i) {
+        if (i > 0) m = 1.0 / (b - s * s * m);
+        const std::complex<double> al = s * m;
+        m_re[i] = m.real();
+        m_im[i] = m.imag();
+        a_re[i] = al.real();
+        a_im[i] = al.imag();
+    }
+}
+
+// Table metadata of axis a for its chunk geometry (C points per chunk).
+static void table_meta(AxisPlan &X, bool fp32)
+{
+    std::vector<double> mr, mi, ar, ai;
+    thomas_coefs(X.sig_re, X.sig_im, X.n, mr, mi, ar, ai);
+    const int n = X.n;
+    // constant tail: first index from which every entry equals the last one
+    int ic = n - 1;
+    while (ic > 0 && mr[ic - 1] == mr[n - 1] && mi[ic - 1] == mi[n - 1] && ar[ic - 1] == ar[n - 1] &&
+           ai[ic - 1] == ai[n - 1])
+        --ic;
+    X.i_conv = ic;
+    X.ac_re = ar[n - 1];
+    X.ac_im = ai[n - 1];
+    X.mc_re = mr[n - 1];
+    X.mc_im = mi[n - 1];
+    // largest product of |alpha| over a full chunk, and the number of
+    // preceding chunks whose contribution can exceed the threshold
+    double amax = 0.0;
+    const int C = std::max(1, X.C);
+    for (int c0 = 0; c0 + C <= n; c0 += C) {
+        double p = 1.0;
+        for (int i = c0; i < c0 + C; ++i) p *= std::hypot(ar[i], ai[i]);
+        amax = std::max(amax, p);
+    }
+    const double lthr = fp32 ? -35.0 * std::log(2.0) : -64.0 * std::log(2.0);
+    int d = 1;
+    if (amax > 0.0) {
+        const double q = lthr / std::log(amax);  // a^q = thr
+        d = (q > 1e6) ? 1000000 : std::max(1, (int)std::ceil(q));
+    }
+    if (X.kind == K_ROW) {
+        int ks = 0;
+        while ((1 << ks) < d && ks < 6) ++ks;
+        X.depth = ks;
+    } else {
+        X.depth = std::min(d, std::max(1, X.W * std::max(1, X.L)));
+    }
+}
+
 // Largest chunk length per thread kept in registers, by element size.
 static int cmax_row(size_t S) { return S >= 16 ? 8 : (S >= 8 ? 16 : 32); }
 static int cmax_col(size_t S) { return S >= 16 ? 16 : (S >= 8 ? 32 : 64); }
@@ -108,8 +168,10 @@ int make_plan(const sscn_problem &pb, const TileOverride *ov, Plan &P)
                 X.wpl = wpl;
                 X.lpb = std::max(1, 4 / wpl);
                 X.block = 64 * wpl * X.lpb;
-                X.grid = (int)std::min<int64_t>(ceil_div(X.nlines, X.lpb), 1 << 20);
-                X.lds = (size_t)X.lpb * wpl * 4 * P.S;
+                X.grid = (int)std::min<int64_t>(ceil_div(X.nlines, X.lpb), 4096);
+                // single-wave lines stage their table in LDS; multi-wave
+                // lines exchange 4 values per wave
+                X.lds = (wpl == 1) ? (size_t)c * 64 * 2 * P.S : (size_t)X.lpb * wpl * 4 * P.S;
                 X.tab_entries = (size_t)c * 64 * wpl;
             }
         } else {
@@ -117,17 +179,22 @@ int make_plan(const sscn_problem &pb, const TileOverride *ov, Plan &P)
             X.s1 = 1;
             X.s2 = (a == 1) ? nx * ny : nx;
             X.stride = (a == 1) ? nx : nx * ny;
-            int c = pow2ceil(ceil_div(n, 16));
+            // about 32 registers of state per thread: C points, W*L >= n/C
+            int c = std::max(1, (int)(128 / P.S));
+            c = std::min<int64_t>(c, pow2ceil(ceil_div(n, 16)));
             if (ov && ov->col_c[a] > 0) c = ov->col_c[a];
-            const int64_t W = ceil_div(n, c);
-            if (c <= cmax_col(P.S) && W <= 16) {
+            const int64_t K = ceil_div(n, c);           // chunks per line
+            const int L = pow2ceil(ceil_div(K, 16));    // lanes per line
+            const int64_t W = ceil_div(K, L);
+            if (c <= cmax_col(P.S) && L <= 4) {
                 X.kind = K_COL;
                 X.C = c;
                 X.W = (int)W;
+                X.L = L;
                 X.block = 64 * (int)W;
-                X.grid = (int)ceil_div(X.nlines, 64);
-                X.lds = (size_t)2 * W * 64 * P.S;
-                X.tab_entries = (size_t)W * c;
+                X.grid = (int)ceil_div(X.nlines, 64 / L);
+                X.lds = (size_t)W * L * c * 2 * P.S + (size_t)2 * W * 64 * P.S;
+                X.tab_entries = (size_t)W * L * c;
             }
         }
         if (X.kind == K_STREAM) {
@@ -135,6 +202,8 @@ int make_plan(const sscn_problem &pb, const TileOverride *ov, Plan &P)
             X.grid = (int)ceil_div(X.nlines, 256);
             X.tab_entries = (size_t)n;
         }
+        table_meta(X, pb.prec == SSCN_F32);
+        if (X.kind == K_STREAM) X.i_conv = X.n;
         if (X.grid > 2147483647 / 2) return SSCN_E_UNSUPPORTED;
     }
     const AxisPlan &L = P.ax[pb.dim - 1];
@@ -166,16 +235,10 @@ void build_table(const sscn_problem &pb, const Plan &P, int a, std::vector<TabEn
 {
     const AxisPlan &X = P.ax[a];
     const int n = X.n;
-    const std::complex<double> s(X.sig_re, X.sig_im);
-    const std::complex<double> b = 1.0 + 2.0 * s;
-    std::vector<std::complex<double>> m(n), al(n);
-    m[0] = 1.0 / b;
-    for (int i = 1; i < n; ++i) m[i] = 1.0 / (b - s * s * m[i - 1]);
-    for (int i = 0; i < n; ++i) al[i] = s * m[i];
+    std::vector<double> mr, mi, ar, ai;
+    thomas_coefs(X.sig_re, X.sig_im, n, mr, mi, ar, ai);
     out.assign(X.tab_entries, TabEntry{0, 0, 0, 0});
-    auto put = [&](size_t slot, int i) {
-        out[slot] = TabEntry{al[i].real(), al[i].imag(), m[i].real(), m[i].imag()};
-    };
+    auto put = [&](size_t slot, int i) { out[slot] = TabEntry{ar[i], ai[i], mr[i], mi[i]}; };
     if (X.kind == K_ROW) {
         const int G = 64 * X.wpl;
         for (int t = 0; t < G; ++t)
@@ -243,19 +306,34 @@ static PointParams point_params(const sscn_solver *s)
     return pp;
 }
 
+static LineTab line_tab(sscn_solver *s, int a)
+{
+    const AxisPlan &X = s->P.ax[a];
+    LineTab t;
+    t.tab = reinterpret_cast<const TabEntry *>(s->ws + X.tab_off);
+    t.n = X.n;
+    t.i_conv = X.i_conv;
+    t.ac_re = X.ac_re;
+    t.ac_im = X.ac_im;
+    t.mc_re = X.mc_re;
+    t.mc_im = X.mc_im;
+    t.depth = X.depth;
+    return t;
+}
+
 static ColArgs col_args(sscn_solver *s, int a, bool last)
 {
     const AxisPlan &X = s->P.ax[a];
     ColArgs c;
     c.psi = s->psi;
-    c.tab = reinterpret_cast<const TabEntry *>(s->ws + X.tab_off);
-    c.n = X.n;
+    c.lt = line_tab(s, a);
     c.nlines = (int32_t)X.nlines;
     c.stride = X.stride;
     c.m1 = X.m1;
     c.s1 = X.s1;
     c.s2 = X.s2;
     c.W = X.W;
+    c.L = X.L;
     c.sig_re = X.sig_re;
     c.sig_im = X.sig_im;
     c.partial = last ? reinterpret_cast<double *>(s->ws + s->P.off_part) : nullptr;
@@ -297,8 +375,7 @@ static hipError_t enqueue_step(sscn_solver *s, bool do_renorm, Timer *tm)
         if (X.kind == K_ROW) {
             RowArgs r;
             r.psi = s->psi;
-            r.tab = reinterpret_cast<const TabEntry *>(s->ws + X.tab_off);
-            r.n = X.n;
+            r.lt = line_tab(s, 0);
             r.nlines = (int32_t)X.nlines;
             r.wpl = X.wpl;
             r.lpb = X.lpb;
@@ -434,7 +511,7 @@ int sscn_plan_info(const sscn_problem *pb, int32_t *info, int32_t cap)
 {
     int v = validate(pb);
     if (v != SSCN_OK) return v;
-    if (!info || cap < 15) return SSCN_E_INVALID;
+    if (!info || cap < 24) return SSCN_E_INVALID;
     Plan P;
     TileOverride ov;
     v = make_plan(*pb, tile_hint_copy(*pb, ov) ? &ov : nullptr, P);
@@ -442,11 +519,15 @@ int sscn_plan_info(const sscn_problem *pb, int32_t *info, int32_t cap)
     for (int a = 0; a < 3; ++a) {
         const AxisPlan &X = P.ax[a];
         const bool used = a < pb->dim;
-        info[5 * a + 0] = used ? X.kind : -1;
-        info[5 * a + 1] = used ? X.C : 0;
-        info[5 * a + 2] = used ? (X.kind == K_ROW ? X.wpl : X.W) : 0;
-        info[5 * a + 3] = used ? X.grid : 0;
-        info[5 * a + 4] = used ? X.block : 0;
+        int32_t *o = info + 8 * a;
+        o[0] = used ? X.kind : -1;
+        o[1] = used ? X.C : 0;
+        o[2] = used ? (X.kind == K_ROW ? X.wpl : X.W) : 0;
+        o[3] = used ? (X.kind == K_COL ? X.L : 1) : 0;
+        o[4] = used ? X.grid : 0;
+        o[5] = used ? X.block : 0;
+        o[6] = used ? X.i_conv : 0;
+        o[7] = used ? X.depth : 0;
     }
     return SSCN_OK;
 }

@@ -28,6 +28,62 @@ __device__ __forceinline__ void dev_sincos(T x, T *s, T *c)
     if constexpr (sizeof(T) == 8) sincos(x, s, c); else sincosf(x, s, c);
 }
 
+// sin and cos for |x| <= pi/4 from their Maclaurin series, through x^17 and
+// x^18 in FP64 (remainders below 1e-19 there) and through x^9 and x^10 in
+// FP32 (below 3e-9).  Horner form in x^2.
+template <class T>
+__device__ __forceinline__ void sincos_small(T x, T *s, T *c)
+{
+    const T x2 = x * x;
+    if constexpr (sizeof(T) == 8) {
+        T p = T(1.0 / 355687428096000.0);           //  1/17!
+        p = fmaT(p, -x2, T(1.0 / 1307674368000.0));  //  1/15!
+        p = fmaT(p, -x2, T(1.0 / 6227020800.0));     //  1/13!
+        p = fmaT(p, -x2, T(1.0 / 39916800.0));       //  1/11!
+        p = fmaT(p, -x2, T(1.0 / 362880.0));         //  1/9!
+        p = fmaT(p, -x2, T(1.0 / 5040.0));           //  1/7!
+        p = fmaT(p, -x2, T(1.0 / 120.0));            //  1/5!
+        p = fmaT(p, -x2, T(1.0 / 6.0));              //  1/3!
+        p = fmaT(p, -x2, T(1.0));
+        *s = x * p;
+        T q = T(1.0 / 6402373705728000.0);          //  1/18!
+        q = fmaT(q, -x2, T(1.0 / 20922789888000.0)); //  1/16!
+        q = fmaT(q, -x2, T(1.0 / 87178291200.0));    //  1/14!
+        q = fmaT(q, -x2, T(1.0 / 479001600.0));      //  1/12!
+        q = fmaT(q, -x2, T(1.0 / 3628800.0));        //  1/10!
+        q = fmaT(q, -x2, T(1.0 / 40320.0));          //  1/8!
+        q = fmaT(q, -x2, T(1.0 / 720.0));            //  1/6!
+        q = fmaT(q, -x2, T(1.0 / 24.0));             //  1/4!
+        q = fmaT(q, -x2, T(1.0 / 2.0));              //  1/2!
+        q = fmaT(q, -x2, T(1.0));
+        *c = q;
+    } else {
+        T p = T(1.0 / 362880.0);
+        p = fmaT(p, -x2, T(1.0 / 5040.0));
+        p = fmaT(p, -x2, T(1.0 / 120.0));
+        p = fmaT(p, -x2, T(1.0 / 6.0));
+        p = fmaT(p, -x2, T(1.0));
+        *s = x * p;
+        T q = T(1.0 / 3628800.0);
+        q = fmaT(q, -x2, T(1.0 / 40320.0));
+        q = fmaT(q, -x2, T(1.0 / 720.0));
+        q = fmaT(q, -x2, T(1.0 / 24.0));
+        q = fmaT(q, -x2, T(1.0 / 2.0));
+        q = fmaT(q, -x2, T(1.0));
+        *c = q;
+    }
+}
+
+// Library sin/cos for phases outside [-pi/4, pi/4], kept out of line so the
+// common small-phase path does not carry its registers.
+template <class T>
+__device__ __attribute__((noinline)) cpx<T> phase_slow(T x)
+{
+    T sn, cs;
+    dev_sincos<T>(x, &sn, &cs);
+    return cpx<T>{cs, sn};
+}
+
 // Pointwise substep on one value (imaginary time: scale first; real time: phase).
 template <class T, bool CPLX>
 __device__ __forceinline__ typename Alg<T, CPLX>::V
@@ -42,7 +98,13 @@ apply_point(typename Alg<T, CPLX>::V u, T scale, T vpot, T dt, T g)
         (void)scale;
         T phi = dt * fmaT(g, A::norm2t(u), vpot);
         T sn, cs;
-        dev_sincos<T>(phi, &sn, &cs);
+        if (__builtin_fabs(phi) <= T(0.78539816339744830962)) {
+            sincos_small<T>(phi, &sn, &cs);
+        } else {
+            const cpx<T> e = phase_slow<T>(phi);
+            cs = e.re;
+            sn = e.im;
+        }
         return typename A::V{fmaT(cs, u.re, sn * u.im), fmaT(cs, u.im, -sn * u.re)};
     }
 }
@@ -53,32 +115,92 @@ __device__ __forceinline__ T coord(int i, double cen, double dx)
     return T((double(i) - cen) * dx);
 }
 
+// A table entry in the kernel's working precision (FP64 tables are rounded
+// to FP32 here for the FP32 forms).
+template <class V>
+struct LTab {
+    V al, m;
+};
+
+// Copy a kernel's table slice (cnt entries, zero-padded past the line end
+// by the host) into LDS in the working precision; the caller synchronises
+// before reading it.
+template <class T, bool CPLX>
+__device__ __forceinline__ void stage_table(const TabEntry *__restrict__ src,
+                                            LTab<typename Alg<T, CPLX>::V> *dst, int cnt)
+{
+    using A = Alg<T, CPLX>;
+    for (int q = threadIdx.x; q < cnt; q += blockDim.x) {
+        const TabEntry e = src[q];
+        dst[q] = LTab<typename A::V>{A::coef(e.ar, e.ai), A::coef(e.mr, e.mi)};
+    }
+}
+
+template <class T, bool CPLX>
+__device__ __forceinline__ typename Alg<T, CPLX>::V tab_alpha(const LTab<typename Alg<T, CPLX>::V> *tb, int q)
+{
+    return tb[q].al;
+}
+
+template <class T, bool CPLX>
+__device__ __forceinline__ typename Alg<T, CPLX>::V tab_m(const LTab<typename Alg<T, CPLX>::V> *tb, int q)
+{
+    return tb[q].m;
+}
+
+// Same accessors on the FP64 table in global memory (multi-wave x lines).
+template <class T, bool CPLX>
+__device__ __forceinline__ typename Alg<T, CPLX>::V tab_alpha(const TabEntry *tb, int q)
+{
+    return Alg<T, CPLX>::coef(tb[q].ar, tb[q].ai);
+}
+
+template <class T, bool CPLX>
+__device__ __forceinline__ typename Alg<T, CPLX>::V tab_m(const TabEntry *tb, int q)
+{
+    return Alg<T, CPLX>::coef(tb[q].mr, tb[q].mi);
+}
+
 // ===========================================================================
-// ROW: x lines, G = 64 * wpl threads per line, C points per thread
+// ROW: x lines, G = 64 * wpl threads per line, C points per thread.
+// Single-wave lines (MW = false) stage the lane-major table (C * 64 entries)
+// in LDS; multi-wave lines (MW = true, long 1D lines) read it from global
+// memory and exchange 4 values per wave through LDS.
 // ===========================================================================
-template <class T, bool CPLX, int C, bool LAST>
-__global__ void __launch_bounds__(1024) k_row(RowArgs a)
+template <class T, bool CPLX, int C, bool LAST, bool MW>
+__global__ void __launch_bounds__(MW ? 1024 : 256) k_row(RowArgs a)
 {
     using A = Alg<T, CPLX>;
     using V = typename A::V;
     extern __shared__ unsigned char lds_raw[];
     __shared__ double red[16];
 
-    const int G = 64 * a.wpl;
+    const int G = MW ? 64 * a.wpl : 64;
     const int tid = threadIdx.x;
     const int lb = tid / G;
     const int t = tid - lb * G;
     const int lane = tid & 63;
     const int wl = t >> 6;
+    LTab<V> *tl = reinterpret_cast<LTab<V> *>(lds_raw);
+    const auto tb = [&]() {
+        if constexpr (MW) return a.lt.tab;
+        else return static_cast<const LTab<V> *>(tl);
+    }();
     V *xs = reinterpret_cast<V *>(lds_raw) + lb * a.wpl * 4;
 
     const V sig = A::coef(a.sig_re, a.sig_im);
     const T scale = CPLX ? T(1) : T(*a.scale);
     const T dt = T(a.pp.dt), g = T(a.pp.g);
     V *psi = reinterpret_cast<V *>(a.psi);
-    const int n = a.n;
+    const int n = a.lt.n;
+    const int ks = a.lt.depth;
     const int i0 = t * C;
     double nacc = 0.0;
+
+    if constexpr (!MW) {
+        stage_table<T, CPLX>(a.lt.tab, tl, C * G);
+        __syncthreads();
+    }
 
     for (long long gb = (long long)blockIdx.x * a.lpb; gb < a.nlines;
          gb += (long long)gridDim.x * a.lpb) {
@@ -100,12 +222,14 @@ __global__ void __launch_bounds__(1024) k_row(RowArgs a)
         for (int k = 0; k < C; ++k) {
             const int i = i0 + k;
             V v = A::zero();
-            if (active && i < n) {
-                v = psi[base + i];
-                const T x = coord<T>(i, a.pp.cen[0], a.pp.dx[0]);
-                v = apply_point<T, CPLX>(v, scale, T(a.pp.w2h[0]) * x * x + vyz, dt, g);
-            }
+            if (active && i < n) v = psi[base + i];
             u[k] = v;
+        }
+#pragma unroll
+        for (int k = 0; k < C; ++k) {
+            const int i = i0 + k;
+            const T x = coord<T>(i, a.pp.cen[0], a.pp.dx[0]);
+            u[k] = apply_point<T, CPLX>(u[k], scale, T(a.pp.w2h[0]) * x * x + vyz, dt, g);
         }
 
         // ---- neighbours across chunk boundaries ----
@@ -113,7 +237,7 @@ __global__ void __launch_bounds__(1024) k_row(RowArgs a)
         V right = A::shfl_down(u[0], 1);
         if (lane == 0) left = A::zero();
         if (lane == 63) right = A::zero();
-        if (a.wpl > 1) {
+        if constexpr (MW) {
             if (lane == 0) xs[wl * 4 + 0] = u[0];
             if (lane == 63) xs[wl * 4 + 1] = u[C - 1];
             __syncthreads();
@@ -122,8 +246,9 @@ __global__ void __launch_bounds__(1024) k_row(RowArgs a)
             __syncthreads();
         }
 
-        // ---- right-hand side, tables ----
-        V al[C], be[C];
+        // ---- m_i (1 - sT)u, and the chunk's forward map d -> Ac d + d_loc ----
+        V be[C];
+        V Ac = A::one(), d = A::zero();
         {
             V prev = left;
 #pragma unroll
@@ -131,24 +256,19 @@ __global__ void __launch_bounds__(1024) k_row(RowArgs a)
                 const V nxt = (k + 1 < C) ? u[k + 1] : right;
                 const V r = cn_rhs<T, CPLX>(prev, u[k], nxt, sig);
                 prev = u[k];
-                const TabEntry e = a.tab[(size_t)k * G + t];
-                al[k] = A::coef(e.ar, e.ai);
-                be[k] = A::mul(A::coef(e.mr, e.mi), r);
+                const V al = tab_alpha<T, CPLX>(tb, k * G + t);
+                be[k] = A::mul(tab_m<T, CPLX>(tb, k * G + t), r);
+                d = A::fma(al, d, be[k]);
+                Ac = A::mul(al, Ac);
             }
         }
 
-        // ---- forward recurrence: local map, scan, exact pass ----
-        V Ac = A::one(), d = A::zero();
-#pragma unroll
-        for (int k = 0; k < C; ++k) {
-            d = A::fma(al[k], d, be[k]);
-            Ac = A::mul(al[k], Ac);
-        }
+        // ---- forward: scan of chunk maps over the preceding chunks ----
         V din;
         {
             V PA = Ac, PB = d;
-#pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
+            for (int s = 0; s < ks; ++s) {
+                const int o = 1 << s;
                 const V a2 = A::shfl_up(PA, o), b2 = A::shfl_up(PB, o);
                 if (lane >= o) {
                     PB = A::fma(PA, b2, PB);
@@ -160,7 +280,7 @@ __global__ void __launch_bounds__(1024) k_row(RowArgs a)
                 EA = A::one();
                 EB = A::zero();
             }
-            if (a.wpl > 1) {
+            if constexpr (MW) {
                 if (lane == 63) {
                     xs[wl * 4 + 2] = PA;
                     xs[wl * 4 + 3] = PB;
@@ -177,19 +297,19 @@ __global__ void __launch_bounds__(1024) k_row(RowArgs a)
         d = din;
 #pragma unroll
         for (int k = 0; k < C; ++k) {
-            d = A::fma(al[k], d, be[k]);
+            d = A::fma(tab_alpha<T, CPLX>(tb, k * G + t), d, be[k]);
             be[k] = d;
         }
 
-        // ---- backward recurrence ----
+        // ---- backward ----
         V v = A::zero();
 #pragma unroll
-        for (int k = C - 1; k >= 0; --k) v = A::fma(al[k], v, be[k]);
+        for (int k = C - 1; k >= 0; --k) v = A::fma(tab_alpha<T, CPLX>(tb, k * G + t), v, be[k]);
         V vin;
         {
             V PA = Ac, PB = v;
-#pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
+            for (int s = 0; s < ks; ++s) {
+                const int o = 1 << s;
                 const V a2 = A::shfl_down(PA, o), b2 = A::shfl_down(PB, o);
                 if (lane + o < 64) {
                     PB = A::fma(PA, b2, PB);
@@ -201,7 +321,7 @@ __global__ void __launch_bounds__(1024) k_row(RowArgs a)
                 EA = A::one();
                 EB = A::zero();
             }
-            if (a.wpl > 1) {
+            if constexpr (MW) {
                 if (lane == 0) {
                     xs[wl * 4 + 2] = PA;
                     xs[wl * 4 + 3] = PB;
@@ -218,7 +338,7 @@ __global__ void __launch_bounds__(1024) k_row(RowArgs a)
         v = vin;
 #pragma unroll
         for (int k = C - 1; k >= 0; --k) {
-            v = A::fma(al[k], v, be[k]);
+            v = A::fma(tab_alpha<T, CPLX>(tb, k * G + t), v, be[k]);
             be[k] = v;
         }
 
@@ -239,7 +359,10 @@ __global__ void __launch_bounds__(1024) k_row(RowArgs a)
 }
 
 // ===========================================================================
-// COL: 64 lines per block (lanes), W chunks of C points per line (waves)
+// COL: 64/L lines per block, W*L chunks of C points per line.  Lane l of
+// wave w holds chunk w*L + l/(64/L) of line l%(64/L), so the lanes of each
+// 64/L group read 64/L adjacent lines (contiguous memory).  LDS: the table
+// (W*L*C entries), then two chunk x line exchange arrays.
 // ===========================================================================
 template <class T, bool CPLX, int C, bool LAST>
 __global__ void __launch_bounds__(1024) k_col(ColArgs a)
@@ -248,20 +371,29 @@ __global__ void __launch_bounds__(1024) k_col(ColArgs a)
     using V = typename A::V;
     extern __shared__ unsigned char lds_raw[];
     __shared__ double red[16];
-    V *xs0 = reinterpret_cast<V *>(lds_raw);
-    V *xs1 = xs0 + a.W * 64;
+    const int L = a.L;
+    const int LPB = 64 / L;
+    const int nch = a.W * L;
+    LTab<V> *tb = reinterpret_cast<LTab<V> *>(lds_raw);
+    V *xs0 = reinterpret_cast<V *>(tb + nch * C);
+    V *xs1 = xs0 + nch * LPB;
 
     const int lane = threadIdx.x & 63;
-    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const long long line = (long long)blockIdx.x * 64 + lane;
+    const int w = threadIdx.x >> 6;
+    const int sub = lane / LPB;
+    const int li = lane - sub * LPB;
+    const int ch = w * L + sub;
+    const long long line = (long long)blockIdx.x * LPB + li;
     const bool active = line < a.nlines;
     long long base = 0;
     if (active) base = (line % a.m1) * a.s1 + (line / a.m1) * a.s2;
     V *psi = reinterpret_cast<V *>(a.psi);
     const V sig = A::coef(a.sig_re, a.sig_im);
-    const int n = a.n;
-    const int i0 = w * C;
+    const int n = a.lt.n;
+    const int i0 = ch * C;
     const long long st = a.stride;
+    const int qlo = max(0, ch - a.lt.depth);
+    const int qhi = min(nch - 1, ch + a.lt.depth);
 
     V u[C];
 #pragma unroll
@@ -269,16 +401,18 @@ __global__ void __launch_bounds__(1024) k_col(ColArgs a)
         const int i = i0 + k;
         u[k] = (active && i < n) ? psi[base + (long long)i * st] : A::zero();
     }
+    stage_table<T, CPLX>(a.lt.tab, tb, nch * C);
 
-    // neighbours from the adjacent chunks (waves)
-    xs0[w * 64 + lane] = u[0];
-    xs1[w * 64 + lane] = u[C - 1];
+    // neighbours from the adjacent chunks
+    xs0[ch * LPB + li] = u[0];
+    xs1[ch * LPB + li] = u[C - 1];
     __syncthreads();
-    const V left = (w > 0) ? xs1[(w - 1) * 64 + lane] : A::zero();
-    const V right = (w + 1 < a.W) ? xs0[(w + 1) * 64 + lane] : A::zero();
+    const V left = (ch > 0) ? xs1[(ch - 1) * LPB + li] : A::zero();
+    const V right = (ch + 1 < nch) ? xs0[(ch + 1) * LPB + li] : A::zero();
     __syncthreads();
 
     V be[C];
+    V Ac = A::one(), d = A::zero();
     {
         V prev = left;
 #pragma unroll
@@ -286,55 +420,46 @@ __global__ void __launch_bounds__(1024) k_col(ColArgs a)
             const V nxt = (k + 1 < C) ? u[k + 1] : right;
             const V r = cn_rhs<T, CPLX>(prev, u[k], nxt, sig);
             prev = u[k];
-            const TabEntry e = a.tab[i0 + k];
-            be[k] = A::mul(A::coef(e.mr, e.mi), r);
+            const V al = tab_alpha<T, CPLX>(tb, i0 + k);
+            be[k] = A::mul(tab_m<T, CPLX>(tb, i0 + k), r);
+            d = A::fma(al, d, be[k]);
+            Ac = A::mul(al, Ac);
         }
     }
-
-    // forward
-    V Ac = A::one(), d = A::zero();
-#pragma unroll
-    for (int k = 0; k < C; ++k) {
-        const TabEntry e = a.tab[i0 + k];
-        const V al = A::coef(e.ar, e.ai);
-        d = A::fma(al, d, be[k]);
-        Ac = A::mul(al, Ac);
-    }
-    xs0[w * 64 + lane] = Ac;
-    xs1[w * 64 + lane] = d;
+    xs0[ch * LPB + li] = Ac;
+    xs1[ch * LPB + li] = d;
     __syncthreads();
     V din = A::zero();
-    for (int q = 0; q < w; ++q) din = A::fma(xs0[q * 64 + lane], din, xs1[q * 64 + lane]);
+    for (int q = qlo; q < ch; ++q) din = A::fma(xs0[q * LPB + li], din, xs1[q * LPB + li]);
     __syncthreads();
     d = din;
 #pragma unroll
     for (int k = 0; k < C; ++k) {
-        const TabEntry e = a.tab[i0 + k];
-        d = A::fma(A::coef(e.ar, e.ai), d, be[k]);
+        d = A::fma(tab_alpha<T, CPLX>(tb, i0 + k), d, be[k]);
         be[k] = d;
     }
 
     // backward
     V v = A::zero();
 #pragma unroll
-    for (int k = C - 1; k >= 0; --k) {
-        const TabEntry e = a.tab[i0 + k];
-        v = A::fma(A::coef(e.ar, e.ai), v, be[k]);
-    }
-    xs1[w * 64 + lane] = v;
+    for (int k = C - 1; k >= 0; --k) v = A::fma(tab_alpha<T, CPLX>(tb, i0 + k), v, be[k]);
+    xs1[ch * LPB + li] = v;
     __syncthreads();
     V vin = A::zero();
-    for (int q = a.W - 1; q > w; --q) vin = A::fma(xs0[q * 64 + lane], vin, xs1[q * 64 + lane]);
+    for (int q = qhi; q > ch; --q) vin = A::fma(xs0[q * LPB + li], vin, xs1[q * LPB + li]);
     v = vin;
     double nacc = 0.0;
 #pragma unroll
     for (int k = C - 1; k >= 0; --k) {
-        const TabEntry e = a.tab[i0 + k];
-        v = A::fma(A::coef(e.ar, e.ai), v, be[k]);
+        v = A::fma(tab_alpha<T, CPLX>(tb, i0 + k), v, be[k]);
+        be[k] = v;
+    }
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
         const int i = i0 + k;
         if (active && i < n) {
-            psi[base + (long long)i * st] = v;
-            if constexpr (LAST) nacc += A::norm2(v);
+            psi[base + (long long)i * st] = be[k];
+            if constexpr (LAST) nacc += A::norm2(be[k]);
         }
     }
     if constexpr (LAST) {
@@ -356,7 +481,7 @@ __global__ void __launch_bounds__(256) k_stream(ColArgs a)
     const long long base = (line % a.m1) * a.s1 + (line / a.m1) * a.s2;
     V *p = reinterpret_cast<V *>(a.psi) + base;
     const long long st = a.stride;
-    const int n = a.n;
+    const int n = a.lt.n;
     const V sig = A::coef(a.sig_re, a.sig_im);
     // forward: d_i stored in place of psi_i; the original u_{i-1}, u_i kept
     V um = A::zero(), u0 = p[0];
@@ -364,7 +489,7 @@ __global__ void __launch_bounds__(256) k_stream(ColArgs a)
     for (int i = 0; i < n; ++i) {
         const V up = (i + 1 < n) ? p[(long long)(i + 1) * st] : A::zero();
         const V r = cn_rhs<T, CPLX>(um, u0, up, sig);
-        const TabEntry e = a.tab[i];
+        const TabEntry e = a.lt.tab[i];
         d = A::fma(A::coef(e.ar, e.ai), d, A::mul(A::coef(e.mr, e.mi), r));
         p[(long long)i * st] = d;
         um = u0;
@@ -372,7 +497,7 @@ __global__ void __launch_bounds__(256) k_stream(ColArgs a)
     }
     V v = A::zero();
     for (int i = n - 1; i >= 0; --i) {
-        const TabEntry e = a.tab[i];
+        const TabEntry e = a.lt.tab[i];
         v = A::fma(A::coef(e.ar, e.ai), v, p[(long long)i * st]);
         p[(long long)i * st] = v;
     }
@@ -595,8 +720,11 @@ __global__ void __launch_bounds__(256) k_density_2d(const void *psi_, int nx, in
 template <class T, bool CPLX, int C>
 static void row_launch_c(bool last, const RowArgs &a, int grid, int block, size_t lds, hipStream_t st)
 {
-    if (last) hipLaunchKernelGGL((k_row<T, CPLX, C, true>), dim3(grid), dim3(block), lds, st, a);
-    else hipLaunchKernelGGL((k_row<T, CPLX, C, false>), dim3(grid), dim3(block), lds, st, a);
+    const bool mw = a.wpl > 1;
+    if (last && mw) hipLaunchKernelGGL((k_row<T, CPLX, C, true, true>), dim3(grid), dim3(block), lds, st, a);
+    else if (last) hipLaunchKernelGGL((k_row<T, CPLX, C, true, false>), dim3(grid), dim3(block), lds, st, a);
+    else if (mw) hipLaunchKernelGGL((k_row<T, CPLX, C, false, true>), dim3(grid), dim3(block), lds, st, a);
+    else hipLaunchKernelGGL((k_row<T, CPLX, C, false, false>), dim3(grid), dim3(block), lds, st, a);
 }
 
 template <class T, bool CPLX>

@@ -9,11 +9,25 @@
 
 namespace sscn {
 
+// Thomas coefficients of one axis as the line kernels read them.  Entries
+// at i >= i_conv are all equal to (alpha_inf, m_inf) (the FP64 recurrence
+// has reached its fixed point) and are not loaded; entries past the line end
+// are zero.  `depth` bounds how many preceding chunks feed a chunk's
+// incoming value: the neglected terms carry a product of at least that many
+// chunk factors |prod alpha| and are below 2^-64 (FP64) / 2^-35 (FP32) of
+// the largest term, i.e. below the rounding of the exact sum.
+struct LineTab {
+    const TabEntry *tab;
+    int32_t n;
+    int32_t i_conv;
+    double ac_re, ac_im, mc_re, mc_im;
+    int32_t depth;         // ROW: Kogge-Stone steps (0..6); COL: chunks folded
+};
+
 // x sweep with the pointwise substep fused into its load (ROW geometry).
 struct RowArgs {
     void *psi;
-    const TabEntry *tab;   // lane-major: entry (k, t) at [k * 64 * wpl + t]
-    int32_t n;             // line length n_x
+    LineTab lt;            // tab lane-major: entry (k, t) at [k * 64 * wpl + t]
     int32_t nlines;        // n_y * n_z
     int32_t wpl;           // waves per line (power of two, <= 16)
     int32_t lpb;           // lines per block
@@ -28,13 +42,13 @@ struct RowArgs {
 // apart.
 struct ColArgs {
     void *psi;
-    const TabEntry *tab;   // entry i at [i], zero past the line end
-    int32_t n;
+    LineTab lt;            // tab: entry i at [i]
     int32_t nlines;
     int64_t stride;
     int32_t m1;
     int64_t s1, s2;
-    int32_t W;             // waves per block = chunks per line (COL)
+    int32_t W;             // COL: waves per block
+    int32_t L;             // COL: lanes per line (chunks per line = W * L)
     double sig_re, sig_im;
     double *partial;
 };

@@ -22,7 +22,8 @@ struct AxisPlan {
     int C;        // points per thread
     int wpl;      // ROW: waves per line
     int lpb;      // ROW: lines per block
-    int W;        // COL: waves (chunks) per block
+    int W;        // COL: waves per block
+    int L;        // COL: lanes per line (chunks per line = W * L)
     int grid, block;
     size_t lds;
     size_t tab_off, tab_entries;
@@ -30,6 +31,11 @@ struct AxisPlan {
     int m1;
     int64_t s1, s2, stride;
     double sig_re, sig_im;
+    // table metadata (see LineTab): first index of the constant tail, the
+    // constant entry, and the scan / fold depth of the chunk geometry
+    int i_conv;
+    double ac_re, ac_im, mc_re, mc_im;
+    int depth;
 };
 
 struct Plan {
@@ -53,6 +59,9 @@ size_t elem_bytes(int elem);
 int validate(const sscn_problem *pb);
 int make_plan(const sscn_problem &pb, const TileOverride *ov, Plan &P);
 void build_table(const sscn_problem &pb, const Plan &P, int a, std::vector<TabEntry> &out);
+// FP64 Thomas coefficients m_i and alpha_i = s m_i of tridiag(-s, 1+2s, -s).
+void thomas_coefs(double s_re, double s_im, int n, std::vector<double> &m_re, std::vector<double> &m_im,
+                  std::vector<double> &a_re, std::vector<double> &a_im);
 
 // Tile hints registered through the ABI, keyed by (dim, n, mode, prec):
 // copies the hint for pb's shape into out and returns true if there is one.

@@ -195,14 +195,14 @@ def workspace_bytes(prob: Problem) -> int:
 
 def plan_info(prob: Problem):
     pc = prob.c()
-    info = (ctypes.c_int32 * 15)()
-    _check(lib().sscn_plan_info(ctypes.byref(pc), info, 15), "sscn_plan_info")
+    info = (ctypes.c_int32 * 24)()
+    _check(lib().sscn_plan_info(ctypes.byref(pc), info, 24), "sscn_plan_info")
     kinds = {0: "row", 1: "col", 2: "stream", -1: None}
     out = []
     for a in range(3):
-        k = info[5 * a]
-        out.append(None if k < 0 else dict(kind=kinds[k], chunk=info[5 * a + 1], waves=info[5 * a + 2],
-                                           grid=info[5 * a + 3], block=info[5 * a + 4]))
+        o = info[8 * a: 8 * a + 8]
+        out.append(None if o[0] < 0 else dict(kind=kinds[o[0]], chunk=o[1], waves=o[2], lanes=o[3],
+                                              grid=o[4], block=o[5], i_conv=o[6], depth=o[7]))
     return out
 
 

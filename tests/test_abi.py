@@ -90,7 +90,8 @@ def test_plan_geometries():
     p = Problem(3, (256, 256, 256), (0.1,) * 3, (1, 1.5, 2), 80.0, 2e-4, REAL, F64, 0)
     info = sscn.plan_info(p)
     assert info[0]["kind"] == "row" and info[0]["chunk"] == 4 and info[0]["waves"] == 1
-    assert info[1]["kind"] == "col" and info[1]["chunk"] * info[1]["waves"] >= 256
+    assert info[1]["kind"] == "col" and info[1]["chunk"] * info[1]["waves"] * info[1]["lanes"] >= 256
+    assert info[1]["chunk"] == 8 and info[1]["lanes"] == 2
     assert info[2]["kind"] == "col"
     # long x lines use several waves per line; too long falls back
     p = Problem(1, (5000, 1, 1), (0.1,), (1,), 1.0, 1e-3, IMAG, F64, 1)
@@ -115,3 +116,34 @@ def test_tile_hints_change_the_plan():
     finally:
         sscn.clear_tile_hints()
     assert sscn.plan_info(p)[1]["chunk"] == 4
+
+
+@pytest.mark.parametrize("sigma", [0.005, 0.025, 0.3, 10.0])
+@pytest.mark.parametrize("mode", [IMAG, REAL])
+def test_scan_depth_bounds_neglected_terms(sigma, mode):
+    """The scan depth chosen by the plan is the smallest that keeps every
+    neglected term below 2^-64 of the largest (FP64): a term from k chunks
+    back carries a product of k chunk factors prod |alpha|."""
+    import numpy as np
+    n = 256
+    dx = 0.1
+    dt = sigma * 4 * dx * dx
+    p = Problem(2, (n, n, 1), (dx, dx), (1, 1), 1.0, dt, mode, F64, 1 if mode == IMAG else 0)
+    info = sscn.plan_info(p)
+    s = sigma if mode == IMAG else 1j * sigma
+    m = np.zeros(n, dtype=complex)
+    m[0] = 1 / (1 + 2 * s)
+    for i in range(1, n):
+        m[i] = 1 / (1 + 2 * s - s * s * m[i - 1])
+    al = np.abs(s * m)
+    for ax in (0, 1):
+        C = info[ax]["chunk"]
+        amax = max(np.prod(al[c:c + C]) for c in range(0, n - C + 1, C))
+        covered = (2 ** info[ax]["depth"]) if info[ax]["kind"] == "row" else info[ax]["depth"]
+        nchunks = -(-n // C)
+        if covered < nchunks - 1:
+            assert amax ** covered <= 2.0 ** -64
+            assert amax ** (covered // 2 if info[ax]["kind"] == "row" else covered - 1) > 2.0 ** -64 or covered == 1
+        # the tail the kernels read as one constant is constant to round-off
+        ic = info[ax]["i_conv"]
+        assert np.all(np.abs(m[ic:] - m[-1]) <= 4e-16 * abs(m[-1]))

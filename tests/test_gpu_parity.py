@@ -220,3 +220,78 @@ def test_nonfinite_state_reported():
     s = sscn.Solver(p, psi0)
     ob = s.observe()
     assert ob.status == sscn.E_NONFINITE
+
+
+@pytest.mark.parametrize("mode", [IMAG, REAL])
+@pytest.mark.parametrize("sigma", [0.3, 10.0, 300.0])
+def test_large_sigma_full_depth_scans(mode, sigma):
+    """Large CN coefficients make |alpha| close to 1: the scans must then
+    reach across many chunks (up to the full line)."""
+    dx = (0.2, 0.25, 0.3)
+    dt = sigma * 4 * 0.2 * 0.2
+    # g = 0: with steps this long the nonlinear phase would amplify any
+    # rounding difference step after step; the linear problem isolates the
+    # line solves
+    p = Problem(3, (130, 40, 24), dx, (1.0, 1.5, 2.0), 0.0, dt, mode, F64, 1 if mode == IMAG else 0)
+    got, ref, ob, orf = run_both(p, 5, seed=8)
+    # the CN matrix has condition number ~1 + 4 sigma, which scales the
+    # rounding differences between the scan and the oracle's Thomas order
+    assert rel_l2(got, ref) <= max(1e-12, 1e-13 * (1 + 4 * sigma))
+
+
+def _golden_c1():
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c1_oracle_1000.json")
+    with open(path) as f:
+        return json.load(f)
+
+
+def _c1_run(prec, steps=1000):
+    p = c1_problem(prec)
+    psi0 = inputs.thomas_fermi(3, p.n, p.dx, p.omega, 100.0, phase_sigma=0.05, seed=1)
+    s = sscn.Solver(p, psi0)
+    s.step(steps)
+    ob = s.observe()
+    flat = s.state().reshape(-1)
+    s.close()
+    return ob, flat
+
+
+def test_c1_1000_steps_matches_stored_oracle():
+    """256^3 complex128, 1000 steps, bench launch configuration, against the
+    stored oracle run (tests/golden/make_c1_reference.py): relative L2 over
+    4096 seeded sample points <= 1e-10, observables <= 1e-10 relative."""
+    ref = _golden_c1()
+    ob, flat = _c1_run(F64)
+    idx = np.asarray(ref["sample_index"])
+    exp = np.asarray(ref["sample_re"]) + 1j * np.asarray(ref["sample_im"])
+    got = flat[idx].astype(np.complex128)
+    err = np.linalg.norm(got - exp) / np.linalg.norm(exp)
+    print(f"C1 FP64 sampled rel-L2 {err:.3e}", flush=True)
+    assert err <= 1e-10
+    assert abs(np.sum(np.abs(flat) ** 2) / ref["l2sq"] - 1) <= 1e-12
+    for f, g in (("norm", "norm"), ("mu", "mu"), ("energy", "energy"), ("ekin", "K"), ("epot", "P"),
+                 ("eint", "I")):
+        assert abs(getattr(ob, f) - ref["obs1"][g]) <= 1e-10 * abs(ref["obs1"][g]), f
+
+
+def test_c2_fp32_error_against_stored_oracle():
+    """complex64 storage, FP32 sweeps, FP64 tables and reductions, 1000 steps:
+    the stated errors against the FP64 oracle; gate |d mu| <= 1e-5."""
+    ref = _golden_c1()
+    ob, flat = _c1_run(F32)
+    idx = np.asarray(ref["sample_index"])
+    exp = np.asarray(ref["sample_re"]) + 1j * np.asarray(ref["sample_im"])
+    got = flat[idx].astype(np.complex128)
+    err = np.linalg.norm(got - exp) / np.linalg.norm(exp)
+    o1 = ref["obs1"]
+    dmu = abs(ob.mu - o1["mu"])
+    dE = abs(ob.energy - o1["energy"]) / abs(o1["energy"])
+    dN = abs(ob.norm - o1["norm"])
+    print(f"C2 FP32: psi sampled rel-L2 {err:.3e}  |d mu| {dmu:.3e}  rel dE {dE:.3e}  |d norm| {dN:.3e}",
+          flush=True)
+    assert dmu <= 1e-5
+    assert err <= 1e-3
+    assert dE <= 1e-5
+    assert dN <= 1e-5
