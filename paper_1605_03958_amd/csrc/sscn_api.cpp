@@ -127,6 +127,9 @@ static void table_meta(AxisPlan &X, bool fp32)
     }
 }
 
+// Bytes of one staged table entry: (alpha, m) in FP64, hi/lo pairs in FP32.
+static size_t ltab_bytes(const Plan &P) { return (P.elem == 1 || P.elem == 3) ? 4 * P.S : 2 * P.S; }
+
 // Largest chunk length per thread kept in registers, by element size.
 static int cmax_row(size_t S) { return S >= 16 ? 8 : (S >= 8 ? 16 : 32); }
 static int cmax_col(size_t S) { return S >= 16 ? 16 : (S >= 8 ? 32 : 64); }
@@ -171,7 +174,7 @@ int make_plan(const sscn_problem &pb, const TileOverride *ov, Plan &P)
                 X.grid = (int)std::min<int64_t>(ceil_div(X.nlines, X.lpb), 4096);
                 // single-wave lines stage their table in LDS; multi-wave
                 // lines exchange 4 values per wave
-                X.lds = (wpl == 1) ? (size_t)c * 64 * 2 * P.S : (size_t)X.lpb * wpl * 4 * P.S;
+                X.lds = (wpl == 1) ? (size_t)c * 64 * ltab_bytes(P) : (size_t)X.lpb * wpl * 4 * P.S;
                 X.tab_entries = (size_t)c * 64 * wpl;
             }
         } else {
@@ -179,21 +182,26 @@ int make_plan(const sscn_problem &pb, const TileOverride *ov, Plan &P)
             X.s1 = 1;
             X.s2 = (a == 1) ? nx * ny : nx;
             X.stride = (a == 1) ? nx : nx * ny;
-            // about 32 registers of state per thread: C points, W*L >= n/C
-            int c = std::max(1, (int)(128 / P.S));
+            // 4 points per thread (registers for two 1024-thread blocks per
+            // CU), more only when 16 waves x Lmax lanes cannot cover the
+            // line; Lmax keeps a wave's row segment (64/L lines x S bytes)
+            // at 128 bytes or more
+            const int lmax = std::max(1, std::min(4, (int)(P.S / 2)));
+            int c = 4;
+            while (c < 64 && ceil_div(n, c) > 16 * lmax) c *= 2;
             c = std::min<int64_t>(c, pow2ceil(ceil_div(n, 16)));
             if (ov && ov->col_c[a] > 0) c = ov->col_c[a];
             const int64_t K = ceil_div(n, c);           // chunks per line
             const int L = pow2ceil(ceil_div(K, 16));    // lanes per line
             const int64_t W = ceil_div(K, L);
-            if (c <= cmax_col(P.S) && L <= 4) {
+            if (c <= cmax_col(P.S) && L <= 8) {
                 X.kind = K_COL;
                 X.C = c;
                 X.W = (int)W;
                 X.L = L;
                 X.block = 64 * (int)W;
                 X.grid = (int)ceil_div(X.nlines, 64 / L);
-                X.lds = (size_t)W * L * c * 2 * P.S + (size_t)2 * W * 64 * P.S;
+                X.lds = (size_t)W * L * c * ltab_bytes(P) + (size_t)2 * W * 64 * P.S;
                 X.tab_entries = (size_t)W * L * c;
             }
         }

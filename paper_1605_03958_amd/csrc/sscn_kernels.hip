@@ -115,50 +115,74 @@ __device__ __forceinline__ T coord(int i, double cen, double dx)
     return T((double(i) - cen) * dx);
 }
 
-// A table entry in the kernel's working precision (FP64 tables are rounded
-// to FP32 here for the FP32 forms).
-template <class V>
-struct LTab {
+// A Thomas table entry as the sweeps use it.  FP64: (alpha, m).  FP32: each
+// FP64 coefficient c is kept as the unevaluated pair hi + lo with hi = fl32(c)
+// and lo = fl32(c - hi), and every product c x is formed as hi x + lo x in
+// FP32.  The coefficients then carry ~48 bits, so the FP32 operator stays
+// the FP64 one up to the rounding of the data arithmetic: rounding the
+// coefficients once would perturb every line of every step identically and
+// the real-time norm would drift coherently (about 1e-4 over 1000 steps).
+template <class T, bool CPLX>
+struct LTab;
+
+template <bool CPLX>
+struct LTab<double, CPLX> {
+    using A = Alg<double, CPLX>;
+    using V = typename A::V;
     V al, m;
+    __device__ __forceinline__ static LTab make(const TabEntry &e)
+    {
+        return LTab{A::coef(e.ar, e.ai), A::coef(e.mr, e.mi)};
+    }
+    __device__ __forceinline__ V afma(V x, V y) const { return A::fma(al, x, y); }   // alpha x + y
+    __device__ __forceinline__ V mmul(V r) const { return A::mul(m, r); }            // m r
+    __device__ __forceinline__ V alpha() const { return al; }
+};
+
+template <bool CPLX>
+struct LTab<float, CPLX> {
+    using A = Alg<float, CPLX>;
+    using V = typename A::V;
+    V al, al_lo, m, m_lo;
+    __device__ __forceinline__ static V lo_of(double re, double im, V hi)
+    {
+        if constexpr (CPLX) return V{float(re - double(hi.re)), float(im - double(hi.im))};
+        else return float(re - double(hi));
+    }
+    __device__ __forceinline__ static LTab make(const TabEntry &e)
+    {
+        LTab t;
+        t.al = A::coef(e.ar, e.ai);
+        t.m = A::coef(e.mr, e.mi);
+        t.al_lo = lo_of(e.ar, e.ai, t.al);
+        t.m_lo = lo_of(e.mr, e.mi, t.m);
+        return t;
+    }
+    __device__ __forceinline__ V afma(V x, V y) const { return A::fma(al, x, A::fma(al_lo, x, y)); }
+    __device__ __forceinline__ V mmul(V r) const { return A::fma(m, r, A::mul(m_lo, r)); }
+    __device__ __forceinline__ V alpha() const { return al; }
 };
 
 // Copy a kernel's table slice (cnt entries, zero-padded past the line end
-// by the host) into LDS in the working precision; the caller synchronises
-// before reading it.
+// by the host) into LDS in the working representation; the caller
+// synchronises before reading it.
 template <class T, bool CPLX>
-__device__ __forceinline__ void stage_table(const TabEntry *__restrict__ src,
-                                            LTab<typename Alg<T, CPLX>::V> *dst, int cnt)
+__device__ __forceinline__ void stage_table(const TabEntry *__restrict__ src, LTab<T, CPLX> *dst, int cnt)
 {
-    using A = Alg<T, CPLX>;
-    for (int q = threadIdx.x; q < cnt; q += blockDim.x) {
-        const TabEntry e = src[q];
-        dst[q] = LTab<typename A::V>{A::coef(e.ar, e.ai), A::coef(e.mr, e.mi)};
-    }
+    for (int q = threadIdx.x; q < cnt; q += blockDim.x) dst[q] = LTab<T, CPLX>::make(src[q]);
+}
+
+// Table entry q from LDS (staged) or from the FP64 table in global memory.
+template <class T, bool CPLX>
+__device__ __forceinline__ LTab<T, CPLX> tab_at(const LTab<T, CPLX> *tb, int q)
+{
+    return tb[q];
 }
 
 template <class T, bool CPLX>
-__device__ __forceinline__ typename Alg<T, CPLX>::V tab_alpha(const LTab<typename Alg<T, CPLX>::V> *tb, int q)
+__device__ __forceinline__ LTab<T, CPLX> tab_at(const TabEntry *tb, int q)
 {
-    return tb[q].al;
-}
-
-template <class T, bool CPLX>
-__device__ __forceinline__ typename Alg<T, CPLX>::V tab_m(const LTab<typename Alg<T, CPLX>::V> *tb, int q)
-{
-    return tb[q].m;
-}
-
-// Same accessors on the FP64 table in global memory (multi-wave x lines).
-template <class T, bool CPLX>
-__device__ __forceinline__ typename Alg<T, CPLX>::V tab_alpha(const TabEntry *tb, int q)
-{
-    return Alg<T, CPLX>::coef(tb[q].ar, tb[q].ai);
-}
-
-template <class T, bool CPLX>
-__device__ __forceinline__ typename Alg<T, CPLX>::V tab_m(const TabEntry *tb, int q)
-{
-    return Alg<T, CPLX>::coef(tb[q].mr, tb[q].mi);
+    return LTab<T, CPLX>::make(tb[q]);
 }
 
 // ===========================================================================
@@ -181,10 +205,10 @@ __global__ void __launch_bounds__(MW ? 1024 : 256) k_row(RowArgs a)
     const int t = tid - lb * G;
     const int lane = tid & 63;
     const int wl = t >> 6;
-    LTab<V> *tl = reinterpret_cast<LTab<V> *>(lds_raw);
+    LTab<T, CPLX> *tl = reinterpret_cast<LTab<T, CPLX> *>(lds_raw);
     const auto tb = [&]() {
         if constexpr (MW) return a.lt.tab;
-        else return static_cast<const LTab<V> *>(tl);
+        else return static_cast<const LTab<T, CPLX> *>(tl);
     }();
     V *xs = reinterpret_cast<V *>(lds_raw) + lb * a.wpl * 4;
 
@@ -208,15 +232,6 @@ __global__ void __launch_bounds__(MW ? 1024 : 256) k_row(RowArgs a)
         const bool active = line < a.nlines;
         const long long base = line * (long long)n;
 
-        // ---- load + pointwise substep ----
-        T vyz = T(0);
-        if (active) {
-            const int j = (int)(line % a.pp.n[1]);
-            const int k = (int)(line / a.pp.n[1]);
-            const T y = coord<T>(j, a.pp.cen[1], a.pp.dx[1]);
-            const T z = coord<T>(k, a.pp.cen[2], a.pp.dx[2]);
-            vyz = T(a.pp.w2h[1]) * y * y + T(a.pp.w2h[2]) * z * z;
-        }
         V u[C];
 #pragma unroll
         for (int k = 0; k < C; ++k) {
@@ -224,6 +239,16 @@ __global__ void __launch_bounds__(MW ? 1024 : 256) k_row(RowArgs a)
             V v = A::zero();
             if (active && i < n) v = psi[base + i];
             u[k] = v;
+        }
+
+        // ---- pointwise substep ----
+        T vyz = T(0);
+        if (active) {
+            const int j = (int)(line % a.pp.n[1]);
+            const int k = (int)(line / a.pp.n[1]);
+            const T y = coord<T>(j, a.pp.cen[1], a.pp.dx[1]);
+            const T z = coord<T>(k, a.pp.cen[2], a.pp.dx[2]);
+            vyz = T(a.pp.w2h[1]) * y * y + T(a.pp.w2h[2]) * z * z;
         }
 #pragma unroll
         for (int k = 0; k < C; ++k) {
@@ -256,10 +281,10 @@ __global__ void __launch_bounds__(MW ? 1024 : 256) k_row(RowArgs a)
                 const V nxt = (k + 1 < C) ? u[k + 1] : right;
                 const V r = cn_rhs<T, CPLX>(prev, u[k], nxt, sig);
                 prev = u[k];
-                const V al = tab_alpha<T, CPLX>(tb, k * G + t);
-                be[k] = A::mul(tab_m<T, CPLX>(tb, k * G + t), r);
-                d = A::fma(al, d, be[k]);
-                Ac = A::mul(al, Ac);
+                const LTab<T, CPLX> e = tab_at<T, CPLX>(tb, k * G + t);
+                be[k] = e.mmul(r);
+                d = e.afma(d, be[k]);
+                Ac = A::mul(e.alpha(), Ac);
             }
         }
 
@@ -297,14 +322,14 @@ __global__ void __launch_bounds__(MW ? 1024 : 256) k_row(RowArgs a)
         d = din;
 #pragma unroll
         for (int k = 0; k < C; ++k) {
-            d = A::fma(tab_alpha<T, CPLX>(tb, k * G + t), d, be[k]);
+            d = tab_at<T, CPLX>(tb, k * G + t).afma(d, be[k]);
             be[k] = d;
         }
 
         // ---- backward ----
         V v = A::zero();
 #pragma unroll
-        for (int k = C - 1; k >= 0; --k) v = A::fma(tab_alpha<T, CPLX>(tb, k * G + t), v, be[k]);
+        for (int k = C - 1; k >= 0; --k) v = tab_at<T, CPLX>(tb, k * G + t).afma(v, be[k]);
         V vin;
         {
             V PA = Ac, PB = v;
@@ -338,7 +363,7 @@ __global__ void __launch_bounds__(MW ? 1024 : 256) k_row(RowArgs a)
         v = vin;
 #pragma unroll
         for (int k = C - 1; k >= 0; --k) {
-            v = A::fma(tab_alpha<T, CPLX>(tb, k * G + t), v, be[k]);
+            v = tab_at<T, CPLX>(tb, k * G + t).afma(v, be[k]);
             be[k] = v;
         }
 
@@ -374,7 +399,7 @@ __global__ void __launch_bounds__(1024) k_col(ColArgs a)
     const int L = a.L;
     const int LPB = 64 / L;
     const int nch = a.W * L;
-    LTab<V> *tb = reinterpret_cast<LTab<V> *>(lds_raw);
+    LTab<T, CPLX> *tb = reinterpret_cast<LTab<T, CPLX> *>(lds_raw);
     V *xs0 = reinterpret_cast<V *>(tb + nch * C);
     V *xs1 = xs0 + nch * LPB;
 
@@ -420,10 +445,10 @@ __global__ void __launch_bounds__(1024) k_col(ColArgs a)
             const V nxt = (k + 1 < C) ? u[k + 1] : right;
             const V r = cn_rhs<T, CPLX>(prev, u[k], nxt, sig);
             prev = u[k];
-            const V al = tab_alpha<T, CPLX>(tb, i0 + k);
-            be[k] = A::mul(tab_m<T, CPLX>(tb, i0 + k), r);
-            d = A::fma(al, d, be[k]);
-            Ac = A::mul(al, Ac);
+            const LTab<T, CPLX> e = tab_at<T, CPLX>(tb, i0 + k);
+            be[k] = e.mmul(r);
+            d = e.afma(d, be[k]);
+            Ac = A::mul(e.alpha(), Ac);
         }
     }
     xs0[ch * LPB + li] = Ac;
@@ -435,14 +460,14 @@ __global__ void __launch_bounds__(1024) k_col(ColArgs a)
     d = din;
 #pragma unroll
     for (int k = 0; k < C; ++k) {
-        d = A::fma(tab_alpha<T, CPLX>(tb, i0 + k), d, be[k]);
+        d = tab_at<T, CPLX>(tb, i0 + k).afma(d, be[k]);
         be[k] = d;
     }
 
     // backward
     V v = A::zero();
 #pragma unroll
-    for (int k = C - 1; k >= 0; --k) v = A::fma(tab_alpha<T, CPLX>(tb, i0 + k), v, be[k]);
+    for (int k = C - 1; k >= 0; --k) v = tab_at<T, CPLX>(tb, i0 + k).afma(v, be[k]);
     xs1[ch * LPB + li] = v;
     __syncthreads();
     V vin = A::zero();
@@ -451,7 +476,7 @@ __global__ void __launch_bounds__(1024) k_col(ColArgs a)
     double nacc = 0.0;
 #pragma unroll
     for (int k = C - 1; k >= 0; --k) {
-        v = A::fma(tab_alpha<T, CPLX>(tb, i0 + k), v, be[k]);
+        v = tab_at<T, CPLX>(tb, i0 + k).afma(v, be[k]);
         be[k] = v;
     }
 #pragma unroll
@@ -489,16 +514,15 @@ __global__ void __launch_bounds__(256) k_stream(ColArgs a)
     for (int i = 0; i < n; ++i) {
         const V up = (i + 1 < n) ? p[(long long)(i + 1) * st] : A::zero();
         const V r = cn_rhs<T, CPLX>(um, u0, up, sig);
-        const TabEntry e = a.lt.tab[i];
-        d = A::fma(A::coef(e.ar, e.ai), d, A::mul(A::coef(e.mr, e.mi), r));
+        const LTab<T, CPLX> e = tab_at<T, CPLX>(a.lt.tab, i);
+        d = e.afma(d, e.mmul(r));
         p[(long long)i * st] = d;
         um = u0;
         u0 = up;
     }
     V v = A::zero();
     for (int i = n - 1; i >= 0; --i) {
-        const TabEntry e = a.lt.tab[i];
-        v = A::fma(A::coef(e.ar, e.ai), v, p[(long long)i * st]);
+        v = tab_at<T, CPLX>(a.lt.tab, i).afma(v, p[(long long)i * st]);
         p[(long long)i * st] = v;
     }
 }

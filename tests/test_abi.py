@@ -91,7 +91,7 @@ def test_plan_geometries():
     info = sscn.plan_info(p)
     assert info[0]["kind"] == "row" and info[0]["chunk"] == 4 and info[0]["waves"] == 1
     assert info[1]["kind"] == "col" and info[1]["chunk"] * info[1]["waves"] * info[1]["lanes"] >= 256
-    assert info[1]["chunk"] == 8 and info[1]["lanes"] == 2
+    assert info[1]["chunk"] == 4 and info[1]["lanes"] == 4
     assert info[2]["kind"] == "col"
     # long x lines use several waves per line; too long falls back
     p = Problem(1, (5000, 1, 1), (0.1,), (1,), 1.0, 1e-3, IMAG, F64, 1)
@@ -101,6 +101,8 @@ def test_plan_geometries():
     p = Problem(1, (300000, 1, 1), (0.1,), (1,), 1.0, 1e-3, IMAG, F64, 1)
     assert sscn.plan_info(p)[0]["kind"] == "stream"
     p = Problem(2, (64, 700, 1), (0.1, 0.1), (1, 1), 1.0, 1e-3, REAL, F64, 0)
+    assert sscn.plan_info(p)[1]["kind"] == "col" and sscn.plan_info(p)[1]["lanes"] == 4
+    p = Problem(2, (64, 5000, 1), (0.1, 0.1), (1, 1), 1.0, 1e-3, REAL, F64, 0)
     assert sscn.plan_info(p)[1]["kind"] == "stream"
 
 
@@ -110,7 +112,7 @@ def test_tile_hints_change_the_plan():
         sscn.set_tile_hint(p, (2, 8, 16))
         info = sscn.plan_info(p)
         assert info[0]["chunk"] == 2 and info[1]["chunk"] == 8 and info[2]["chunk"] == 16
-        assert info[1]["waves"] == 8 and info[2]["waves"] == 4
+        assert info[1]["waves"] * info[1]["lanes"] == 8 and info[2]["waves"] * info[2]["lanes"] == 4
         with pytest.raises(sscn.SSCNError):
             sscn.set_tile_hint(p, (3, 0, 0))
     finally:

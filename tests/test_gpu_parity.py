@@ -78,7 +78,7 @@ def test_fp64_matches_oracle_small(dim, n, dx, omega, mode):
         assert abs(ob.msq[a] - orf.msq[a]) <= 1e-11 * max(1.0, orf.msq[a])
 
 
-@pytest.mark.parametrize("dim,n", [(2, (64, 600, 1)), (3, (20, 600, 40)), (1, (200000, 1, 1))])
+@pytest.mark.parametrize("dim,n", [(2, (64, 5000, 1)), (3, (16, 5000, 8)), (1, (200000, 1, 1))])
 @pytest.mark.parametrize("mode", [IMAG, REAL])
 def test_fp64_fallback_lines_match_oracle(dim, n, mode):
     """Lines too long for the register-resident kernels take the exact
