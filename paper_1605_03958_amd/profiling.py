@@ -1,0 +1,153 @@
+"""Summarise rocprofv3 runs of bench.py into profiles/.
+
+Input: three rocprofv3 output directories of the same bench.py command
+  trace  --kernel-trace --stats   (kernel_stats.csv, kernel_trace.csv)
+  fetch  --pmc FETCH_SIZE         (counter_collection.csv)
+  write  --pmc WRITE_SIZE         (counter_collection.csv)
+Output: profiles/<name>.md (durations, counters, calibration) and an entry
+in profiles/pmc_traffic.json that bench.py reads as roofline.traffic.
+
+HBM traffic per launch = FETCH_SIZE * f_fetch + WRITE_SIZE * f_write, where
+f_* = (bytes a plain device copy of known size must move) / (what the same
+counter reads for that copy kernel) -- the copy is bench.py's torch copy of
+one state's worth of bytes.  Kernel classes follow the launch order of a
+step: the x sweep (k_row), then the y and z sweeps (k_col, in that order).
+
+Usage:
+  python -m paper_1605_03958_amd.profiling --trace DIR --fetch DIR --write DIR \
+      --workload c1_256cube_c128 --state-bytes 268435456 --name sweeps_c1_256cube_c128 \
+      --command "<the rocprofv3 command lines>"
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+from collections import defaultdict
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+COPY_KERNEL = "__amd_rocclr_copyBuffer"
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for name in ("sscn_dev.hpp", "sscn_kernels.hip"):
+        with open(os.path.join(ROOT, "paper_1605_03958_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def _find(d: str, suffix: str) -> str:
+    hits = sorted(glob.glob(os.path.join(d, "**", f"*{suffix}"), recursive=True))
+    if not hits:
+        raise FileNotFoundError(f"no *{suffix} under {d}")
+    return hits[0]
+
+
+def classify(rows):
+    """Assign each sweep dispatch (in dispatch order) to x / y / z."""
+    out = []
+    after_row = 0
+    for r in sorted(rows, key=lambda r: int(r["Dispatch_Id"])):
+        name = r["Kernel_Name"]
+        if "k_row" in name:
+            cls = "x_sweep_pointwise"
+            after_row = 0
+        elif "k_col" in name:
+            after_row += 1
+            cls = "y_sweep" if after_row == 1 else "z_sweep_norm"
+        elif name.startswith(COPY_KERNEL):
+            cls = "copy"
+        else:
+            cls = None
+        out.append((cls, r))
+    return out
+
+
+def counter_means(path: str, counter: str):
+    rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter]
+    acc = defaultdict(list)
+    for cls, r in classify(rows):
+        if cls:
+            acc[cls].append(float(r["Counter_Value"]))
+    return {k: sum(v) / len(v) for k, v in acc.items()}, {k: len(v) for k, v in acc.items()}
+
+
+def trace_means(path: str):
+    rows = list(csv.DictReader(open(path)))
+    for r in rows:
+        r.setdefault("Dispatch_Id", r.get("Dispatch_Id", "0"))
+    acc = defaultdict(list)
+    for cls, r in classify(rows):
+        if cls:
+            acc[cls].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    return {k: sum(v) / len(v) for k, v in acc.items()}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--trace", required=True)
+    ap.add_argument("--fetch", required=True)
+    ap.add_argument("--write", required=True)
+    ap.add_argument("--workload", required=True)
+    ap.add_argument("--state-bytes", type=int, required=True)
+    ap.add_argument("--name", required=True)
+    ap.add_argument("--command", default="")
+    args = ap.parse_args()
+
+    stats = list(csv.DictReader(open(_find(args.trace, "kernel_stats.csv"))))
+    dur = trace_means(_find(args.trace, "kernel_trace.csv"))
+    fetch, nf = counter_means(_find(args.fetch, "counter_collection.csv"), "FETCH_SIZE")
+    write, nw = counter_means(_find(args.write, "counter_collection.csv"), "WRITE_SIZE")
+    kib = 1024.0
+    S = args.state_bytes
+    f_fetch = S / (fetch["copy"] * kib)
+    f_write = S / (write["copy"] * kib)
+    alg = 2 * S
+    lines = [f"# rocprofv3 summary: {args.name}", "",
+             f"Workload: `{args.workload}`; state {S} bytes; algorithmic bytes per sweep launch "
+             f"(one read + one write of the state) {alg}.", "",
+             "Commands (run from the repository root on the GPU box):", "", "```",
+             args.command.strip(), "```", "",
+             "## Kernel statistics (--kernel-trace --stats)", "",
+             "| kernel | calls | average ns | share % |", "|---|---|---|---|"]
+    for r in stats:
+        lines.append(f"| `{r['Name'][:90]}` | {r['Calls']} | {float(r['AverageNs']):.0f} | "
+                     f"{float(r['Percentage']):.2f} |")
+    lines += ["", "## Per class (dispatch order within a step)", "",
+              "| class | mean duration us | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM bytes / launch "
+              "(calibrated) | / algorithmic | achieved GB/s (algorithmic) |", "|---|---|---|---|---|---|---|"]
+    rec = {}
+    for cls in ("x_sweep_pointwise", "y_sweep", "z_sweep_norm", "copy"):
+        if cls not in fetch:
+            continue
+        tb = fetch[cls] * kib * f_fetch + write[cls] * kib * f_write
+        d = dur.get(cls, float("nan"))
+        lines.append(f"| {cls} | {d / 1e3:.1f} | {fetch[cls]:.0f} | {write[cls]:.0f} | {tb:.4g} | "
+                     f"{tb / alg:.3f} | {alg / d:.0f} |")
+        if cls != "copy":
+            rec[cls] = {"bytes_per_launch": tb, "alg_bytes_per_launch": alg, "mean_ns": d,
+                        "source_hash": source_hash()}
+    lines += ["", f"Calibration: the copy kernel `{COPY_KERNEL}` moves {S} bytes each way; "
+              f"FETCH_SIZE reads {fetch['copy']:.0f} KiB (factor {f_fetch:.4f}), WRITE_SIZE "
+              f"{write['copy']:.0f} KiB (factor {f_write:.4f}).", "",
+              f"Kernel source hash: `{source_hash()}`.", ""]
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    with open(os.path.join(ROOT, "profiles", f"{args.name}.md"), "w") as f:
+        f.write("\n".join(lines))
+    jp = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    allrec = {}
+    if os.path.exists(jp):
+        with open(jp) as f:
+            allrec = json.load(f)
+    allrec[args.workload] = rec
+    with open(jp, "w") as f:
+        json.dump(allrec, f, indent=1)
+    print("\n".join(lines))
+
+
+if __name__ == "__main__":
+    main()
