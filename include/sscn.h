@@ -54,6 +54,7 @@ extern "C" {
 /* status codes */
 #define SSCN_OK              0
 #define SSCN_NOT_CONVERGED   1   /* informational: step cap reached first */
+#define SSCN_BUSY            2   /* informational: results not ready yet (non-blocking poll) */
 #define SSCN_E_INVALID      -1   /* bad argument or problem */
 #define SSCN_E_HIP          -2   /* a HIP runtime call failed */
 #define SSCN_E_NONFINITE    -3   /* norm or chemical potential is NaN/Inf */
@@ -184,6 +185,82 @@ int sscn_destroy(sscn_solver *s);
  * (2D, dim == 3 only).  Enqueued on the stream; FP64. */
 int sscn_density_1d(sscn_solver *s, int keep, void *d_out);
 int sscn_density_2d(sscn_solver *s, int drop, void *d_out);
+
+/* ------------------------------------------------------------------------
+ * Batched persistent stepping (many uneven instances, FP32 forms).
+ *
+ * A batch advances every running instance by one SSCN step per launch of a
+ * persistent kernel whose blocks take tiles of all instances from a work
+ * list in dependency order (x tiles, then y, z, observation tiles, then one
+ * finalisation per instance); on a non-null stream a call's launches are
+ * captured once into a hipGraph and replayed.  Every instance uses the same
+ * method as sscn_step with prec = SSCN_F32 and renorm_every = 1 (imaginary
+ * time) and is observed every observe_every steps; a ground-state instance
+ * stops at the first observation with |mu - mu_prev| < mu_tol (mu_tol > 0),
+ * any instance stops after max_steps.  An instance's tile shapes depend only
+ * on its own shape and all its reductions have fixed order, so its results
+ * do not depend on the other instances.  The caller owns every device
+ * buffer: the control block, and each instance's state and workspace.
+ * ------------------------------------------------------------------------ */
+typedef struct sscn_batch sscn_batch;
+
+#define SSCN_SLOT_EMPTY     0
+#define SSCN_SLOT_RUNNING   1
+#define SSCN_SLOT_CONVERGED 2   /* |d mu| < mu_tol reached */
+#define SSCN_SLOT_DONE      3   /* max_steps taken */
+#define SSCN_SLOT_NONFINITE 4   /* norm or mu became NaN/Inf; the instance stopped */
+
+typedef struct {
+    int32_t  state;         /* SSCN_SLOT_* */
+    int32_t  pad_;
+    int64_t  steps;         /* steps taken since admission */
+    double   last_norm;     /* dV sum |psi|^2 after the last step, before renormalisation */
+    sscn_obs obs;           /* observables at the last observation step (obs.step) */
+} sscn_batch_slot;
+
+/* Bytes of the control block for max_slots instances and a work list of up
+ * to max_items tiles per step.  SSCN_E_INVALID for out-of-range sizes. */
+int sscn_batch_ctl_bytes(int32_t max_slots, int64_t max_items, size_t *bytes);
+
+/* Bytes of one instance's workspace in a batch (FP64 tables and partials).
+ * SSCN_E_UNSUPPORTED unless prec == SSCN_F32 and the lines fit the
+ * persistent kernel's tiles (x lines up to 16384 points in float and complex;
+ * y and z lines up to 1024 (complex) / 2048 (float) points). */
+int sscn_batch_workspace_bytes(const sscn_problem *pb, size_t *bytes);
+
+/* Create a batch over a caller-owned, 256-byte aligned device control block
+ * of at least sscn_batch_ctl_bytes bytes, on hip_stream.  Clears the block.
+ * Allocates pinned host mirrors only. */
+int sscn_batch_create(int32_t max_slots, int64_t max_items, void *d_ctl, size_t ctl_bytes, void *hip_stream,
+                      sscn_batch **out);
+
+/* Admit an instance into an empty slot: d_psi holds its initial state (layout
+ * and dtype as for sscn_create), d_ws is its workspace.  Uploads its FP64
+ * tables and waits for the copy.  SSCN_E_NOSPACE if the slot is busy or the
+ * work list would exceed max_items; SSCN_E_INVALID / SSCN_E_UNSUPPORTED as
+ * above.  No side effect on error. */
+int sscn_batch_admit(sscn_batch *b, int32_t slot, const sscn_problem *pb, void *d_psi, void *d_ws,
+                     double mu_tol, int64_t max_steps);
+
+/* Release a slot; in imaginary time the state is renormalised first (the
+ * pending factor of its last step is applied).  Waits for the stream. */
+int sscn_batch_evict(sscn_batch *b, int32_t slot);
+
+/* Enqueue nsteps persistent launches (one per step) and an asynchronous copy
+ * of the per-instance status to a pinned host mirror. */
+int sscn_batch_step(sscn_batch *b, int32_t nsteps);
+
+/* Copy the status of slots 0..nslots-1 from the mirror written by the last
+ * sscn_batch_step.  wait = 0: SSCN_BUSY if that copy has not landed yet;
+ * wait != 0: waits for it. */
+int sscn_batch_poll(sscn_batch *b, sscn_batch_slot *out, int32_t nslots, int32_t wait);
+
+/* 1 in *flag if a bounded wait inside the persistent kernel ever gave up
+ * (results of that launch are then invalid); waits for the stream. */
+int sscn_batch_error(sscn_batch *b, int32_t *flag);
+
+/* Free the batch's host state (device buffers belong to the caller). */
+int sscn_batch_destroy(sscn_batch *b);
 
 #ifdef __cplusplus
 }

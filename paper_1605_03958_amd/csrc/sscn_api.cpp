@@ -88,7 +88,7 @@ void thomas_coefs(double s_re, double s_im, int n, std::vector<double> &m_re, st
 }
 
 // Table metadata of axis a for its chunk geometry (C points per chunk).
-static void table_meta(AxisPlan &X, bool fp32)
+void table_meta(AxisPlan &X, bool fp32)
 {
     std::vector<double> mr, mi, ar, ai;
     thomas_coefs(X.sig_re, X.sig_im, X.n, mr, mi, ar, ai);

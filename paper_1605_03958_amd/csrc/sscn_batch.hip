@@ -1,0 +1,366 @@
+// sscn_batch.hip -- batched persistent SSCN step on gfx950 (FP32 forms).
+//
+// One launch advances every running instance of the batch by one step (the
+// ordering and waiting scheme is described in sscn_batch.hpp).  Work items:
+//   x tile    ROW line solve (pointwise substep + pending scale fused)
+//   y/z tile  COL line solve; the last sweep writes one FP64 norm partial
+//   obs tile  FP64 sums of the observables over 16384 points, on
+//             observation steps only
+//   fin       fixed-order sums -> renormalisation factor, mu, E, the
+//             convergence test and the instance's step count
+// The line solves are those of the single-problem kernels (sscn_lines.hpp).
+#include "sscn_batch.hpp"
+#include "sscn_lines.hpp"
+
+namespace sscn {
+
+// ---------------------------------------------------------------------------
+// items
+// ---------------------------------------------------------------------------
+template <class T, bool CPLX, int C, bool MW>
+__device__ __forceinline__ void batch_row(const BInst &I, const BState &S, int tile, unsigned char *lds,
+                                          double *red, bool last)
+{
+    using A = Alg<T, CPLX>;
+    using V = typename A::V;
+    const BAxis &X = I.ax[0];
+    const int G = MW ? 64 * X.wpl : 64;
+    const int tid = threadIdx.x;
+    const int lb = tid / G;
+    const int t = tid - lb * G;
+    const int lane = tid & 63;
+    const int wl = t >> 6;
+    LTab<T, CPLX> *tl = reinterpret_cast<LTab<T, CPLX> *>(lds);
+    V *xs = reinterpret_cast<V *>(lds) + lb * X.wpl * 4;
+    if constexpr (!MW) {
+        stage_table<T, CPLX>(X.lt.tab, tl, C * 64);
+        __syncthreads();
+    }
+    const long long line = (long long)tile * X.lpi + lb;
+    const bool active = line < X.nlines;
+    const V sig = A::coef(X.sig_re, X.sig_im);
+    const T scale = CPLX ? T(1) : T(S.scale);
+    V *psi = reinterpret_cast<V *>(I.psi);
+    double nacc;
+    if constexpr (MW)
+        nacc = row_line<T, CPLX, C, true>(psi, line, active, X.lt.n, X.lt.tab, G, t, lane, wl, X.wpl, xs, sig,
+                                          scale, T(I.pp.dt), T(I.pp.g), I.pp, X.lt.depth, last);
+    else
+        nacc = row_line<T, CPLX, C, false>(psi, line, active, X.lt.n, static_cast<const LTab<T, CPLX> *>(tl), G,
+                                           t, lane, wl, 1, xs, sig, scale, T(I.pp.dt), T(I.pp.g), I.pp,
+                                           X.lt.depth, last);
+    if (last) {
+        const double s = block_sum(nacc, red);
+        if (tid == 0) I.norm_part[tile] = s;
+    }
+}
+
+template <class T, bool CPLX, int C>
+__device__ __forceinline__ void batch_col(const BInst &I, int axis, int tile, unsigned char *lds, double *red,
+                                          bool last)
+{
+    using A = Alg<T, CPLX>;
+    using V = typename A::V;
+    const BAxis &X = I.ax[axis];
+    const int L = X.L, W = X.W;
+    const int LPB = 64 / L;
+    const int nch = W * L;
+    const int wave = threadIdx.x >> 6;
+    const int st_i = wave / W;          // sub-tile of this wave
+    const int w = wave - st_i * W;
+    const int lane = threadIdx.x & 63;
+    const int sub = lane / LPB;
+    const int li = lane - sub * LPB;
+    const int ch = w * L + sub;
+    LTab<T, CPLX> *tb = reinterpret_cast<LTab<T, CPLX> *>(lds);
+    V *xs0 = reinterpret_cast<V *>(tb + nch * C) + st_i * (2 * nch * LPB);
+    V *xs1 = xs0 + nch * LPB;
+    const long long line = ((long long)tile * X.tpi + st_i) * LPB + li;
+    const bool active = line < X.nlines;
+    long long base = 0;
+    if (active) base = (line % X.m1) * X.s1 + (line / X.m1) * X.s2;
+    stage_table<T, CPLX>(X.lt.tab, tb, nch * C);
+    const double nacc = col_tile<T, CPLX, C>(reinterpret_cast<V *>(I.psi), active, base, X.lt.n, X.stride, nch,
+                                             ch, LPB, li, tb, xs0, xs1, A::coef(X.sig_re, X.sig_im), X.lt.depth,
+                                             last);
+    if (last) {
+        const double s = block_sum(nacc, red);
+        if (threadIdx.x == 0) I.norm_part[tile] = s;
+    }
+}
+
+__device__ __forceinline__ bool batch_observes(const BInst &I, const BState &S)
+{
+    const int64_t s = S.step + 1;
+    return (s % I.observe_every) == 0 || s >= I.max_steps;
+}
+
+// FP64 sums over one tile of points: q, kinetic edges, V q, q^2, x_a q, x_a^2 q.
+template <class T, bool CPLX>
+__device__ __forceinline__ void batch_obs(const BInst &I, const BState &S, int tile, double (*redq)[16])
+{
+    using A = Alg<T, CPLX>;
+    using V = typename A::V;
+    if (!batch_observes(I, S)) return;
+    const V *psi = reinterpret_cast<const V *>(I.psi);
+    const long long nx = I.pp.n[0], ny = I.pp.n[1];
+    const int n3[3] = {I.pp.n[0], I.pp.n[1], I.pp.n[2]};
+    const long long sx[3] = {1, nx, nx * ny};
+    double acc[BATCH_NOBS];
+#pragma unroll
+    for (int q = 0; q < BATCH_NOBS; ++q) acc[q] = 0.0;
+    const long long p0 = (long long)tile * BATCH_OBS_PTS;
+    const long long p1 = min((long long)I.npts, p0 + BATCH_OBS_PTS);
+    for (long long p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+        const int idx[3] = {(int)(p % nx), (int)((p / nx) % ny), (int)(p / (nx * ny))};
+        const V v = psi[p];
+        const double q = A::norm2(v);
+        double vp = 0.0, kin = 0.0;
+        for (int ax = 0; ax < I.dim; ++ax) {
+            const double x = (double(idx[ax]) - I.pp.cen[ax]) * I.pp.dx[ax];
+            vp += I.pp.w2h[ax] * x * x;
+            acc[4 + ax] += x * q;
+            acc[7 + ax] += x * x * q;
+            const V nb = (idx[ax] + 1 < n3[ax]) ? psi[p + sx[ax]] : A::zero();
+            double e = A::norm2(A::sub(nb, v));
+            if (idx[ax] == 0) e += q;
+            kin += e / (I.pp.dx[ax] * I.pp.dx[ax]);
+        }
+        acc[0] += q;
+        acc[1] += kin;
+        acc[2] += vp * q;
+        acc[3] += q * q;
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < BATCH_NOBS; ++q) {
+        const double s = wave_sum(acc[q]);
+        if (lane == 0) redq[q][wid] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < BATCH_NOBS) {
+        const int q = threadIdx.x;
+        double s = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += redq[q][w];
+        I.obs_part[(size_t)tile * BATCH_NOBS + q] = s;
+    }
+}
+
+// Finalisation of one instance's step (one block).
+__device__ __forceinline__ void batch_fin(const BInst &I, BState &S, double *red)
+{
+    const int nt = I.ax[I.last_pass].ntiles;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nt; i += blockDim.x) acc += I.norm_part[i];
+    const double nraw = block_sum(acc, red);
+    const bool obs_now = batch_observes(I, S);
+    double tot[BATCH_NOBS];
+    for (int q = 0; q < BATCH_NOBS; ++q) tot[q] = 0.0;
+    if (obs_now) {
+        for (int q = 0; q < BATCH_NOBS; ++q) {
+            double a = 0.0;
+            for (int i = threadIdx.x; i < I.obs_tiles; i += blockDim.x) a += I.obs_part[(size_t)i * BATCH_NOBS + q];
+            tot[q] = block_sum(a, red);
+        }
+    }
+    if (threadIdx.x != 0) return;
+    const double dv = I.dvol;
+    const double N = dv * nraw;
+    const double s = I.imag ? 1.0 / sqrt(N) : 1.0;   // renormalisation every step in imaginary time
+    int32_t status = S.status;
+    if (!__builtin_isfinite(N) || !(N > 0.0)) status = BS_NONFINITE;
+    if (obs_now && status == BS_RUNNING) {
+        // observables of the step's state, renormalised in imaginary time:
+        // K and P scale with s^2, I with s^4, the norm with s^2
+        const double s2 = s * s;
+        const double Nq = dv * tot[0] * s2;
+        const double K = 0.5 * dv * tot[1] * s2;
+        const double P = dv * tot[2] * s2;
+        const double In = dv * tot[3] * s2 * s2;
+        const double g = I.pp.g;
+        const double mu = (K + P + g * In) / Nq;
+        S.obs[0] = Nq;
+        S.obs[1] = mu;
+        S.obs[2] = (K + P + 0.5 * g * In) / Nq;
+        S.obs[3] = K;
+        S.obs[4] = P;
+        S.obs[5] = In;
+        for (int ax = 0; ax < 3; ++ax) {
+            S.obs[6 + ax] = dv * tot[4 + ax] * s2 / Nq;
+            S.obs[9 + ax] = dv * tot[7 + ax] * s2 / Nq;
+        }
+        S.obs_step = S.step + 1;
+        if (!__builtin_isfinite(mu)) {
+            status = BS_NONFINITE;
+        } else if (I.mu_tol > 0.0 && ((S.step + 1) % I.observe_every) == 0) {
+            if (S.have_prev && fabs(mu - S.mu_prev) < I.mu_tol) status = BS_CONVERGED;
+            S.mu_prev = mu;
+            S.have_prev = 1;
+        }
+    }
+    S.norm = N;
+    S.scale = s;
+    S.step += 1;
+    if (status == BS_RUNNING && S.step >= I.max_steps) status = BS_DONE;
+    S.status = status;
+}
+
+// ---------------------------------------------------------------------------
+// dispatch
+// ---------------------------------------------------------------------------
+template <class T, bool CPLX, bool BIG>
+__device__ __forceinline__ void batch_sweep(const BInst &I, const BState &S, int pass, int tile, unsigned char *lds,
+                                            double *red)
+{
+    const bool last = pass == I.last_pass;
+    const BAxis &X = I.ax[pass];
+    if (pass == BP_X) {
+        const bool mw = X.wpl > 1;
+        switch (X.C * 2 + (mw ? 1 : 0)) {
+        case 2: batch_row<T, CPLX, 1, false>(I, S, tile, lds, red, last); break;
+        case 4: batch_row<T, CPLX, 2, false>(I, S, tile, lds, red, last); break;
+        case 8: batch_row<T, CPLX, 4, false>(I, S, tile, lds, red, last); break;
+        case 16: batch_row<T, CPLX, 8, false>(I, S, tile, lds, red, last); break;
+        case 32:
+            if constexpr (!CPLX) batch_row<T, CPLX, 16, false>(I, S, tile, lds, red, last);
+            break;
+        case 9: batch_row<T, CPLX, 4, true>(I, S, tile, lds, red, last); break;
+        case 17: batch_row<T, CPLX, 8, true>(I, S, tile, lds, red, last); break;
+        case 33:
+            if constexpr (BIG) batch_row<T, CPLX, 16, true>(I, S, tile, lds, red, last);
+            break;
+        default: break;
+        }
+    } else {
+        switch (X.C) {
+        case 2: batch_col<T, CPLX, 2>(I, pass, tile, lds, red, last); break;
+        case 4: batch_col<T, CPLX, 4>(I, pass, tile, lds, red, last); break;
+        case 8: batch_col<T, CPLX, 8>(I, pass, tile, lds, red, last); break;
+        case 16:
+            if constexpr (BIG && !CPLX) batch_col<T, CPLX, 16>(I, pass, tile, lds, red, last);
+            break;
+        default: break;
+        }
+    }
+}
+
+// BIG adds the variants for 1D lines longer than 8192 points (16 points per
+// thread over the whole block), whose registers the other paths do not need.
+template <bool BIG>
+__global__ void __launch_bounds__(BATCH_BLOCK) k_batch_step(BatchArgs a)
+{
+    extern __shared__ unsigned char lds_raw[];
+    __shared__ double red[16];
+    __shared__ double redq[BATCH_NOBS][16];
+    __shared__ int s_item;
+    const int total = a.ctl->total_items;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_item = atomicAdd(&a.ctl->ticket, 1);
+        __syncthreads();
+        const int it = s_item;
+        if (it >= total) break;
+        const BItem w = a.items[it];
+        const BInst &I = a.inst[w.slot];
+        BState &S = a.state[w.slot];
+        if (S.status != BS_RUNNING) continue;
+
+        // wait until the instance's previous pass has completed (bounded)
+        const int dep = I.dep[w.pass];
+        if (dep >= 0) {
+            if (threadIdx.x == 0) {
+                int32_t *cnt = a.done + (size_t)w.slot * 4 + dep;
+                int spins = 0;
+                // bounded: after spin_limit polls (or once any wait of the
+                // launch has given up) the item proceeds and the error flag
+                // marks the launch's results invalid
+                while (__hip_atomic_load(cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < I.need[w.pass]) {
+                    __builtin_amdgcn_s_sleep(2);
+                    ++spins;
+                    if (spins > a.spin_limit ||
+                        ((spins & 1023) == 0 &&
+                         __hip_atomic_load(&a.ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)) {
+                        atomicOr(&a.ctl->error, 1);
+                        break;
+                    }
+                }
+            }
+            __syncthreads();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+
+        if (w.pass <= BP_Z) {
+            if (I.elem == 1) batch_sweep<float, false, BIG>(I, S, w.pass, w.tile, lds_raw, red);
+            else batch_sweep<float, true, BIG>(I, S, w.pass, w.tile, lds_raw, red);
+        } else if (w.pass == BP_OBS) {
+            if (I.elem == 1) batch_obs<float, false>(I, S, w.tile, redq);
+            else batch_obs<float, true>(I, S, w.tile, redq);
+        } else {
+            batch_fin(I, S, red);
+        }
+
+        if (w.pass < BP_FIN) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __syncthreads();
+            if (threadIdx.x == 0)
+                __hip_atomic_fetch_add(a.done + (size_t)w.slot * 4 + w.pass, 1, __ATOMIC_RELEASE,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+    // the last block out resets the counters for the next launch
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const int prev = atomicAdd(&a.ctl->exited, 1);
+        if (prev == (int)gridDim.x - 1) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            const int nd = a.ctl->max_slots * 4;
+            for (int q = 0; q < nd; ++q) a.done[q] = 0;
+            a.ctl->ticket = 0;
+            a.ctl->exited = 0;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        }
+    }
+}
+
+// Apply the pending renormalisation factor of a finished instance and clear it.
+template <class T, bool CPLX>
+__global__ void __launch_bounds__(256) k_batch_scale(void *psi_, long long npts, const double *scale)
+{
+    using A = Alg<T, CPLX>;
+    using V = typename A::V;
+    V *psi = reinterpret_cast<V *>(psi_);
+    const T s = T(*scale);
+    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < npts;
+         p += (long long)gridDim.x * blockDim.x)
+        psi[p] = A::scal(s, psi[p]);
+}
+
+__global__ void k_batch_unit(double *scale)
+{
+    if (threadIdx.x == 0) *scale = 1.0;
+}
+
+hipError_t launch_batch_step(const BatchArgs &a, bool big, int grid, size_t lds, hipStream_t st)
+{
+    if (big) hipLaunchKernelGGL(k_batch_step<true>, dim3(grid), dim3(BATCH_BLOCK), lds, st, a);
+    else hipLaunchKernelGGL(k_batch_step<false>, dim3(grid), dim3(BATCH_BLOCK), lds, st, a);
+    return hipGetLastError();
+}
+
+hipError_t batch_step_occupancy(bool big, size_t lds, int *blocks_per_cu)
+{
+    if (big) return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batch_step<true>, BATCH_BLOCK, lds);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batch_step<false>, BATCH_BLOCK, lds);
+}
+
+hipError_t launch_batch_scale(int elem, void *psi, int64_t npts, double *scale, hipStream_t st)
+{
+    const int grid = (int)std::min<int64_t>((npts + 255) / 256, 4096);
+    if (elem == 1) hipLaunchKernelGGL((k_batch_scale<float, false>), dim3(grid), dim3(256), 0, st, psi, (long long)npts, scale);
+    else if (elem == 3) hipLaunchKernelGGL((k_batch_scale<float, true>), dim3(grid), dim3(256), 0, st, psi, (long long)npts, scale);
+    else return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_batch_unit, dim3(1), dim3(64), 0, st, scale);
+    return hipGetLastError();
+}
+
+}  // namespace sscn

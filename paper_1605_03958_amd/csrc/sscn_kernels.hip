@@ -12,178 +12,9 @@
 // Fallbacks for lines too long to keep in registers: k_pointwise (separate
 // pointwise substep), k_stream (one thread per line, exact Thomas with the
 // forward intermediates stored in place) and k_norm_partials.
-#include "sscn_launch.hpp"
+#include "sscn_lines.hpp"
 
 namespace sscn {
-
-template <class T>
-__device__ __forceinline__ T dev_exp(T x)
-{
-    if constexpr (sizeof(T) == 8) return exp(x); else return expf(x);
-}
-
-template <class T>
-__device__ __forceinline__ void dev_sincos(T x, T *s, T *c)
-{
-    if constexpr (sizeof(T) == 8) sincos(x, s, c); else sincosf(x, s, c);
-}
-
-// sin and cos for |x| <= pi/4 from their Maclaurin series, through x^17 and
-// x^18 in FP64 (remainders below 1e-19 there) and through x^9 and x^10 in
-// FP32 (below 3e-9).  Horner form in x^2.
-template <class T>
-__device__ __forceinline__ void sincos_small(T x, T *s, T *c)
-{
-    const T x2 = x * x;
-    if constexpr (sizeof(T) == 8) {
-        T p = T(1.0 / 355687428096000.0);           //  1/17!
-        p = fmaT(p, -x2, T(1.0 / 1307674368000.0));  //  1/15!
-        p = fmaT(p, -x2, T(1.0 / 6227020800.0));     //  1/13!
-        p = fmaT(p, -x2, T(1.0 / 39916800.0));       //  1/11!
-        p = fmaT(p, -x2, T(1.0 / 362880.0));         //  1/9!
-        p = fmaT(p, -x2, T(1.0 / 5040.0));           //  1/7!
-        p = fmaT(p, -x2, T(1.0 / 120.0));            //  1/5!
-        p = fmaT(p, -x2, T(1.0 / 6.0));              //  1/3!
-        p = fmaT(p, -x2, T(1.0));
-        *s = x * p;
-        T q = T(1.0 / 6402373705728000.0);          //  1/18!
-        q = fmaT(q, -x2, T(1.0 / 20922789888000.0)); //  1/16!
-        q = fmaT(q, -x2, T(1.0 / 87178291200.0));    //  1/14!
-        q = fmaT(q, -x2, T(1.0 / 479001600.0));      //  1/12!
-        q = fmaT(q, -x2, T(1.0 / 3628800.0));        //  1/10!
-        q = fmaT(q, -x2, T(1.0 / 40320.0));          //  1/8!
-        q = fmaT(q, -x2, T(1.0 / 720.0));            //  1/6!
-        q = fmaT(q, -x2, T(1.0 / 24.0));             //  1/4!
-        q = fmaT(q, -x2, T(1.0 / 2.0));              //  1/2!
-        q = fmaT(q, -x2, T(1.0));
-        *c = q;
-    } else {
-        T p = T(1.0 / 362880.0);
-        p = fmaT(p, -x2, T(1.0 / 5040.0));
-        p = fmaT(p, -x2, T(1.0 / 120.0));
-        p = fmaT(p, -x2, T(1.0 / 6.0));
-        p = fmaT(p, -x2, T(1.0));
-        *s = x * p;
-        T q = T(1.0 / 3628800.0);
-        q = fmaT(q, -x2, T(1.0 / 40320.0));
-        q = fmaT(q, -x2, T(1.0 / 720.0));
-        q = fmaT(q, -x2, T(1.0 / 24.0));
-        q = fmaT(q, -x2, T(1.0 / 2.0));
-        q = fmaT(q, -x2, T(1.0));
-        *c = q;
-    }
-}
-
-// Library sin/cos for phases outside [-pi/4, pi/4], kept out of line so the
-// common small-phase path does not carry its registers.
-template <class T>
-__device__ __attribute__((noinline)) cpx<T> phase_slow(T x)
-{
-    T sn, cs;
-    dev_sincos<T>(x, &sn, &cs);
-    return cpx<T>{cs, sn};
-}
-
-// Pointwise substep on one value (imaginary time: scale first; real time: phase).
-template <class T, bool CPLX>
-__device__ __forceinline__ typename Alg<T, CPLX>::V
-apply_point(typename Alg<T, CPLX>::V u, T scale, T vpot, T dt, T g)
-{
-    using A = Alg<T, CPLX>;
-    if constexpr (!CPLX) {
-        u = A::scal(scale, u);
-        T phi = dt * fmaT(g, A::norm2t(u), vpot);
-        return dev_exp<T>(-phi) * u;
-    } else {
-        (void)scale;
-        T phi = dt * fmaT(g, A::norm2t(u), vpot);
-        T sn, cs;
-        if (__builtin_fabs(phi) <= T(0.78539816339744830962)) {
-            sincos_small<T>(phi, &sn, &cs);
-        } else {
-            const cpx<T> e = phase_slow<T>(phi);
-            cs = e.re;
-            sn = e.im;
-        }
-        return typename A::V{fmaT(cs, u.re, sn * u.im), fmaT(cs, u.im, -sn * u.re)};
-    }
-}
-
-template <class T>
-__device__ __forceinline__ T coord(int i, double cen, double dx)
-{
-    return T((double(i) - cen) * dx);
-}
-
-// A Thomas table entry as the sweeps use it.  FP64: (alpha, m).  FP32: each
-// FP64 coefficient c is kept as the unevaluated pair hi + lo with hi = fl32(c)
-// and lo = fl32(c - hi), and every product c x is formed as hi x + lo x in
-// FP32.  The coefficients then carry ~48 bits, so the FP32 operator stays
-// the FP64 one up to the rounding of the data arithmetic: rounding the
-// coefficients once would perturb every line of every step identically and
-// the real-time norm would drift coherently (about 1e-4 over 1000 steps).
-template <class T, bool CPLX>
-struct LTab;
-
-template <bool CPLX>
-struct LTab<double, CPLX> {
-    using A = Alg<double, CPLX>;
-    using V = typename A::V;
-    V al, m;
-    __device__ __forceinline__ static LTab make(const TabEntry &e)
-    {
-        return LTab{A::coef(e.ar, e.ai), A::coef(e.mr, e.mi)};
-    }
-    __device__ __forceinline__ V afma(V x, V y) const { return A::fma(al, x, y); }   // alpha x + y
-    __device__ __forceinline__ V mmul(V r) const { return A::mul(m, r); }            // m r
-    __device__ __forceinline__ V alpha() const { return al; }
-};
-
-template <bool CPLX>
-struct LTab<float, CPLX> {
-    using A = Alg<float, CPLX>;
-    using V = typename A::V;
-    V al, al_lo, m, m_lo;
-    __device__ __forceinline__ static V lo_of(double re, double im, V hi)
-    {
-        if constexpr (CPLX) return V{float(re - double(hi.re)), float(im - double(hi.im))};
-        else return float(re - double(hi));
-    }
-    __device__ __forceinline__ static LTab make(const TabEntry &e)
-    {
-        LTab t;
-        t.al = A::coef(e.ar, e.ai);
-        t.m = A::coef(e.mr, e.mi);
-        t.al_lo = lo_of(e.ar, e.ai, t.al);
-        t.m_lo = lo_of(e.mr, e.mi, t.m);
-        return t;
-    }
-    __device__ __forceinline__ V afma(V x, V y) const { return A::fma(al, x, A::fma(al_lo, x, y)); }
-    __device__ __forceinline__ V mmul(V r) const { return A::fma(m, r, A::mul(m_lo, r)); }
-    __device__ __forceinline__ V alpha() const { return al; }
-};
-
-// Copy a kernel's table slice (cnt entries, zero-padded past the line end
-// by the host) into LDS in the working representation; the caller
-// synchronises before reading it.
-template <class T, bool CPLX>
-__device__ __forceinline__ void stage_table(const TabEntry *__restrict__ src, LTab<T, CPLX> *dst, int cnt)
-{
-    for (int q = threadIdx.x; q < cnt; q += blockDim.x) dst[q] = LTab<T, CPLX>::make(src[q]);
-}
-
-// Table entry q from LDS (staged) or from the FP64 table in global memory.
-template <class T, bool CPLX>
-__device__ __forceinline__ LTab<T, CPLX> tab_at(const LTab<T, CPLX> *tb, int q)
-{
-    return tb[q];
-}
-
-template <class T, bool CPLX>
-__device__ __forceinline__ LTab<T, CPLX> tab_at(const TabEntry *tb, int q)
-{
-    return LTab<T, CPLX>::make(tb[q]);
-}
 
 // ===========================================================================
 // ROW: x lines, G = 64 * wpl threads per line, C points per thread.
@@ -206,176 +37,27 @@ __global__ void __launch_bounds__(MW ? 1024 : 256) k_row(RowArgs a)
     const int lane = tid & 63;
     const int wl = t >> 6;
     LTab<T, CPLX> *tl = reinterpret_cast<LTab<T, CPLX> *>(lds_raw);
-    const auto tb = [&]() {
-        if constexpr (MW) return a.lt.tab;
-        else return static_cast<const LTab<T, CPLX> *>(tl);
-    }();
     V *xs = reinterpret_cast<V *>(lds_raw) + lb * a.wpl * 4;
-
     const V sig = A::coef(a.sig_re, a.sig_im);
     const T scale = CPLX ? T(1) : T(*a.scale);
     const T dt = T(a.pp.dt), g = T(a.pp.g);
     V *psi = reinterpret_cast<V *>(a.psi);
-    const int n = a.lt.n;
-    const int ks = a.lt.depth;
-    const int i0 = t * C;
     double nacc = 0.0;
 
     if constexpr (!MW) {
         stage_table<T, CPLX>(a.lt.tab, tl, C * G);
         __syncthreads();
     }
-
     for (long long gb = (long long)blockIdx.x * a.lpb; gb < a.nlines;
          gb += (long long)gridDim.x * a.lpb) {
         const long long line = gb + lb;
         const bool active = line < a.nlines;
-        const long long base = line * (long long)n;
-
-        V u[C];
-#pragma unroll
-        for (int k = 0; k < C; ++k) {
-            const int i = i0 + k;
-            V v = A::zero();
-            if (active && i < n) v = psi[base + i];
-            u[k] = v;
-        }
-
-        // ---- pointwise substep ----
-        T vyz = T(0);
-        if (active) {
-            const int j = (int)(line % a.pp.n[1]);
-            const int k = (int)(line / a.pp.n[1]);
-            const T y = coord<T>(j, a.pp.cen[1], a.pp.dx[1]);
-            const T z = coord<T>(k, a.pp.cen[2], a.pp.dx[2]);
-            vyz = T(a.pp.w2h[1]) * y * y + T(a.pp.w2h[2]) * z * z;
-        }
-#pragma unroll
-        for (int k = 0; k < C; ++k) {
-            const int i = i0 + k;
-            const T x = coord<T>(i, a.pp.cen[0], a.pp.dx[0]);
-            u[k] = apply_point<T, CPLX>(u[k], scale, T(a.pp.w2h[0]) * x * x + vyz, dt, g);
-        }
-
-        // ---- neighbours across chunk boundaries ----
-        V left = A::shfl_up(u[C - 1], 1);
-        V right = A::shfl_down(u[0], 1);
-        if (lane == 0) left = A::zero();
-        if (lane == 63) right = A::zero();
-        if constexpr (MW) {
-            if (lane == 0) xs[wl * 4 + 0] = u[0];
-            if (lane == 63) xs[wl * 4 + 1] = u[C - 1];
-            __syncthreads();
-            if (lane == 0 && wl > 0) left = xs[(wl - 1) * 4 + 1];
-            if (lane == 63 && wl < a.wpl - 1) right = xs[(wl + 1) * 4 + 0];
-            __syncthreads();
-        }
-
-        // ---- m_i (1 - sT)u, and the chunk's forward map d -> Ac d + d_loc ----
-        V be[C];
-        V Ac = A::one(), d = A::zero();
-        {
-            V prev = left;
-#pragma unroll
-            for (int k = 0; k < C; ++k) {
-                const V nxt = (k + 1 < C) ? u[k + 1] : right;
-                const V r = cn_rhs<T, CPLX>(prev, u[k], nxt, sig);
-                prev = u[k];
-                const LTab<T, CPLX> e = tab_at<T, CPLX>(tb, k * G + t);
-                be[k] = e.mmul(r);
-                d = e.afma(d, be[k]);
-                Ac = A::mul(e.alpha(), Ac);
-            }
-        }
-
-        // ---- forward: scan of chunk maps over the preceding chunks ----
-        V din;
-        {
-            V PA = Ac, PB = d;
-            for (int s = 0; s < ks; ++s) {
-                const int o = 1 << s;
-                const V a2 = A::shfl_up(PA, o), b2 = A::shfl_up(PB, o);
-                if (lane >= o) {
-                    PB = A::fma(PA, b2, PB);
-                    PA = A::mul(PA, a2);
-                }
-            }
-            V EA = A::shfl_up(PA, 1), EB = A::shfl_up(PB, 1);
-            if (lane == 0) {
-                EA = A::one();
-                EB = A::zero();
-            }
-            if constexpr (MW) {
-                if (lane == 63) {
-                    xs[wl * 4 + 2] = PA;
-                    xs[wl * 4 + 3] = PB;
-                }
-                __syncthreads();
-                V Dw = A::zero();
-                for (int q = 0; q < wl; ++q) Dw = A::fma(xs[q * 4 + 2], Dw, xs[q * 4 + 3]);
-                __syncthreads();
-                din = A::fma(EA, Dw, EB);
-            } else {
-                din = EB;
-            }
-        }
-        d = din;
-#pragma unroll
-        for (int k = 0; k < C; ++k) {
-            d = tab_at<T, CPLX>(tb, k * G + t).afma(d, be[k]);
-            be[k] = d;
-        }
-
-        // ---- backward ----
-        V v = A::zero();
-#pragma unroll
-        for (int k = C - 1; k >= 0; --k) v = tab_at<T, CPLX>(tb, k * G + t).afma(v, be[k]);
-        V vin;
-        {
-            V PA = Ac, PB = v;
-            for (int s = 0; s < ks; ++s) {
-                const int o = 1 << s;
-                const V a2 = A::shfl_down(PA, o), b2 = A::shfl_down(PB, o);
-                if (lane + o < 64) {
-                    PB = A::fma(PA, b2, PB);
-                    PA = A::mul(PA, a2);
-                }
-            }
-            V EA = A::shfl_down(PA, 1), EB = A::shfl_down(PB, 1);
-            if (lane == 63) {
-                EA = A::one();
-                EB = A::zero();
-            }
-            if constexpr (MW) {
-                if (lane == 0) {
-                    xs[wl * 4 + 2] = PA;
-                    xs[wl * 4 + 3] = PB;
-                }
-                __syncthreads();
-                V Vw = A::zero();
-                for (int q = a.wpl - 1; q > wl; --q) Vw = A::fma(xs[q * 4 + 2], Vw, xs[q * 4 + 3]);
-                __syncthreads();
-                vin = A::fma(EA, Vw, EB);
-            } else {
-                vin = EB;
-            }
-        }
-        v = vin;
-#pragma unroll
-        for (int k = C - 1; k >= 0; --k) {
-            v = tab_at<T, CPLX>(tb, k * G + t).afma(v, be[k]);
-            be[k] = v;
-        }
-
-        // ---- store ----
-#pragma unroll
-        for (int k = 0; k < C; ++k) {
-            const int i = i0 + k;
-            if (active && i < n) {
-                psi[base + i] = be[k];
-                if constexpr (LAST) nacc += A::norm2(be[k]);
-            }
-        }
+        if constexpr (MW)
+            nacc += row_line<T, CPLX, C, true>(psi, line, active, a.lt.n, a.lt.tab, G, t, lane, wl, a.wpl, xs,
+                                               sig, scale, dt, g, a.pp, a.lt.depth, LAST);
+        else
+            nacc += row_line<T, CPLX, C, false>(psi, line, active, a.lt.n, static_cast<const LTab<T, CPLX> *>(tl),
+                                                G, t, lane, wl, 1, xs, sig, scale, dt, g, a.pp, a.lt.depth, LAST);
     }
     if constexpr (LAST) {
         const double s = block_sum(nacc, red);
@@ -384,10 +66,8 @@ __global__ void __launch_bounds__(MW ? 1024 : 256) k_row(RowArgs a)
 }
 
 // ===========================================================================
-// COL: 64/L lines per block, W*L chunks of C points per line.  Lane l of
-// wave w holds chunk w*L + l/(64/L) of line l%(64/L), so the lanes of each
-// 64/L group read 64/L adjacent lines (contiguous memory).  LDS: the table
-// (W*L*C entries), then two chunk x line exchange arrays.
+// COL: 64/L lines per block, W*L chunks of C points per line.  LDS: the
+// table (W*L*C entries), then two chunk x line exchange arrays.
 // ===========================================================================
 template <class T, bool CPLX, int C, bool LAST>
 __global__ void __launch_bounds__(1024) k_col(ColArgs a)
@@ -412,81 +92,10 @@ __global__ void __launch_bounds__(1024) k_col(ColArgs a)
     const bool active = line < a.nlines;
     long long base = 0;
     if (active) base = (line % a.m1) * a.s1 + (line / a.m1) * a.s2;
-    V *psi = reinterpret_cast<V *>(a.psi);
-    const V sig = A::coef(a.sig_re, a.sig_im);
-    const int n = a.lt.n;
-    const int i0 = ch * C;
-    const long long st = a.stride;
-    const int qlo = max(0, ch - a.lt.depth);
-    const int qhi = min(nch - 1, ch + a.lt.depth);
-
-    V u[C];
-#pragma unroll
-    for (int k = 0; k < C; ++k) {
-        const int i = i0 + k;
-        u[k] = (active && i < n) ? psi[base + (long long)i * st] : A::zero();
-    }
     stage_table<T, CPLX>(a.lt.tab, tb, nch * C);
-
-    // neighbours from the adjacent chunks
-    xs0[ch * LPB + li] = u[0];
-    xs1[ch * LPB + li] = u[C - 1];
-    __syncthreads();
-    const V left = (ch > 0) ? xs1[(ch - 1) * LPB + li] : A::zero();
-    const V right = (ch + 1 < nch) ? xs0[(ch + 1) * LPB + li] : A::zero();
-    __syncthreads();
-
-    V be[C];
-    V Ac = A::one(), d = A::zero();
-    {
-        V prev = left;
-#pragma unroll
-        for (int k = 0; k < C; ++k) {
-            const V nxt = (k + 1 < C) ? u[k + 1] : right;
-            const V r = cn_rhs<T, CPLX>(prev, u[k], nxt, sig);
-            prev = u[k];
-            const LTab<T, CPLX> e = tab_at<T, CPLX>(tb, i0 + k);
-            be[k] = e.mmul(r);
-            d = e.afma(d, be[k]);
-            Ac = A::mul(e.alpha(), Ac);
-        }
-    }
-    xs0[ch * LPB + li] = Ac;
-    xs1[ch * LPB + li] = d;
-    __syncthreads();
-    V din = A::zero();
-    for (int q = qlo; q < ch; ++q) din = A::fma(xs0[q * LPB + li], din, xs1[q * LPB + li]);
-    __syncthreads();
-    d = din;
-#pragma unroll
-    for (int k = 0; k < C; ++k) {
-        d = tab_at<T, CPLX>(tb, i0 + k).afma(d, be[k]);
-        be[k] = d;
-    }
-
-    // backward
-    V v = A::zero();
-#pragma unroll
-    for (int k = C - 1; k >= 0; --k) v = tab_at<T, CPLX>(tb, i0 + k).afma(v, be[k]);
-    xs1[ch * LPB + li] = v;
-    __syncthreads();
-    V vin = A::zero();
-    for (int q = qhi; q > ch; --q) vin = A::fma(xs0[q * LPB + li], vin, xs1[q * LPB + li]);
-    v = vin;
-    double nacc = 0.0;
-#pragma unroll
-    for (int k = C - 1; k >= 0; --k) {
-        v = tab_at<T, CPLX>(tb, i0 + k).afma(v, be[k]);
-        be[k] = v;
-    }
-#pragma unroll
-    for (int k = 0; k < C; ++k) {
-        const int i = i0 + k;
-        if (active && i < n) {
-            psi[base + (long long)i * st] = be[k];
-            if constexpr (LAST) nacc += A::norm2(be[k]);
-        }
-    }
+    const double nacc = col_tile<T, CPLX, C>(reinterpret_cast<V *>(a.psi), active, base, a.lt.n, a.stride, nch, ch,
+                                             LPB, li, tb, xs0, xs1, A::coef(a.sig_re, a.sig_im), a.lt.depth,
+                                             LAST);
     if constexpr (LAST) {
         const double s = block_sum(nacc, red);
         if (threadIdx.x == 0) a.partial[blockIdx.x] = s;

@@ -1,0 +1,436 @@
+// sscn_lines.hpp -- line solves of one SSCN step, shared by the
+// single-problem kernels (sscn_kernels.hip) and the batched persistent
+// kernel (sscn_batch.hip), so both run the same arithmetic.
+//
+// ROW (x lines): a line group of G = 64 * wpl threads holds consecutive
+// chunks of C points of one line; the pointwise substep and the pending
+// renormalisation are applied to the loaded values; the chunk maps are
+// scanned across lanes (and across waves through LDS when wpl > 1).
+// COL (y, z lines): 64/L adjacent lines per tile, chunk ch = w*L + l/(64/L)
+// of line l%(64/L) on lane l of wave w; chunk maps folded through LDS.
+#pragma once
+
+#include "sscn_launch.hpp"
+
+namespace sscn {
+
+template <class T>
+__device__ __forceinline__ T dev_exp(T x)
+{
+    if constexpr (sizeof(T) == 8) return exp(x); else return expf(x);
+}
+
+template <class T>
+__device__ __forceinline__ void dev_sincos(T x, T *s, T *c)
+{
+    if constexpr (sizeof(T) == 8) sincos(x, s, c); else sincosf(x, s, c);
+}
+
+// sin and cos for |x| <= pi/4 from their Maclaurin series, through x^17 and
+// x^18 in FP64 (remainders below 1e-19 there) and through x^9 and x^10 in
+// FP32 (below 3e-9).  Horner form in x^2.
+template <class T>
+__device__ __forceinline__ void sincos_small(T x, T *s, T *c)
+{
+    const T x2 = x * x;
+    if constexpr (sizeof(T) == 8) {
+        T p = T(1.0 / 355687428096000.0);           //  1/17!
+        p = fmaT(p, -x2, T(1.0 / 1307674368000.0));  //  1/15!
+        p = fmaT(p, -x2, T(1.0 / 6227020800.0));     //  1/13!
+        p = fmaT(p, -x2, T(1.0 / 39916800.0));       //  1/11!
+        p = fmaT(p, -x2, T(1.0 / 362880.0));         //  1/9!
+        p = fmaT(p, -x2, T(1.0 / 5040.0));           //  1/7!
+        p = fmaT(p, -x2, T(1.0 / 120.0));            //  1/5!
+        p = fmaT(p, -x2, T(1.0 / 6.0));              //  1/3!
+        p = fmaT(p, -x2, T(1.0));
+        *s = x * p;
+        T q = T(1.0 / 6402373705728000.0);          //  1/18!
+        q = fmaT(q, -x2, T(1.0 / 20922789888000.0)); //  1/16!
+        q = fmaT(q, -x2, T(1.0 / 87178291200.0));    //  1/14!
+        q = fmaT(q, -x2, T(1.0 / 479001600.0));      //  1/12!
+        q = fmaT(q, -x2, T(1.0 / 3628800.0));        //  1/10!
+        q = fmaT(q, -x2, T(1.0 / 40320.0));          //  1/8!
+        q = fmaT(q, -x2, T(1.0 / 720.0));            //  1/6!
+        q = fmaT(q, -x2, T(1.0 / 24.0));             //  1/4!
+        q = fmaT(q, -x2, T(1.0 / 2.0));              //  1/2!
+        q = fmaT(q, -x2, T(1.0));
+        *c = q;
+    } else {
+        T p = T(1.0 / 362880.0);
+        p = fmaT(p, -x2, T(1.0 / 5040.0));
+        p = fmaT(p, -x2, T(1.0 / 120.0));
+        p = fmaT(p, -x2, T(1.0 / 6.0));
+        p = fmaT(p, -x2, T(1.0));
+        *s = x * p;
+        T q = T(1.0 / 3628800.0);
+        q = fmaT(q, -x2, T(1.0 / 40320.0));
+        q = fmaT(q, -x2, T(1.0 / 720.0));
+        q = fmaT(q, -x2, T(1.0 / 24.0));
+        q = fmaT(q, -x2, T(1.0 / 2.0));
+        q = fmaT(q, -x2, T(1.0));
+        *c = q;
+    }
+}
+
+// Library sin/cos for phases outside [-pi/4, pi/4], kept out of line so the
+// common small-phase path does not carry its registers.
+template <class T>
+__device__ __attribute__((noinline)) cpx<T> phase_slow(T x)
+{
+    T sn, cs;
+    dev_sincos<T>(x, &sn, &cs);
+    return cpx<T>{cs, sn};
+}
+
+// Pointwise substep on one value (imaginary time: scale first; real time: phase).
+template <class T, bool CPLX>
+__device__ __forceinline__ typename Alg<T, CPLX>::V
+apply_point(typename Alg<T, CPLX>::V u, T scale, T vpot, T dt, T g)
+{
+    using A = Alg<T, CPLX>;
+    if constexpr (!CPLX) {
+        u = A::scal(scale, u);
+        T phi = dt * fmaT(g, A::norm2t(u), vpot);
+        return dev_exp<T>(-phi) * u;
+    } else {
+        (void)scale;
+        T phi = dt * fmaT(g, A::norm2t(u), vpot);
+        T sn, cs;
+        if (__builtin_fabs(phi) <= T(0.78539816339744830962)) {
+            sincos_small<T>(phi, &sn, &cs);
+        } else {
+            const cpx<T> e = phase_slow<T>(phi);
+            cs = e.re;
+            sn = e.im;
+        }
+        return typename A::V{fmaT(cs, u.re, sn * u.im), fmaT(cs, u.im, -sn * u.re)};
+    }
+}
+
+template <class T>
+__device__ __forceinline__ T coord(int i, double cen, double dx)
+{
+    return T((double(i) - cen) * dx);
+}
+
+// A Thomas table entry as the sweeps use it.  FP64: (alpha, m).  FP32: each
+// FP64 coefficient c is kept as the unevaluated pair hi + lo with hi = fl32(c)
+// and lo = fl32(c - hi), and every product c x is formed as hi x + lo x in
+// FP32.  The coefficients then carry ~48 bits, so the FP32 operator stays
+// the FP64 one up to the rounding of the data arithmetic: rounding the
+// coefficients once would perturb every line of every step identically and
+// the real-time norm would drift coherently (about 1e-4 over 1000 steps).
+template <class T, bool CPLX>
+struct LTab;
+
+template <bool CPLX>
+struct LTab<double, CPLX> {
+    using A = Alg<double, CPLX>;
+    using V = typename A::V;
+    V al, m;
+    __device__ __forceinline__ static LTab make(const TabEntry &e)
+    {
+        return LTab{A::coef(e.ar, e.ai), A::coef(e.mr, e.mi)};
+    }
+    __device__ __forceinline__ V afma(V x, V y) const { return A::fma(al, x, y); }   // alpha x + y
+    __device__ __forceinline__ V mmul(V r) const { return A::mul(m, r); }            // m r
+    __device__ __forceinline__ V alpha() const { return al; }
+};
+
+template <bool CPLX>
+struct LTab<float, CPLX> {
+    using A = Alg<float, CPLX>;
+    using V = typename A::V;
+    V al, al_lo, m, m_lo;
+    __device__ __forceinline__ static V lo_of(double re, double im, V hi)
+    {
+        if constexpr (CPLX) return V{float(re - double(hi.re)), float(im - double(hi.im))};
+        else return float(re - double(hi));
+    }
+    __device__ __forceinline__ static LTab make(const TabEntry &e)
+    {
+        LTab t;
+        t.al = A::coef(e.ar, e.ai);
+        t.m = A::coef(e.mr, e.mi);
+        t.al_lo = lo_of(e.ar, e.ai, t.al);
+        t.m_lo = lo_of(e.mr, e.mi, t.m);
+        return t;
+    }
+    __device__ __forceinline__ V afma(V x, V y) const { return A::fma(al, x, A::fma(al_lo, x, y)); }
+    __device__ __forceinline__ V mmul(V r) const { return A::fma(m, r, A::mul(m_lo, r)); }
+    __device__ __forceinline__ V alpha() const { return al; }
+};
+
+// Copy a kernel's table slice (cnt entries, zero-padded past the line end
+// by the host) into LDS in the working representation; the caller
+// synchronises before reading it.
+template <class T, bool CPLX>
+__device__ __forceinline__ void stage_table(const TabEntry *__restrict__ src, LTab<T, CPLX> *dst, int cnt)
+{
+    for (int q = threadIdx.x; q < cnt; q += blockDim.x) dst[q] = LTab<T, CPLX>::make(src[q]);
+}
+
+// Table entry q from LDS (staged) or from the FP64 table in global memory.
+template <class T, bool CPLX>
+__device__ __forceinline__ LTab<T, CPLX> tab_at(const LTab<T, CPLX> *tb, int q)
+{
+    return tb[q];
+}
+
+template <class T, bool CPLX>
+__device__ __forceinline__ LTab<T, CPLX> tab_at(const TabEntry *tb, int q)
+{
+    return LTab<T, CPLX>::make(tb[q]);
+}
+
+// ---------------------------------------------------------------------------
+// ROW: one x line per line group.  xs: 4 values per wave of the group (LDS,
+// used when MW).  Returns the thread's sum |v|^2 when `last`.
+// ---------------------------------------------------------------------------
+template <class T, bool CPLX, int C, bool MW, class TB>
+__device__ __forceinline__ double row_line(typename Alg<T, CPLX>::V *__restrict__ psi, long long line,
+                                           bool active, int n, const TB *tb, int G, int t, int lane, int wl,
+                                           int wpl, typename Alg<T, CPLX>::V *xs, typename Alg<T, CPLX>::V sig,
+                                           T scale, T dt, T g, const PointParams &pp, int ks, bool last)
+{
+    using A = Alg<T, CPLX>;
+    using V = typename A::V;
+    const int i0 = t * C;
+    const long long base = line * (long long)n;
+
+    V u[C];
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+        const int i = i0 + k;
+        V v = A::zero();
+        if (active && i < n) v = psi[base + i];
+        u[k] = v;
+    }
+
+    // ---- pointwise substep ----
+    T vyz = T(0);
+    if (active) {
+        const int j = (int)(line % pp.n[1]);
+        const int k = (int)(line / pp.n[1]);
+        const T y = coord<T>(j, pp.cen[1], pp.dx[1]);
+        const T z = coord<T>(k, pp.cen[2], pp.dx[2]);
+        vyz = T(pp.w2h[1]) * y * y + T(pp.w2h[2]) * z * z;
+    }
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+        const int i = i0 + k;
+        const T x = coord<T>(i, pp.cen[0], pp.dx[0]);
+        u[k] = apply_point<T, CPLX>(u[k], scale, T(pp.w2h[0]) * x * x + vyz, dt, g);
+    }
+
+    // ---- neighbours across chunk boundaries ----
+    V left = A::shfl_up(u[C - 1], 1);
+    V right = A::shfl_down(u[0], 1);
+    if (lane == 0) left = A::zero();
+    if (lane == 63) right = A::zero();
+    if constexpr (MW) {
+        if (lane == 0) xs[wl * 4 + 0] = u[0];
+        if (lane == 63) xs[wl * 4 + 1] = u[C - 1];
+        __syncthreads();
+        if (lane == 0 && wl > 0) left = xs[(wl - 1) * 4 + 1];
+        if (lane == 63 && wl < wpl - 1) right = xs[(wl + 1) * 4 + 0];
+        __syncthreads();
+    }
+
+    // ---- m_i (1 - sT)u, and the chunk's forward map d -> Ac d + d_loc ----
+    V be[C];
+    V Ac = A::one(), d = A::zero();
+    {
+        V prev = left;
+#pragma unroll
+        for (int k = 0; k < C; ++k) {
+            const V nxt = (k + 1 < C) ? u[k + 1] : right;
+            const V r = cn_rhs<T, CPLX>(prev, u[k], nxt, sig);
+            prev = u[k];
+            const LTab<T, CPLX> e = tab_at<T, CPLX>(tb, k * G + t);
+            be[k] = e.mmul(r);
+            d = e.afma(d, be[k]);
+            Ac = A::mul(e.alpha(), Ac);
+        }
+    }
+
+    // ---- forward: scan of chunk maps over the preceding chunks ----
+    V din;
+    {
+        V PA = Ac, PB = d;
+        for (int s = 0; s < ks; ++s) {
+            const int o = 1 << s;
+            const V a2 = A::shfl_up(PA, o), b2 = A::shfl_up(PB, o);
+            if (lane >= o) {
+                PB = A::fma(PA, b2, PB);
+                PA = A::mul(PA, a2);
+            }
+        }
+        V EA = A::shfl_up(PA, 1), EB = A::shfl_up(PB, 1);
+        if (lane == 0) {
+            EA = A::one();
+            EB = A::zero();
+        }
+        if constexpr (MW) {
+            if (lane == 63) {
+                xs[wl * 4 + 2] = PA;
+                xs[wl * 4 + 3] = PB;
+            }
+            __syncthreads();
+            V Dw = A::zero();
+            for (int q = 0; q < wl; ++q) Dw = A::fma(xs[q * 4 + 2], Dw, xs[q * 4 + 3]);
+            __syncthreads();
+            din = A::fma(EA, Dw, EB);
+        } else {
+            din = EB;
+        }
+    }
+    d = din;
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+        d = tab_at<T, CPLX>(tb, k * G + t).afma(d, be[k]);
+        be[k] = d;
+    }
+
+    // ---- backward ----
+    V v = A::zero();
+#pragma unroll
+    for (int k = C - 1; k >= 0; --k) v = tab_at<T, CPLX>(tb, k * G + t).afma(v, be[k]);
+    V vin;
+    {
+        V PA = Ac, PB = v;
+        for (int s = 0; s < ks; ++s) {
+            const int o = 1 << s;
+            const V a2 = A::shfl_down(PA, o), b2 = A::shfl_down(PB, o);
+            if (lane + o < 64) {
+                PB = A::fma(PA, b2, PB);
+                PA = A::mul(PA, a2);
+            }
+        }
+        V EA = A::shfl_down(PA, 1), EB = A::shfl_down(PB, 1);
+        if (lane == 63) {
+            EA = A::one();
+            EB = A::zero();
+        }
+        if constexpr (MW) {
+            if (lane == 0) {
+                xs[wl * 4 + 2] = PA;
+                xs[wl * 4 + 3] = PB;
+            }
+            __syncthreads();
+            V Vw = A::zero();
+            for (int q = wpl - 1; q > wl; --q) Vw = A::fma(xs[q * 4 + 2], Vw, xs[q * 4 + 3]);
+            __syncthreads();
+            vin = A::fma(EA, Vw, EB);
+        } else {
+            vin = EB;
+        }
+    }
+    v = vin;
+#pragma unroll
+    for (int k = C - 1; k >= 0; --k) {
+        v = tab_at<T, CPLX>(tb, k * G + t).afma(v, be[k]);
+        be[k] = v;
+    }
+
+    // ---- store ----
+    double nacc = 0.0;
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+        const int i = i0 + k;
+        if (active && i < n) {
+            psi[base + i] = be[k];
+            if (last) nacc += A::norm2(be[k]);
+        }
+    }
+    return nacc;
+}
+
+// ---------------------------------------------------------------------------
+// COL: one tile of LPB = 64/L lines, nch = W*L chunks per line.  `line` and
+// `base` are this lane's line and its first point; tb is the staged table;
+// xs0/xs1 hold nch x LPB values each.  Returns sum |v|^2 when `last`.
+// ---------------------------------------------------------------------------
+template <class T, bool CPLX, int C>
+__device__ __forceinline__ double col_tile(typename Alg<T, CPLX>::V *__restrict__ psi, bool active,
+                                           long long base, int n, long long st, int nch, int ch, int LPB, int li,
+                                           const LTab<T, CPLX> *tb, typename Alg<T, CPLX>::V *xs0,
+                                           typename Alg<T, CPLX>::V *xs1, typename Alg<T, CPLX>::V sig, int depth,
+                                           bool last)
+{
+    using A = Alg<T, CPLX>;
+    using V = typename A::V;
+    const int i0 = ch * C;
+    const int qlo = max(0, ch - depth);
+    const int qhi = min(nch - 1, ch + depth);
+
+    V u[C];
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+        const int i = i0 + k;
+        u[k] = (active && i < n) ? psi[base + (long long)i * st] : A::zero();
+    }
+
+    // neighbours from the adjacent chunks
+    xs0[ch * LPB + li] = u[0];
+    xs1[ch * LPB + li] = u[C - 1];
+    __syncthreads();
+    const V left = (ch > 0) ? xs1[(ch - 1) * LPB + li] : A::zero();
+    const V right = (ch + 1 < nch) ? xs0[(ch + 1) * LPB + li] : A::zero();
+    __syncthreads();
+
+    V be[C];
+    V Ac = A::one(), d = A::zero();
+    {
+        V prev = left;
+#pragma unroll
+        for (int k = 0; k < C; ++k) {
+            const V nxt = (k + 1 < C) ? u[k + 1] : right;
+            const V r = cn_rhs<T, CPLX>(prev, u[k], nxt, sig);
+            prev = u[k];
+            const LTab<T, CPLX> e = tab_at<T, CPLX>(tb, i0 + k);
+            be[k] = e.mmul(r);
+            d = e.afma(d, be[k]);
+            Ac = A::mul(e.alpha(), Ac);
+        }
+    }
+    xs0[ch * LPB + li] = Ac;
+    xs1[ch * LPB + li] = d;
+    __syncthreads();
+    V din = A::zero();
+    for (int q = qlo; q < ch; ++q) din = A::fma(xs0[q * LPB + li], din, xs1[q * LPB + li]);
+    __syncthreads();
+    d = din;
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+        d = tab_at<T, CPLX>(tb, i0 + k).afma(d, be[k]);
+        be[k] = d;
+    }
+
+    // backward
+    V v = A::zero();
+#pragma unroll
+    for (int k = C - 1; k >= 0; --k) v = tab_at<T, CPLX>(tb, i0 + k).afma(v, be[k]);
+    xs1[ch * LPB + li] = v;
+    __syncthreads();
+    V vin = A::zero();
+    for (int q = qhi; q > ch; --q) vin = A::fma(xs0[q * LPB + li], vin, xs1[q * LPB + li]);
+    v = vin;
+#pragma unroll
+    for (int k = C - 1; k >= 0; --k) {
+        v = tab_at<T, CPLX>(tb, i0 + k).afma(v, be[k]);
+        be[k] = v;
+    }
+    double nacc = 0.0;
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+        const int i = i0 + k;
+        if (active && i < n) {
+            psi[base + (long long)i * st] = be[k];
+            if (last) nacc += A::norm2(be[k]);
+        }
+    }
+    return nacc;
+}
+
+}  // namespace sscn

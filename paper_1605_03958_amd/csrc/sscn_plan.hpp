@@ -59,6 +59,9 @@ size_t elem_bytes(int elem);
 int validate(const sscn_problem *pb);
 int make_plan(const sscn_problem &pb, const TileOverride *ov, Plan &P);
 void build_table(const sscn_problem &pb, const Plan &P, int a, std::vector<TabEntry> &out);
+// Constant-tail index, constant entry and scan depth of an axis whose kind,
+// n, C, W, L and sigma are set.
+void table_meta(AxisPlan &X, bool fp32);
 // FP64 Thomas coefficients m_i and alpha_i = s m_i of tridiag(-s, 1+2s, -s).
 void thomas_coefs(double s_re, double s_im, int n, std::vector<double> &m_re, std::vector<double> &m_im,
                   std::vector<double> &a_re, std::vector<double> &a_im);

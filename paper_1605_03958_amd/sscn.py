@@ -17,7 +17,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsscn.so")
 
-OK, NOT_CONVERGED = 0, 1
+OK, NOT_CONVERGED, BUSY = 0, 1, 2
 E_INVALID, E_HIP, E_NONFINITE, E_NOSPACE, E_UNSUPPORTED = -1, -2, -3, -4, -5
 IMAG, REAL = 0, 1
 F64, F32 = 0, 1
@@ -62,6 +62,18 @@ class CObs(ctypes.Structure):
     ]
 
 
+class CBatchSlot(ctypes.Structure):
+    _fields_ = [
+        ("state", ctypes.c_int32),
+        ("pad_", ctypes.c_int32),
+        ("steps", ctypes.c_int64),
+        ("last_norm", ctypes.c_double),
+        ("obs", CObs),
+    ]
+
+
+SLOT_EMPTY, SLOT_RUNNING, SLOT_CONVERGED, SLOT_DONE, SLOT_NONFINITE = 0, 1, 2, 3, 4
+
 EXPORTS = {
     "sscn_abi_version": ([], ctypes.c_int),
     "sscn_status_string": ([ctypes.c_int], ctypes.c_char_p),
@@ -83,6 +95,18 @@ EXPORTS = {
     "sscn_destroy": ([ctypes.c_void_p], ctypes.c_int),
     "sscn_density_1d": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
     "sscn_density_2d": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
+    "sscn_batch_ctl_bytes": ([ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "sscn_batch_workspace_bytes": ([ctypes.POINTER(CProblem), ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "sscn_batch_create": ([ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                           ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
+    "sscn_batch_admit": ([ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(CProblem), ctypes.c_void_p,
+                          ctypes.c_void_p, ctypes.c_double, ctypes.c_int64], ctypes.c_int),
+    "sscn_batch_evict": ([ctypes.c_void_p, ctypes.c_int32], ctypes.c_int),
+    "sscn_batch_step": ([ctypes.c_void_p, ctypes.c_int32], ctypes.c_int),
+    "sscn_batch_poll": ([ctypes.c_void_p, ctypes.POINTER(CBatchSlot), ctypes.c_int32, ctypes.c_int32],
+                        ctypes.c_int),
+    "sscn_batch_error": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+    "sscn_batch_destroy": ([ctypes.c_void_p], ctypes.c_int),
 }
 
 _lib = None
@@ -322,6 +346,115 @@ class Solver:
     def close(self) -> None:
         if getattr(self, "_h", None):
             lib().sscn_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------
+# batch
+# ---------------------------------------------------------------------------
+
+def batch_ctl_bytes(max_slots: int, max_items: int) -> int:
+    v = ctypes.c_size_t(0)
+    _check(lib().sscn_batch_ctl_bytes(int(max_slots), int(max_items), ctypes.byref(v)), "sscn_batch_ctl_bytes")
+    return int(v.value)
+
+
+def batch_workspace_bytes(prob: Problem) -> int:
+    pc = prob.c()
+    v = ctypes.c_size_t(0)
+    _check(lib().sscn_batch_workspace_bytes(ctypes.byref(pc), ctypes.byref(v)), "sscn_batch_workspace_bytes")
+    return int(v.value)
+
+
+@dataclass
+class SlotStatus:
+    state: int
+    steps: int
+    last_norm: float
+    obs: Obs
+
+
+class Batch:
+    """A batch of FP32 instances advanced by one persistent launch per step.
+
+    Owns (as torch tensors) the control block and, per admitted slot, the
+    instance state and workspace."""
+
+    def __init__(self, max_slots: int, max_items: int = 1 << 20, device: str = "cuda", stream=None):
+        import torch
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.max_slots = int(max_slots)
+        nb = batch_ctl_bytes(max_slots, max_items)
+        self.ctl = torch.zeros(nb // 8 + 64, dtype=torch.float64, device=self.device)
+        self.psi = [None] * self.max_slots
+        self.ws = [None] * self.max_slots
+        self.prob = [None] * self.max_slots
+        h = ctypes.c_void_p(0)
+        torch.cuda.synchronize(self.device)
+        _check(lib().sscn_batch_create(self.max_slots, int(max_items), ctypes.c_void_p(self.ctl.data_ptr()),
+                                       ctypes.c_size_t(nb), ctypes.c_void_p(self.stream.cuda_stream),
+                                       ctypes.byref(h)), "sscn_batch_create")
+        self._h = h
+
+    def footprint(self, prob: Problem) -> int:
+        """HBM bytes a slot of this problem keeps resident (state + workspace)."""
+        return state_bytes(prob) + batch_workspace_bytes(prob)
+
+    def admit(self, slot: int, prob: Problem, psi0, mu_tol: float = 0.0, max_steps: int = 1 << 40):
+        import torch
+        wsb = batch_workspace_bytes(prob)
+        psi = torch.empty(prob.shape, dtype=prob.torch_dtype(), device=self.device)
+        if isinstance(psi0, torch.Tensor):
+            src = psi0.to(device=self.device, dtype=prob.torch_dtype()).reshape(prob.shape)
+        else:
+            a = np.ascontiguousarray(np.asarray(psi0).reshape(prob.shape))
+            if prob.mode == IMAG and np.iscomplexobj(a):
+                a = a.real
+            src = torch.from_numpy(a.astype(prob.numpy_dtype())).to(self.device)
+        with torch.cuda.stream(self.stream):
+            psi.copy_(src)
+        ws = torch.zeros(wsb // 8 + 32, dtype=torch.float64, device=self.device)
+        self.stream.synchronize()
+        pc = prob.c()
+        _check(lib().sscn_batch_admit(self._h, int(slot), ctypes.byref(pc), ctypes.c_void_p(psi.data_ptr()),
+                                      ctypes.c_void_p(ws.data_ptr()), float(mu_tol), int(max_steps)),
+               "sscn_batch_admit")
+        self.psi[slot], self.ws[slot], self.prob[slot] = psi, ws, prob
+
+    def evict(self, slot: int):
+        """Release a slot; returns its (renormalised) state tensor."""
+        _check(lib().sscn_batch_evict(self._h, int(slot)), "sscn_batch_evict")
+        psi = self.psi[slot]
+        self.psi[slot] = self.ws[slot] = self.prob[slot] = None
+        return psi
+
+    def step(self, nsteps: int) -> None:
+        _check(lib().sscn_batch_step(self._h, int(nsteps)), "sscn_batch_step")
+
+    def poll(self, wait: bool = True):
+        buf = (CBatchSlot * self.max_slots)()
+        rc = lib().sscn_batch_poll(self._h, buf, self.max_slots, 1 if wait else 0)
+        if rc == BUSY:
+            return None
+        _check(rc, "sscn_batch_poll")
+        return [SlotStatus(buf[i].state, int(buf[i].steps), buf[i].last_norm, Obs.from_c(buf[i].obs))
+                for i in range(self.max_slots)]
+
+    def error(self) -> bool:
+        f = ctypes.c_int32(0)
+        _check(lib().sscn_batch_error(self._h, ctypes.byref(f)), "sscn_batch_error")
+        return bool(f.value)
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib().sscn_batch_destroy(self._h)
             self._h = None
 
     def __del__(self):

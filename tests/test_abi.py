@@ -26,7 +26,7 @@ def test_library_exports_every_declared_symbol():
     for name in names:
         assert hasattr(L, name), name
     # and the binding declares a signature for each of them
-    missing = [n for n in names if n not in sscn.EXPORTS and not n.startswith("sscn_batch")]
+    missing = [n for n in names if n not in sscn.EXPORTS]
     assert not missing, missing
 
 
@@ -149,3 +149,25 @@ def test_scan_depth_bounds_neglected_terms(sigma, mode):
         # the tail the kernels read as one constant is constant to round-off
         ic = info[ax]["i_conv"]
         assert np.all(np.abs(m[ic:] - m[-1]) <= 4e-16 * abs(m[-1]))
+
+
+def test_batch_sizes_and_validation():
+    assert sscn.batch_ctl_bytes(64, 100000) >= 100000 * 8
+    with pytest.raises(sscn.SSCNError):
+        sscn.batch_ctl_bytes(0, 10)
+    p = Problem(3, (64, 48, 40), (0.2,) * 3, (1, 1.5, 2), 10.0, 0.004, IMAG, F32, 1, 10)
+    assert sscn.batch_workspace_bytes(p) % 256 == 0
+    with pytest.raises(sscn.SSCNError) as e:   # the batch runs the FP32 forms only
+        sscn.batch_workspace_bytes(Problem(3, (8, 8, 8), (0.2,) * 3, (1, 1, 1), 1.0, 0.004, IMAG, F64, 1, 10))
+    assert e.value.code == sscn.E_UNSUPPORTED
+    with pytest.raises(sscn.SSCNError) as e:   # observation interval needed
+        sscn.batch_workspace_bytes(Problem(1, (64, 1, 1), (0.2,), (1,), 1.0, 0.004, IMAG, F32, 1, 0))
+    assert e.value.code == sscn.E_INVALID
+    # uneven sizes of the batch mix all fit the persistent tiles
+    from paper_1605_03958_amd import inputs
+    for i in range(64):
+        d = inputs.batch_draw(i)
+        for mode in (IMAG, REAL):
+            q = Problem(d.dim, d.n, d.dx, d.omega, d.g, 0.1 * d.dx[0] ** 2, mode, F32,
+                        1 if mode == IMAG else 0, 10)
+            assert sscn.batch_workspace_bytes(q) > 0

@@ -1,0 +1,152 @@
+"""GPU tests of the batched persistent step: FP32 instances of uneven shape
+and dimension, against the FP64 oracle; bitwise independence from the rest of
+the batch; graph replays equal direct launches; isolation of a blown-up
+instance."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1605_03958_amd import inputs, sscn
+from paper_1605_03958_amd.sscn import F32, IMAG, REAL, Problem
+
+pytestmark = pytest.mark.gpu
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, dtype=np.complex128).reshape(-1)
+    b = np.asarray(b, dtype=np.complex128).reshape(-1)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def oprob(p: Problem) -> oracle.Problem:
+    return oracle.Problem(p.dim, p.n, p.dx, p.omega, p.g, p.dt, p.mode, p.renorm_every)
+
+
+def make(dim, n, mode, g=5.0, dx=None, seed=0, observe_every=10):
+    dx = dx or tuple([0.1 if dim == 1 else 0.2] * dim)
+    om = (1.0, 1.5, 2.0)[:dim]
+    h = min(dx)
+    dt = 0.1 * h * h if mode == IMAG else 0.02 * h * h
+    p = Problem(dim, n, dx, om, g, dt, mode, F32, 1 if mode == IMAG else 0, observe_every)
+    if mode == IMAG:
+        psi0 = inputs.ho_gaussian(dim, p.n, p.dx, p.omega, noise=1e-3, seed=seed)
+    else:
+        psi0 = inputs.thomas_fermi(dim, p.n, p.dx, p.omega, 1.25 * g + 1, phase_sigma=0.05, seed=seed)
+    return p, psi0
+
+
+# shapes that exercise every tile variant of the persistent kernel
+MIX = [
+    (1, (64, 1, 1), IMAG), (1, (300, 1, 1), IMAG), (1, (1000, 1, 1), IMAG), (1, (3000, 1, 1), IMAG),
+    (1, (12000, 1, 1), IMAG), (1, (500, 1, 1), REAL), (1, (6000, 1, 1), REAL), (1, (9000, 1, 1), REAL),
+    (2, (40, 50, 1), IMAG), (2, (64, 130, 1), REAL), (2, (70, 700, 1), IMAG), (2, (33, 600, 1), REAL),
+    (3, (20, 24, 30), IMAG), (3, (16, 20, 12), REAL), (3, (48, 49, 50), IMAG),
+]
+
+
+def run_batch(cases, steps, stream=None, slots=None):
+    b = sscn.Batch(len(cases) if slots is None else max(slots) + 1, stream=stream)
+    slots = slots or list(range(len(cases)))
+    for s, (p, psi0) in zip(slots, cases):
+        b.admit(s, p, psi0, mu_tol=0.0, max_steps=steps)
+    b.step(steps)
+    st = b.poll(wait=True)
+    assert not b.error()
+    out = [b.evict(s).cpu().numpy() for s in slots]
+    b.close()
+    return out, [st[s] for s in slots]
+
+
+def test_batch_matches_oracle_across_tile_variants():
+    cases = [make(d, n, m, seed=i) for i, (d, n, m) in enumerate(MIX)]
+    steps = 30
+    got, st = run_batch(cases, steps)
+    for (p, psi0), g, s in zip(cases, got, st):
+        print(f"dim={p.dim} n={p.n} mode={p.mode}", flush=True)
+        assert s.state == sscn.SLOT_DONE and s.steps == steps
+        ref = oracle.run(oprob(p), psi0, steps).psi
+        assert rel_l2(g, ref) <= 5e-5, (p.n, p.mode, rel_l2(g, ref))
+        orf = oracle.observe(oprob(p), ref)
+        assert abs(s.obs.mu - orf.mu) <= 1e-5 * max(1.0, abs(orf.mu))
+
+
+def test_alone_equals_in_the_mix_bitwise():
+    a = make(3, (20, 24, 30), IMAG, seed=3)
+    r = make(2, (64, 130, 1), REAL, seed=4)
+    others = [make(d, n, m, seed=10 + i) for i, (d, n, m) in enumerate(MIX[:6])]
+    alone, _ = run_batch([a, r], 25, slots=[5, 9])
+    mix, _ = run_batch(others[:3] + [a] + others[3:] + [r], 25)
+    assert np.array_equal(alone[0], mix[3])
+    assert np.array_equal(alone[1], mix[7])
+
+
+def test_graph_replays_equal_direct_launches():
+    import torch
+    cases = [make(d, n, m, seed=20 + i) for i, (d, n, m) in enumerate(MIX[8:14])]
+    s = torch.cuda.Stream()
+    b = sscn.Batch(len(cases), stream=s)
+    for i, (p, psi0) in enumerate(cases):
+        b.admit(i, p, psi0, mu_tol=0.0, max_steps=40)
+    for _ in range(4):          # four replays of the same 10-step graph
+        b.step(10)
+        b.poll(wait=True)
+        torch.zeros(1000, device="cuda").sum().item()   # unrelated eager work in between
+    assert not b.error()
+    graph = [b.evict(i).cpu().numpy() for i in range(len(cases))]
+    b.close()
+    direct, _ = run_batch(cases, 40, stream=torch.cuda.default_stream())
+    for g, d in zip(graph, direct):
+        assert np.array_equal(g, d)
+
+
+def test_blown_up_instance_is_isolated():
+    good = [make(d, n, m, seed=30 + i) for i, (d, n, m) in enumerate(MIX[8:12])]
+    p, psi0 = make(2, (40, 50, 1), IMAG, seed=40)
+    bad = psi0.copy()
+    bad[0, 20, 20] = np.nan
+    ref, _ = run_batch(good, 20)
+    got, st = run_batch(good[:2] + [(p, bad)] + good[2:], 20)
+    assert st[2].state == sscn.SLOT_NONFINITE and st[2].steps == 1
+    for i, j in ((0, 0), (1, 1), (2, 3), (3, 4)):
+        assert np.array_equal(ref[i], got[j])
+
+
+def test_ground_state_stops_like_the_oracle():
+    p, psi0 = make(2, (48, 40, 1), IMAG, g=10.0, dx=(0.3, 0.3), seed=7)
+    b = sscn.Batch(1)
+    b.admit(0, p, psi0, mu_tol=1e-5, max_steps=200000)
+    for _ in range(200):
+        b.step(100)
+        st = b.poll(wait=True)[0]
+        if st.state != sscn.SLOT_RUNNING:
+            break
+    assert st.state == sscn.SLOT_CONVERGED
+    psi = b.evict(0).cpu().numpy()
+    r = oracle.run(oprob(p), psi0, 200000, observe_every=10, mu_tol=1e-5)
+    assert r.converged
+    print(f"batch stop {st.steps} oracle stop {r.steps} mu {st.obs.mu} oracle {r.trace[-1, 2]}", flush=True)
+    assert abs(st.steps - r.steps) <= 0.1 * r.steps
+    assert abs(st.obs.mu - r.trace[-1, 2]) <= 1e-4
+    n = np.prod(p.dx[:2]) * np.sum(np.abs(psi.astype(np.float64)) ** 2)
+    assert abs(n - 1) <= 1e-5          # evict applied the pending renormalisation
+
+
+def test_batch_equals_single_problem_fp32():
+    """Same arithmetic as the single-problem kernels (only the order of the
+    norm partial sums differs)."""
+    p, psi0 = make(3, (32, 30, 28), IMAG, seed=8)
+    got, _ = run_batch([(p, psi0)], 25)
+    s = sscn.Solver(p, psi0)
+    s.step(25)
+    single = s.state()
+    s.close()
+    assert rel_l2(got[0], single) <= 1e-6
+
+
+def test_work_list_capacity_is_enforced():
+    b = sscn.Batch(2, max_items=10)
+    p, psi0 = make(3, (20, 24, 30), IMAG)
+    with pytest.raises(sscn.SSCNError) as e:
+        b.admit(0, p, psi0)
+    assert e.value.code == sscn.E_NOSPACE
+    b.close()
