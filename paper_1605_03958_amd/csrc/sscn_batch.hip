@@ -33,22 +33,24 @@ __device__ __forceinline__ void batch_row(const BInst &I, const BState &S, int t
     LTab<T, CPLX> *tl = reinterpret_cast<LTab<T, CPLX> *>(lds);
     V *xs = reinterpret_cast<V *>(lds) + lb * X.wpl * 4;
     if constexpr (!MW) {
-        stage_table<T, CPLX>(X.lt.tab, tl, C * 64);
+        stage_table<T, CPLX>(X.lt, tl, C * 64, 64, C);
         __syncthreads();
     }
-    const long long line = (long long)tile * X.lpi + lb;
-    const bool active = line < X.nlines;
     const V sig = A::coef(X.sig_re, X.sig_im);
     const T scale = CPLX ? T(1) : T(S.scale);
     V *psi = reinterpret_cast<V *>(I.psi);
-    double nacc;
-    if constexpr (MW)
-        nacc = row_line<T, CPLX, C, true>(psi, line, active, X.lt.n, X.lt.tab, G, t, lane, wl, X.wpl, xs, sig,
-                                          scale, T(I.pp.dt), T(I.pp.g), I.pp, X.lt.depth, last);
-    else
-        nacc = row_line<T, CPLX, C, false>(psi, line, active, X.lt.n, static_cast<const LTab<T, CPLX> *>(tl), G,
-                                           t, lane, wl, 1, xs, sig, scale, T(I.pp.dt), T(I.pp.g), I.pp,
-                                           X.lt.depth, last);
+    double nacc = 0.0;
+    for (int r = 0; r < X.rep; ++r) {
+        const long long line = ((long long)tile * X.rep + r) * X.lpi + lb;
+        const bool active = line < X.nlines;
+        if constexpr (MW)
+            nacc += row_line<T, CPLX, C, true>(psi, line, active, X.lt.n, X.lt.tab, G, t, lane, wl, X.wpl, xs, sig,
+                                               scale, T(I.pp.dt), T(I.pp.g), I.pp, X.lt.depth, last);
+        else
+            nacc += row_line<T, CPLX, C, false>(psi, line, active, X.lt.n, static_cast<const LTab<T, CPLX> *>(tl),
+                                                G, t, lane, wl, 1, xs, sig, scale, T(I.pp.dt), T(I.pp.g), I.pp,
+                                                X.lt.depth, last);
+    }
     if (last) {
         const double s = block_sum(nacc, red);
         if (tid == 0) I.norm_part[tile] = s;
@@ -75,14 +77,18 @@ __device__ __forceinline__ void batch_col(const BInst &I, int axis, int tile, un
     LTab<T, CPLX> *tb = reinterpret_cast<LTab<T, CPLX> *>(lds);
     V *xs0 = reinterpret_cast<V *>(tb + nch * C) + st_i * (2 * nch * LPB);
     V *xs1 = xs0 + nch * LPB;
-    const long long line = ((long long)tile * X.tpi + st_i) * LPB + li;
-    const bool active = line < X.nlines;
-    long long base = 0;
-    if (active) base = (line % X.m1) * X.s1 + (line / X.m1) * X.s2;
-    stage_table<T, CPLX>(X.lt.tab, tb, nch * C);
-    const double nacc = col_tile<T, CPLX, C>(reinterpret_cast<V *>(I.psi), active, base, X.lt.n, X.stride, nch,
-                                             ch, LPB, li, tb, xs0, xs1, A::coef(X.sig_re, X.sig_im), X.lt.depth,
-                                             last);
+    stage_table<T, CPLX>(X.lt, tb, nch * C, 0, C);
+    double nacc = 0.0;
+    for (int r = 0; r < X.rep; ++r) {
+        // the previous set's last LDS reads finish before the next set's writes
+        if (r > 0) __syncthreads();
+        const long long line = (((long long)tile * X.rep + r) * X.tpi + st_i) * LPB + li;
+        const bool active = line < X.nlines;
+        long long base = 0;
+        if (active) base = (line % X.m1) * X.s1 + (line / X.m1) * X.s2;
+        nacc += col_tile<T, CPLX, C>(reinterpret_cast<V *>(I.psi), active, base, X.lt.n, X.stride, nch, ch, LPB,
+                                     li, tb, xs0, xs1, A::coef(X.sig_re, X.sig_im), X.lt.depth, last);
+    }
     if (last) {
         const double s = block_sum(nacc, red);
         if (threadIdx.x == 0) I.norm_part[tile] = s;
@@ -285,8 +291,9 @@ __global__ void __launch_bounds__(BATCH_BLOCK) k_batch_step(BatchArgs a)
                     }
                 }
             }
+            // thread 0's acquire invalidated this CU's caches; the barrier
+            // orders the other waves' reads after it
             __syncthreads();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
 
         if (w.pass <= BP_Z) {
@@ -300,7 +307,8 @@ __global__ void __launch_bounds__(BATCH_BLOCK) k_batch_step(BatchArgs a)
         }
 
         if (w.pass < BP_FIN) {
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            // the barrier makes every wave's stores visible to thread 0, whose
+            // agent-scope release (one L2 write-back per item) publishes them
             __syncthreads();
             if (threadIdx.x == 0)
                 __hip_atomic_fetch_add(a.done + (size_t)w.slot * 4 + w.pass, 1, __ATOMIC_RELEASE,

@@ -35,12 +35,12 @@ struct BAxis {
     int32_t lpi;       // ROW: lines per item (16 / wpl)
     int32_t W, L;      // COL: waves and lanes per line of one sub-tile
     int32_t tpi;       // COL: sub-tiles per item (16 / W)
+    int32_t rep;       // line groups (ROW) or sub-tile sets (COL) per item
     int32_t ntiles;    // items of this pass
     int64_t nlines;
     int64_t stride;
     int64_t s1, s2;
     int32_t m1;
-    int32_t pad_;
     double sig_re, sig_im;
     LineTab lt;        // table in the instance workspace
 };

@@ -110,7 +110,11 @@ int batch_plan(const sscn_problem &pb, BPlan &B)
             X.lpb = 16 / wpl;
             X.tab_entries = (size_t)c * 64 * wpl;
             Y.lpi = X.lpb;
-            Y.ntiles = (int)cdiv(X.nlines, X.lpb);
+            // items of about 32K points: several line groups per item
+            const int64_t units = cdiv(X.nlines, X.lpb);
+            Y.rep = (int)std::max<int64_t>(1, std::min<int64_t>(8, 32768 / std::max<int64_t>(1, (int64_t)X.lpb * n)));
+            Y.rep = (int)std::min<int64_t>(Y.rep, units);
+            Y.ntiles = (int)cdiv(units, Y.rep);
             lds = std::max(lds, wpl == 1 ? (size_t)c * 64 * ltab_size(cplx) : (size_t)16 * 4 * S);
         } else {
             X.kind = K_COL;
@@ -133,8 +137,11 @@ int batch_plan(const sscn_problem &pb, BPlan &B)
             X.L = L;
             X.tab_entries = (size_t)W * L * c;
             Y.tpi = 16 / W;
-            const int64_t lines_per_item = (int64_t)Y.tpi * (64 / L);
-            Y.ntiles = (int)cdiv(X.nlines, lines_per_item);
+            const int64_t lines_per_set = (int64_t)Y.tpi * (64 / L);
+            const int64_t units = cdiv(X.nlines, lines_per_set);
+            Y.rep = (int)std::max<int64_t>(1, std::min<int64_t>(8, 32768 / std::max<int64_t>(1, lines_per_set * n)));
+            Y.rep = (int)std::min<int64_t>(Y.rep, units);
+            Y.ntiles = (int)cdiv(units, Y.rep);
             lds = std::max(lds, (size_t)W * L * c * ltab_size(cplx) + (size_t)Y.tpi * 2 * W * 64 * S);
         }
         table_meta(X, true);
@@ -504,14 +511,20 @@ int sscn_batch_step(sscn_batch *b, int32_t nsteps)
     if (b->dirty && upload_items(b) != hipSuccess) return SSCN_E_HIP;
     if (nsteps > 0 && b->total > 0) {
         const bool big = batch_big(b);
-        const int grid = big ? b->grid_big : b->grid_small;
+        // no more blocks than items: a block that finds no item still costs a
+        // dispatch and two atomics on the shared counters
+        const int grid = std::min(big ? b->grid_big : b->grid_small, (int)b->total);
         const BatchArgs a = batch_args(b);
         if (b->st == nullptr) {
             for (int k = 0; k < nsteps; ++k)
                 if (launch_batch_step(a, big, grid, kBatchLds, b->st) != hipSuccess) return SSCN_E_HIP;
         } else {
-            const auto key = std::make_pair(nsteps, big ? 1 : 0);
+            const auto key = std::make_pair(nsteps, big ? -grid : grid);
             auto it = b->graphs.find(key);
+            if (it == b->graphs.end() && b->graphs.size() >= 16) {
+                for (auto &kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
+                b->graphs.clear();
+            }
             if (it == b->graphs.end()) {
                 hipGraph_t g = nullptr;
                 hipGraphExec_t ex = nullptr;

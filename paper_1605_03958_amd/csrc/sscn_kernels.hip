@@ -45,7 +45,7 @@ __global__ void __launch_bounds__(MW ? 1024 : 256) k_row(RowArgs a)
     double nacc = 0.0;
 
     if constexpr (!MW) {
-        stage_table<T, CPLX>(a.lt.tab, tl, C * G);
+        stage_table<T, CPLX>(a.lt, tl, C * G, G, C);
         __syncthreads();
     }
     for (long long gb = (long long)blockIdx.x * a.lpb; gb < a.nlines;
@@ -92,7 +92,7 @@ __global__ void __launch_bounds__(1024) k_col(ColArgs a)
     const bool active = line < a.nlines;
     long long base = 0;
     if (active) base = (line % a.m1) * a.s1 + (line / a.m1) * a.s2;
-    stage_table<T, CPLX>(a.lt.tab, tb, nch * C);
+    stage_table<T, CPLX>(a.lt, tb, nch * C, 0, C);
     const double nacc = col_tile<T, CPLX, C>(reinterpret_cast<V *>(a.psi), active, base, a.lt.n, a.stride, nch, ch,
                                              LPB, li, tb, xs0, xs1, A::coef(a.sig_re, a.sig_im), a.lt.depth,
                                              LAST);

@@ -161,13 +161,24 @@ struct LTab<float, CPLX> {
     __device__ __forceinline__ V alpha() const { return al; }
 };
 
-// Copy a kernel's table slice (cnt entries, zero-padded past the line end
-// by the host) into LDS in the working representation; the caller
-// synchronises before reading it.
+// Fill a kernel's table slice in LDS (cnt entries) in the working
+// representation; the caller synchronises before reading it.  Slot q holds
+// line point i = pos(q) (ROW: lane-major, i = (q % G) * C + q / G with G =
+// group threads; COL: i = q).  Only the head of the table below lt.i_conv
+// is read from memory; the constant tail is written from lt's constant
+// entry and points past the line end get zeros.
 template <class T, bool CPLX>
-__device__ __forceinline__ void stage_table(const TabEntry *__restrict__ src, LTab<T, CPLX> *dst, int cnt)
+__device__ __forceinline__ void stage_table(const LineTab &lt, LTab<T, CPLX> *dst, int cnt, int G, int C)
 {
-    for (int q = threadIdx.x; q < cnt; q += blockDim.x) dst[q] = LTab<T, CPLX>::make(src[q]);
+    const LTab<T, CPLX> tail = LTab<T, CPLX>::make(TabEntry{lt.ac_re, lt.ac_im, lt.mc_re, lt.mc_im});
+    const LTab<T, CPLX> zero = LTab<T, CPLX>::make(TabEntry{0.0, 0.0, 0.0, 0.0});
+    for (int q = threadIdx.x; q < cnt; q += blockDim.x) {
+        const int i = (G > 0) ? (q % G) * C + q / G : q;
+        LTab<T, CPLX> e = tail;
+        if (i >= lt.n) e = zero;
+        else if (i < lt.i_conv) e = LTab<T, CPLX>::make(lt.tab[q]);
+        dst[q] = e;
+    }
 }
 
 // Table entry q from LDS (staged) or from the FP64 table in global memory.
