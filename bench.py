@@ -6,6 +6,9 @@ dx = 0.1, dt = 0.02 dx^2, trap (1, 1.5, 2), initial Thomas-Fermi profile of
 g = 100 times a seeded random phase (sigma 0.05), propagated with g = 80.
 The same workload in complex64 (FP32 sweeps, FP64 tables and reductions) is
 timed beside it.  Inputs are resident in HBM before the timed region.
+Beside them: the 64-instance uneven batch run to convergence (aggregate
+grid-point-steps/s), and the serving loop under Poisson arrivals (p50/p99
+latency and throughput).
 
 Prints one JSON line (see the design doc for the fields).
 """
@@ -23,6 +26,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "SSCN grid-point-steps/s at 256^3 FP64 vs FP32; p50/p99 batched solve latency"
 HBM_PEAK_GBS = 8000.0
+# Poisson arrival rate of the serving run (requests/s): about 0.7 of the
+# request throughput the server sustains on the same mix when every request
+# is submitted at once
+SERVE_RATE = 19.0
 
 
 def c1_problem(prec):
@@ -105,6 +112,119 @@ def cpu_baseline(target_s: float = 12.0):
                       f"FP64 C oracle with OpenMP over lines"}
 
 
+def c3_problems():
+    """The 64-instance uneven batch: 22 1D, 21 2D, 21 3D draws (seeds 100+i),
+    imaginary time in FP32 with FP64 reductions, dt = 0.1 dx^2."""
+    from paper_1605_03958_amd import inputs
+    from paper_1605_03958_amd.sscn import F32, IMAG, Problem
+    out = []
+    for i in range(64):
+        d = inputs.batch_draw(i)
+        h = d.dx[0]
+        p = Problem(d.dim, d.n, d.dx[:d.dim], d.omega[:d.dim], d.g, 0.1 * h * h, IMAG, F32, 1, 10)
+        out.append((d, p))
+    return out
+
+
+def batch_c3(tick: int = 100, cap: int = 300000, time_limit: float = 60.0):
+    """All 64 instances admitted at once and run to |delta mu| < 1e-6; each
+    is evicted when it stops.  Also times the first steps, while all 64 run,
+    against the HBM roofline (2 d S bytes per point-step)."""
+    import numpy as np
+    import torch
+    from paper_1605_03958_amd import inputs, sscn
+    probs = c3_problems()
+    st = torch.cuda.Stream()
+    b = sscn.Batch(64, stream=st)
+    for i, (d, p) in enumerate(probs):
+        b.admit(i, p, inputs.ho_gaussian(d.dim, d.n, d.dx, d.omega, noise=1e-3, seed=d.seed), mu_tol=1e-6,
+                max_steps=cap)
+    pts = np.array([p.points for _, p in probs], dtype=np.float64)
+    dims = np.array([p.dim for _, p in probs])
+    done = {}
+    t0 = time.perf_counter()
+    # while all 64 run: 20 warm-up launches (the graph is captured), then 20
+    # timed ones; solo 1D instances take several steps per launch, so the
+    # work is counted from the step counters
+    b.step(20)
+    s0 = b.poll(wait=True)
+    ta = time.perf_counter()
+    b.step(20)
+    s = b.poll(wait=True)
+    t_all = time.perf_counter() - ta
+    d_steps = np.array([x.steps - y.steps for x, y in zip(s, s0)], dtype=np.float64)
+    allact = {"launches": 20, "ms_per_launch": 1e3 * t_all / 20,
+              "ptsteps_per_s": float((d_steps * pts).sum()) / t_all,
+              "hbm_frac": float((d_steps * pts * 2 * dims * 4).sum()) / t_all / (HBM_PEAK_GBS * 1e9),
+              "all_running": all(x.state == sscn.SLOT_RUNNING for x in s)}
+    while len(done) < 64 and time.perf_counter() - t0 < time_limit:
+        now = time.perf_counter()
+        for i, x in enumerate(s):
+            if i in done or x.state == sscn.SLOT_EMPTY:
+                continue
+            if x.state != sscn.SLOT_RUNNING:
+                done[i] = (x.state, x.steps, now - t0)
+                b.evict(i)
+        if len(done) == 64:
+            break
+        b.step(tick)
+        s = b.poll(wait=True)
+    el = time.perf_counter() - t0
+    err = b.error()
+    b.close()
+    steps = np.array([done[i][1] if i in done else 0 for i in range(64)], dtype=np.float64)
+    ptsteps = float((steps * pts).sum())
+    byts = float((steps * pts * 2 * dims * 4).sum())
+    conv = sum(1 for v in done.values() if v[0] == sscn.SLOT_CONVERGED)
+    t_done = np.array([done[i][2] for i in sorted(done)])
+    return {
+        "instances": 64, "converged": conv, "finished": len(done), "error_flag": bool(err),
+        "elapsed_s": el, "ptsteps": ptsteps, "ptsteps_per_s": ptsteps / el,
+        "hbm_frac_whole_run": byts / el / (HBM_PEAK_GBS * 1e9),
+        "all_active": allact,
+        "steps_min_median_max": [int(steps.min()), int(np.median(steps)), int(steps.max())],
+        "steps_by_dim_median": {str(d): int(np.median(steps[dims == d])) for d in (1, 2, 3)},
+        "done_time_median_max_s": [float(np.median(t_done)), float(t_done.max())] if len(t_done) else None,
+    }
+
+
+def serving_c4(count: int, rate: float, budget_gib: float, tick: int = 20, slots: int = 64):
+    """Poisson arrivals of ground-state (70 %) and dynamics (30 %) requests
+    drawn like the batch mix, served with continuous batching under an HBM
+    budget; latency is submission -> completion seen by the server."""
+    import threading
+    from paper_1605_03958_amd import inputs, serve
+    reqs = inputs.request_stream(count, rate, seed=200)
+    srv = serve.Server(int(budget_gib * (1 << 30)), max_slots=slots, tick_steps=tick)
+    box = {}
+
+    def client():
+        box["futs"], box["late"] = serve.drive(srv, reqs)
+        srv.close()
+
+    t0 = time.perf_counter()
+    srv.start()
+    th = threading.Thread(target=client)
+    th.start()
+    th.join()
+    srv.join()
+    t1 = time.perf_counter()
+    res = [f.result() for f in box["futs"]]
+    srv.ex.close()
+    st = serve.latency_stats(res, t0, t1)
+    work = sum(r.steps * r.points for r in res)
+    st.update({
+        "rate_per_s": rate, "budget_gib": budget_gib, "tick_steps": tick, "slots": slots,
+        "offered_ptsteps_per_s": rate * work / len(res),
+        "peak_running": srv.peak_running, "peak_bytes": srv.peak_bytes,
+        "submit_lateness_max_s": max(box["late"]),
+        "converged": sum(1 for r in res if r.kind == serve.GROUND and r.status == 2),
+        "ground": sum(1 for r in res if r.kind == serve.GROUND),
+        "nonfinite": sum(1 for r in res if r.status == 4),
+    })
+    return st
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -114,6 +234,11 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--only", choices=["fp64", "fp32"], default=None,
                     help="run only one precision (profiling runs)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance batch")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving loop")
+    ap.add_argument("--serve-requests", type=int, default=512)
+    ap.add_argument("--serve-rate", type=float, default=SERVE_RATE, help="Poisson arrivals per second")
+    ap.add_argument("--serve-budget-gib", type=float, default=32.0, help="HBM budget of the serving loop")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -180,6 +305,13 @@ def main():
                        "speedup_vs_fp64": f["pts"] / m["pts"], "kernel_ms": {k: round(v, 5) for k, v in f["kernels"].items()},
                        "state": "complex64"}
     res["copy_gbs"] = copy_bandwidth(m["S"] * m["points"])
+    if args.only is None and not args.no_batch:
+        res["batch"] = batch_c3()
+    if args.only is None and not args.no_serve:
+        sv = serving_c4(args.serve_requests, args.serve_rate, args.serve_budget_gib)
+        res["serving"] = sv
+        res["p50_latency_s"] = sv["p50_s"]
+        res["p99_latency_s"] = sv["p99_s"]
     if not args.no_cpu and args.only is None:
         res["cpu_baseline"] = cpu_baseline()
     print(json.dumps(res), flush=True)

@@ -259,7 +259,9 @@ __global__ void __launch_bounds__(BATCH_BLOCK) k_batch_step(BatchArgs a)
     __shared__ double red[16];
     __shared__ double redq[BATCH_NOBS][16];
     __shared__ int s_item;
+    __shared__ int s_go;
     const int total = a.ctl->total_items;
+    const int solo_min = a.ctl->solo_min;
     for (;;) {
         __syncthreads();
         if (threadIdx.x == 0) s_item = atomicAdd(&a.ctl->ticket, 1);
@@ -270,9 +272,10 @@ __global__ void __launch_bounds__(BATCH_BLOCK) k_batch_step(BatchArgs a)
         const BInst &I = a.inst[w.slot];
         BState &S = a.state[w.slot];
         if (S.status != BS_RUNNING) continue;
+        const bool solo = w.pass == BP_SOLO;
 
         // wait until the instance's previous pass has completed (bounded)
-        const int dep = I.dep[w.pass];
+        const int dep = solo ? -1 : I.dep[w.pass];
         if (dep >= 0) {
             if (threadIdx.x == 0) {
                 int32_t *cnt = a.done + (size_t)w.slot * 4 + dep;
@@ -296,14 +299,37 @@ __global__ void __launch_bounds__(BATCH_BLOCK) k_batch_step(BatchArgs a)
             __syncthreads();
         }
 
-        if (w.pass <= BP_Z) {
-            if (I.elem == 1) batch_sweep<float, false, BIG>(I, S, w.pass, w.tile, lds_raw, red);
-            else batch_sweep<float, true, BIG>(I, S, w.pass, w.tile, lds_raw, red);
-        } else if (w.pass == BP_OBS) {
-            if (I.elem == 1) batch_obs<float, false>(I, S, w.tile, redq);
-            else batch_obs<float, true>(I, S, w.tile, redq);
-        } else {
-            batch_fin(I, S, red);
+        // A solo item cycles x solve -> observation -> finalisation of its
+        // single tile, whole steps in a row, with block barriers in place of
+        // the counters (the block's waves share one CU, so a barrier orders
+        // their global stores and loads).  It repeats while the instance
+        // runs, up to BATCH_SOLO_MAX steps, and past solo_min steps only
+        // while items of the launch are still unclaimed.
+        int pass = solo ? BP_X : w.pass;
+        for (int k = 1;;) {
+            if (pass <= BP_Z) {
+                if (I.elem == 1) batch_sweep<float, false, BIG>(I, S, pass, w.tile, lds_raw, red);
+                else batch_sweep<float, true, BIG>(I, S, pass, w.tile, lds_raw, red);
+            } else if (pass == BP_OBS) {
+                if (I.elem == 1) batch_obs<float, false>(I, S, w.tile, redq);
+                else batch_obs<float, true>(I, S, w.tile, redq);
+            } else {
+                batch_fin(I, S, red);
+            }
+            if (!solo) break;
+            __syncthreads();
+            if (pass == BP_FIN) {
+                if (threadIdx.x == 0) {
+                    bool go = S.status == BS_RUNNING && k < BATCH_SOLO_MAX;
+                    if (go && k >= solo_min)
+                        go = __hip_atomic_load(&a.ctl->ticket, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < total;
+                    s_go = go ? 1 : 0;
+                }
+                __syncthreads();
+                if (!s_go) break;
+                ++k;
+            }
+            pass = pass == BP_X ? BP_OBS : pass == BP_OBS ? BP_FIN : BP_X;
         }
 
         if (w.pass < BP_FIN) {
@@ -315,18 +341,31 @@ __global__ void __launch_bounds__(BATCH_BLOCK) k_batch_step(BatchArgs a)
                                        __HIP_MEMORY_SCOPE_AGENT);
         }
     }
-    // the last block out resets the counters for the next launch
+    // the last block out resets the counters for the next launch and sets
+    // solo_min from whether any instance other than a solo one still runs
     if (threadIdx.x == 0) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         const int prev = atomicAdd(&a.ctl->exited, 1);
-        if (prev == (int)gridDim.x - 1) {
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            const int nd = a.ctl->max_slots * 4;
-            for (int q = 0; q < nd; ++q) a.done[q] = 0;
-            a.ctl->ticket = 0;
-            a.ctl->exited = 0;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        }
+        s_go = prev == (int)gridDim.x - 1;
+        if (s_go) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+    if (!s_go) return;
+    const int ns = a.ctl->max_slots;
+    int regular = 0;
+    for (int q = threadIdx.x; q < ns; q += blockDim.x) {
+        a.done[4 * q + 0] = 0;
+        a.done[4 * q + 1] = 0;
+        a.done[4 * q + 2] = 0;
+        a.done[4 * q + 3] = 0;
+        if (a.state[q].status == BS_RUNNING && !a.inst[q].solo) regular = 1;
+    }
+    regular = __syncthreads_or(regular);
+    if (threadIdx.x == 0) {
+        a.ctl->solo_min = regular ? 1 : BATCH_SOLO_ONLY;
+        a.ctl->ticket = 0;
+        a.ctl->exited = 0;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     }
 }
 

@@ -11,6 +11,13 @@
 // next launch (or graph replay) starts clean.  Tile shapes depend only on an
 // instance's own shape and every reduction has fixed slots and a fixed
 // order: an instance's results do not depend on what else is in the batch.
+//
+// A 1D instance whose line fits one block is a solo instance: one item runs
+// its whole step (line solve, observation sums, finalisation) inside one
+// block, with block barriers in place of the counters, and repeats steps
+// while other items of the launch are still unclaimed (at least
+// BCtl::solo_min and at most BATCH_SOLO_MAX steps per launch).  The steps are the same arithmetic
+// either way, so only the number of steps a launch advances it varies.
 #pragma once
 
 #include <stdint.h>
@@ -20,12 +27,14 @@
 
 namespace sscn {
 
-enum { BP_X = 0, BP_Y = 1, BP_Z = 2, BP_OBS = 3, BP_FIN = 4, BP_NPASS = 5 };
+enum { BP_X = 0, BP_Y = 1, BP_Z = 2, BP_OBS = 3, BP_FIN = 4, BP_NPASS = 5, BP_SOLO = 5 };
 enum { BS_EMPTY = 0, BS_RUNNING = 1, BS_CONVERGED = 2, BS_DONE = 3, BS_NONFINITE = 4, BS_STALLED = 5 };
 
 constexpr int BATCH_BLOCK = 1024;     // threads per block of the persistent kernel
 constexpr int BATCH_OBS_PTS = 16384;  // grid points per observation tile
 constexpr int BATCH_NOBS = 10;        // FP64 sums per observation tile
+constexpr int BATCH_SOLO_MAX = 256;   // steps of a solo instance per launch, at most
+constexpr int BATCH_SOLO_ONLY = 64;   // ... and at least, once only solo instances run
 
 // Geometry of one axis of one instance (see sscn_lines.hpp for ROW / COL).
 struct BAxis {
@@ -64,6 +73,7 @@ struct BInst {
     int32_t last_pass;     // BP_X + dim - 1
     int32_t dep[BP_NPASS]; // pass an item of this pass waits for (-1: none)
     int32_t need[BP_NPASS];// tiles of that pass
+    int32_t solo;          // whole step in one item (1D, one line, one observation tile)
 };
 
 // Dynamic per-instance state (device-written by the finalisation item).
@@ -92,7 +102,8 @@ struct BCtl {
     int32_t total_items;
     int32_t error;         // set when a bounded wait gave up
     int32_t max_slots;
-    int32_t pad_[3];
+    int32_t solo_min;      // steps a solo item takes before it may stop early
+    int32_t pad_[2];
 };
 
 struct BatchArgs {

@@ -233,6 +233,10 @@ static int64_t count_items(const sscn_batch *b)
     for (int i = 0; i < b->max_slots; ++i) {
         if (!b->used[i]) continue;
         const BInst &I = b->h_inst[i];
+        if (I.solo) {
+            t += 1;
+            continue;
+        }
         for (int a = 0; a < I.dim; ++a) t += I.ax[a].ntiles;
         t += I.obs_tiles + 1;
     }
@@ -247,9 +251,13 @@ static void build_items(sscn_batch *b)
     // larger instances first inside each pass (longest-processing-time order)
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return b->work[x] > b->work[y]; });
     int32_t t = 0;
+    // solo instances first: their items never wait and overlap the rest
+    for (int i : order)
+        if (b->h_inst[i].solo) b->h_items[t++] = BItem{(uint16_t)i, (uint8_t)BP_SOLO, 0, 0};
     for (int pass = BP_X; pass <= BP_FIN; ++pass)
         for (int i : order) {
             const BInst &I = b->h_inst[i];
+            if (I.solo) continue;
             int nt = 0;
             if (pass <= BP_Z) nt = (pass < I.dim) ? I.ax[pass].ntiles : 0;
             else if (pass == BP_OBS) nt = I.obs_tiles;
@@ -265,12 +273,18 @@ static hipError_t upload_items(sscn_batch *b)
     if (e != hipSuccess) return e;
     build_items(b);
     *b->h_total = b->total;
+    bool regular = false;
+    for (int i = 0; i < b->max_slots; ++i)
+        if (b->used[i] && !b->h_inst[i].solo) regular = true;
+    b->h_total[2] = regular ? 1 : BATCH_SOLO_ONLY;
     if (b->total > 0) {
         e = hipMemcpyAsync(b->ctl + b->lay.items, b->h_items, sizeof(BItem) * (size_t)b->total,
                            hipMemcpyHostToDevice, b->st);
         if (e != hipSuccess) return e;
     }
     e = hipMemcpyAsync(&ctl_of(b)->total_items, b->h_total, sizeof(int32_t), hipMemcpyHostToDevice, b->st);
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(&ctl_of(b)->solo_min, b->h_total + 2, sizeof(int32_t), hipMemcpyHostToDevice, b->st);
     if (e != hipSuccess) return e;
     b->dirty = false;
     return hipStreamSynchronize(b->st);
@@ -435,6 +449,7 @@ int sscn_batch_admit(sscn_batch *b, int32_t slot, const sscn_problem *pb, void *
     I.need[BP_OBS] = B.bax[I.last_pass].ntiles;
     I.dep[BP_FIN] = BP_OBS;
     I.need[BP_FIN] = B.obs_tiles;
+    I.solo = pb->dim == 1 && B.bax[0].ntiles == 1 && B.obs_tiles == 1;
 
     // the work list must fit
     const int was = b->used[slot];

@@ -57,14 +57,19 @@ def ho_gaussian(dim, n, dx, omega, noise: float = 1e-3, seed: int = 0,
     """Harmonic-oscillator ground-state Gaussian prod_a (w_a/pi)^(1/4)
     exp(-w_a (x_a - shift_a)^2 / 2), plus U[-noise, noise) per point, then
     normalised so that dV * sum psi^2 = 1.  Real FP64, shape (nz, ny, nx)."""
-    x, y, z = _mesh(dim, n, dx)
+    nn = _pad3(n, 1)
+    dd = _pad3(dx, 1.0)
+    # per-axis coordinates broadcast against the (nz, ny, nx) array: the
+    # same products in the same order as on a full mesh, without the mesh
+    ax = [coords(nn[a], dd[a]) if a < dim else np.zeros(1) for a in range(3)]
     om = _pad3(omega, 1.0)
     sh = _pad3(shift, 0.0)
-    psi = np.ones_like(x)
-    for a, c in enumerate((x, y, z)):
+    psi = np.ones((1, 1, 1))
+    for a, c in enumerate((ax[0][None, None, :], ax[1][None, :, None], ax[2][:, None, None])):
         if a < dim:
             w = om[a]
             psi = psi * (w / math.pi) ** 0.25 * np.exp(-0.5 * w * (c - sh[a]) ** 2)
+    psi = np.broadcast_to(psi, (nn[2], nn[1], nn[0]))
     if noise > 0:
         rng = np.random.default_rng(seed)
         psi = psi + rng.uniform(-noise, noise, size=psi.shape)

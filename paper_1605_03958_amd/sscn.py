@@ -119,6 +119,11 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"libsscn.so is not built ({LIB_PATH}); run paper_1605_03958_amd/build.py")
+    # torch first: its HIP runtime then satisfies the library's dependency
+    # (same soname), so the tensors and streams torch hands over belong to
+    # the runtime the library calls.  Loaded the other way round, torch
+    # would bring a second copy of the runtime into the process.
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     for name, (args, res) in EXPORTS.items():
         f = getattr(L, name)

@@ -171,3 +171,20 @@ def test_batch_sizes_and_validation():
             q = Problem(d.dim, d.n, d.dx, d.omega, d.g, 0.1 * d.dx[0] ** 2, mode, F32,
                         1 if mode == IMAG else 0, 10)
             assert sscn.batch_workspace_bytes(q) > 0
+
+
+def test_one_hip_runtime_in_the_process():
+    """Loading the library before anything imports torch must not bring a
+    second HIP runtime into the process (torch's tensors and streams belong
+    to torch's runtime)."""
+    import subprocess
+    import sys
+    code = ("from paper_1605_03958_amd import sscn\n"
+            "sscn.lib()\n"
+            "import torch\n"
+            "print(sorted({l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}))\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    libs = eval(out.stdout.strip().splitlines()[-1])
+    assert len(libs) == 1, libs

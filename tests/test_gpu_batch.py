@@ -150,3 +150,42 @@ def test_work_list_capacity_is_enforced():
         b.admit(0, p, psi0)
     assert e.value.code == sscn.E_NOSPACE
     b.close()
+
+
+def test_solo_instance_steps_and_mix_independence():
+    """A 1D instance runs whole steps inside one block: alone it advances 64
+    steps per launch; next to a 3D instance it advances at least one per
+    launch, and its state is bitwise the same either way."""
+    one = make(1, (5000, 1, 1), IMAG, seed=50)
+    big = make(3, (48, 49, 50), IMAG, seed=51)
+    b = sscn.Batch(2)
+    b.admit(0, one[0], one[1], mu_tol=0.0, max_steps=300)
+    b.step(2)
+    st = b.poll(wait=True)[0]
+    assert st.state == sscn.SLOT_RUNNING and st.steps == 128
+    b.step(3)
+    st = b.poll(wait=True)[0]
+    assert st.state == sscn.SLOT_DONE and st.steps == 300
+    alone = b.evict(0).cpu().numpy()
+    b.close()
+
+    b = sscn.Batch(2)
+    b.admit(1, big[0], big[1], mu_tol=0.0, max_steps=1 << 30)
+    b.admit(0, one[0], one[1], mu_tol=0.0, max_steps=300)
+    launches = 0
+    while True:
+        b.step(1)
+        launches += 1
+        st = b.poll(wait=True)
+        assert st[1].steps == launches and st[0].steps >= min(launches, 300)
+        if st[0].state != sscn.SLOT_RUNNING:
+            break
+        assert launches < 300
+    assert not b.error()
+    assert st[0].state == sscn.SLOT_DONE and st[0].steps == 300
+    print(f"solo finished 300 steps in {launches} launches beside a 48x49x50 instance", flush=True)
+    mix = b.evict(0).cpu().numpy()
+    b.close()
+    assert np.array_equal(alone, mix)
+    ref = oracle.run(oprob(one[0]), one[1], 300).psi
+    assert rel_l2(mix, ref) <= 5e-5
