@@ -143,11 +143,15 @@ def batch_c3(tick: int = 100, cap: int = 300000, time_limit: float = 60.0):
     dims = np.array([p.dim for _, p in probs])
     done = {}
     t0 = time.perf_counter()
-    # while all 64 run: 20 warm-up launches (the graph is captured), then 20
-    # timed ones; solo 1D instances take several steps per launch, so the
-    # work is counted from the step counters
-    b.step(20)
-    s0 = b.poll(wait=True)
+    # while all 64 run: warm-up launches for 0.3 s (the graph is captured and
+    # the clocks come up after the host-side admissions), then 20 timed ones;
+    # solo 1D instances take several steps per launch, so the work is
+    # counted from the step counters
+    while True:
+        b.step(20)
+        s0 = b.poll(wait=True)
+        if time.perf_counter() - t0 > 0.3:
+            break
     ta = time.perf_counter()
     b.step(20)
     s = b.poll(wait=True)

@@ -228,6 +228,25 @@ int sscn_batch_ctl_bytes(int32_t max_slots, int64_t max_items, size_t *bytes);
  * y and z lines up to 1024 (complex) / 2048 (float) points). */
 int sscn_batch_workspace_bytes(const sscn_problem *pb, size_t *bytes);
 
+/* Batch tile hints (used by the tuner): for instances of pb's shape (dim, n,
+ * mode), chunk[a] points per thread on axis a, 0 keeping the default choice.
+ * x lines: 1, 2, 3, 4, 6, 8 (12, 16 in imaginary time), honoured only when
+ * one wave covers the line; y and z lines: 2, 3, 4, 5, 6, 8 (10, 12, 16 in
+ * imaginary time).  Applies to later admissions and plan queries of that
+ * shape, process-wide; an admitted instance keeps its geometry, and the
+ * geometry of an instance depends on its shape only.  SSCN_E_INVALID for a
+ * bad problem or a chunk outside these lists. */
+int sscn_batch_set_tile_hint(const sscn_problem *pb, const int32_t chunk[3]);
+int sscn_batch_clear_tile_hints(void);
+
+/* Geometry of pb's instances in the persistent kernel, 8 ints per axis (x,
+ * y, z): kind (0 ROW, 1 COL, -1 unused axis), points per thread, waves per
+ * line (ROW) or per sub-tile (COL), lanes per line (COL; 1 otherwise), work
+ * items per step, line groups (ROW) or sub-tile sets (COL) per item, scan
+ * depth, and 1 when the instance needs the kernel variant for long lines.
+ * info needs cap >= 24 entries.  Errors as sscn_batch_workspace_bytes. */
+int sscn_batch_plan_info(const sscn_problem *pb, int32_t *info, int32_t cap);
+
 /* Create a batch over a caller-owned, 256-byte aligned device control block
  * of at least sscn_batch_ctl_bytes bytes, on hip_stream.  Clears the block.
  * Allocates pinned host mirrors only. */

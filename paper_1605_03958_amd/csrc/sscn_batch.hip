@@ -40,16 +40,36 @@ __device__ __forceinline__ void batch_row(const BInst &I, const BState &S, int t
     const T scale = CPLX ? T(1) : T(S.scale);
     V *psi = reinterpret_cast<V *>(I.psi);
     double nacc = 0.0;
-    for (int r = 0; r < X.rep; ++r) {
-        const long long line = ((long long)tile * X.rep + r) * X.lpi + lb;
-        const bool active = line < X.nlines;
-        if constexpr (MW)
-            nacc += row_line<T, CPLX, C, true>(psi, line, active, X.lt.n, X.lt.tab, G, t, lane, wl, X.wpl, xs, sig,
-                                               scale, T(I.pp.dt), T(I.pp.g), I.pp, X.lt.depth, last);
-        else
-            nacc += row_line<T, CPLX, C, false>(psi, line, active, X.lt.n, static_cast<const LTab<T, CPLX> *>(tl),
-                                                G, t, lane, wl, 1, xs, sig, scale, T(I.pp.dt), T(I.pp.g), I.pp,
-                                                X.lt.depth, last);
+    const long long line0 = (long long)tile * X.rep * X.lpi + lb;
+    if constexpr (MW) {
+        for (int r = 0; r < X.rep; ++r) {
+            const long long line = line0 + (long long)r * X.lpi;
+            nacc += row_line<T, CPLX, C, true>(psi, line, line < X.nlines, X.lt.n, X.lt.tab, G, t, lane, wl, X.wpl,
+                                               xs, sig, scale, T(I.pp.dt), T(I.pp.g), I.pp, X.lt.depth, last);
+        }
+    } else {
+        // one block runs an item, so the loads of the next line group are
+        // issued before the current one is solved (when the extra
+        // registers are few): memory latency overlaps the solve
+        constexpr bool PF = C * sizeof(V) <= 32;
+        V u[C];
+        row_load<T, CPLX, C>(psi, line0, line0 < X.nlines, X.lt.n, t, u);
+        for (int r = 0; r < X.rep; ++r) {
+            const long long line = line0 + (long long)r * X.lpi;
+            V nx[C];
+            if constexpr (PF) {
+                if (r + 1 < X.rep) row_load<T, CPLX, C>(psi, line + X.lpi, line + X.lpi < X.nlines, X.lt.n, t, nx);
+            } else if (r > 0) {
+                row_load<T, CPLX, C>(psi, line, line < X.nlines, X.lt.n, t, u);
+            }
+            nacc += row_solve<T, CPLX, C, false>(psi, line, line < X.nlines, X.lt.n,
+                                                 static_cast<const LTab<T, CPLX> *>(tl), G, t, lane, wl, 1, xs, sig,
+                                                 scale, T(I.pp.dt), T(I.pp.g), I.pp, X.lt.depth, last, u);
+            if constexpr (PF) {
+#pragma unroll
+                for (int k = 0; k < C; ++k) u[k] = nx[k];
+            }
+        }
     }
     if (last) {
         const double s = block_sum(nacc, red);
@@ -78,16 +98,42 @@ __device__ __forceinline__ void batch_col(const BInst &I, int axis, int tile, un
     V *xs0 = reinterpret_cast<V *>(tb + nch * C) + st_i * (2 * nch * LPB);
     V *xs1 = xs0 + nch * LPB;
     stage_table<T, CPLX>(X.lt, tb, nch * C, 0, C);
+    V *psi = reinterpret_cast<V *>(I.psi);
+    // this lane's line in set r, and its first point
+    auto line_of = [&](int r) { return (((long long)tile * X.rep + r) * X.tpi + st_i) * LPB + li; };
+    auto base_of = [&](long long line) {
+        return line < X.nlines ? (line % X.m1) * X.s1 + (line / X.m1) * X.s2 : 0LL;
+    };
+    // loads of the next set are issued before the current set is solved
+    // when the extra registers are few (see batch_row)
+    constexpr bool PF = C * sizeof(V) <= 32;
     double nacc = 0.0;
+    V u[C];
+    {
+        const long long l0 = line_of(0);
+        col_load<T, CPLX, C>(psi, l0 < X.nlines, base_of(l0), X.lt.n, X.stride, ch, u);
+    }
     for (int r = 0; r < X.rep; ++r) {
+        const long long line = line_of(r);
+        const bool active = line < X.nlines;
+        const long long base = base_of(line);
+        V nx[C];
+        if constexpr (PF) {
+            if (r + 1 < X.rep) {
+                const long long ln = line_of(r + 1);
+                col_load<T, CPLX, C>(psi, ln < X.nlines, base_of(ln), X.lt.n, X.stride, ch, nx);
+            }
+        } else if (r > 0) {
+            col_load<T, CPLX, C>(psi, active, base, X.lt.n, X.stride, ch, u);
+        }
         // the previous set's last LDS reads finish before the next set's writes
         if (r > 0) __syncthreads();
-        const long long line = (((long long)tile * X.rep + r) * X.tpi + st_i) * LPB + li;
-        const bool active = line < X.nlines;
-        long long base = 0;
-        if (active) base = (line % X.m1) * X.s1 + (line / X.m1) * X.s2;
-        nacc += col_tile<T, CPLX, C>(reinterpret_cast<V *>(I.psi), active, base, X.lt.n, X.stride, nch, ch, LPB,
-                                     li, tb, xs0, xs1, A::coef(X.sig_re, X.sig_im), X.lt.depth, last);
+        nacc += col_solve<T, CPLX, C>(psi, active, base, X.lt.n, X.stride, nch, ch, LPB, li, tb, xs0, xs1,
+                                      A::coef(X.sig_re, X.sig_im), X.lt.depth, last, u);
+        if constexpr (PF) {
+#pragma unroll
+            for (int k = 0; k < C; ++k) u[k] = nx[k];
+        }
     }
     if (last) {
         const double s = block_sum(nacc, red);
@@ -221,27 +267,45 @@ __device__ __forceinline__ void batch_sweep(const BInst &I, const BState &S, int
     const bool last = pass == I.last_pass;
     const BAxis &X = I.ax[pass];
     if (pass == BP_X) {
-        const bool mw = X.wpl > 1;
-        switch (X.C * 2 + (mw ? 1 : 0)) {
-        case 2: batch_row<T, CPLX, 1, false>(I, S, tile, lds, red, last); break;
-        case 4: batch_row<T, CPLX, 2, false>(I, S, tile, lds, red, last); break;
-        case 8: batch_row<T, CPLX, 4, false>(I, S, tile, lds, red, last); break;
-        case 16: batch_row<T, CPLX, 8, false>(I, S, tile, lds, red, last); break;
-        case 32:
-            if constexpr (!CPLX) batch_row<T, CPLX, 16, false>(I, S, tile, lds, red, last);
-            break;
-        case 9: batch_row<T, CPLX, 4, true>(I, S, tile, lds, red, last); break;
-        case 17: batch_row<T, CPLX, 8, true>(I, S, tile, lds, red, last); break;
-        case 33:
-            if constexpr (BIG) batch_row<T, CPLX, 16, true>(I, S, tile, lds, red, last);
-            break;
-        default: break;
+        if (X.wpl > 1) {
+            switch (X.C) {
+            case 8: batch_row<T, CPLX, 8, true>(I, S, tile, lds, red, last); break;
+            case 16:
+                if constexpr (BIG) batch_row<T, CPLX, 16, true>(I, S, tile, lds, red, last);
+                break;
+            default: break;
+            }
+        } else {
+            switch (X.C) {
+            case 1: batch_row<T, CPLX, 1, false>(I, S, tile, lds, red, last); break;
+            case 2: batch_row<T, CPLX, 2, false>(I, S, tile, lds, red, last); break;
+            case 3: batch_row<T, CPLX, 3, false>(I, S, tile, lds, red, last); break;
+            case 4: batch_row<T, CPLX, 4, false>(I, S, tile, lds, red, last); break;
+            case 6: batch_row<T, CPLX, 6, false>(I, S, tile, lds, red, last); break;
+            case 8: batch_row<T, CPLX, 8, false>(I, S, tile, lds, red, last); break;
+            case 12:
+                if constexpr (!CPLX) batch_row<T, CPLX, 12, false>(I, S, tile, lds, red, last);
+                break;
+            case 16:
+                if constexpr (!CPLX) batch_row<T, CPLX, 16, false>(I, S, tile, lds, red, last);
+                break;
+            default: break;
+            }
         }
     } else {
         switch (X.C) {
         case 2: batch_col<T, CPLX, 2>(I, pass, tile, lds, red, last); break;
+        case 3: batch_col<T, CPLX, 3>(I, pass, tile, lds, red, last); break;
         case 4: batch_col<T, CPLX, 4>(I, pass, tile, lds, red, last); break;
+        case 5: batch_col<T, CPLX, 5>(I, pass, tile, lds, red, last); break;
+        case 6: batch_col<T, CPLX, 6>(I, pass, tile, lds, red, last); break;
         case 8: batch_col<T, CPLX, 8>(I, pass, tile, lds, red, last); break;
+        case 10:
+            if constexpr (!CPLX) batch_col<T, CPLX, 10>(I, pass, tile, lds, red, last);
+            break;
+        case 12:
+            if constexpr (!CPLX) batch_col<T, CPLX, 12>(I, pass, tile, lds, red, last);
+            break;
         case 16:
             if constexpr (BIG && !CPLX) batch_col<T, CPLX, 16>(I, pass, tile, lds, red, last);
             break;

@@ -14,6 +14,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -69,8 +70,71 @@ struct BPlan {
 
 size_t ltab_size(bool cplx) { return cplx ? 32 : 16; }  // (alpha, m) hi/lo pairs of float / complex<float>
 
+// Points per thread the persistent kernel is compiled for (sscn_batch.hip).
+const int kRowChunks[] = {1, 2, 3, 4, 6, 8, 12, 16};   // 12, 16: float only
+const int kColChunks[] = {2, 3, 4, 5, 6, 8, 10, 12, 16};  // 10, 12: float only; 16: float, BIG kernel
+
+bool row_chunk_ok(int c, bool cplx)
+{
+    for (int v : kRowChunks)
+        if (v == c) return cplx ? c <= 8 : true;
+    return false;
+}
+bool col_chunk_ok(int c, bool cplx)
+{
+    for (int v : kColChunks)
+        if (v == c) return cplx ? c <= 8 : true;
+    return false;
+}
+
+// COL geometry for lines of n points with c points per thread: W waves of
+// L lanes per line (W*L*c >= n), 16/W sub-tiles of 64/L lines per block.
+// The time of one sub-tile set grows like c plus a fixed part (barriers,
+// the LDS folds), and a set covers (64/L)*(16/W) lines, so the cost per
+// point goes like (c + 6) * L * W; lanes per line beyond 4 also split the
+// 128-byte segments of a row of lines, which costs extra.
+bool col_geometry(int64_t n, int c, int &L, int &W, double &cost)
+{
+    const int64_t K = cdiv(n, c);                  // chunks per line
+    bool found = false;
+    for (int l = 1; l <= 8; l *= 2)
+        for (int w = 1; w <= 16; w *= 2) {
+            if ((int64_t)w * l < K) continue;
+            double q = (double)(c + 6) * l * w * (l == 8 ? 1.25 : 1.0);
+            if (!found || q < cost) {
+                found = true;
+                cost = q;
+                L = l;
+                W = w;
+            }
+        }
+    return found;
+}
+
+// Batch tile hints: shape-keyed chunk choices (0: keep the model's choice),
+// set by the tuner.  An instance's geometry still depends only on its shape.
+struct BHint {
+    int32_t dim, n[3], mode;
+    int32_t chunk[3];
+};
+std::mutex g_bhint_mu;
+std::vector<BHint> g_bhints;
+
+bool bhint_find(const sscn_problem &pb, int32_t chunk[3])
+{
+    std::lock_guard<std::mutex> lk(g_bhint_mu);
+    for (const BHint &h : g_bhints)
+        if (h.dim == pb.dim && h.n[0] == pb.n[0] && h.n[1] == pb.n[1] && h.n[2] == pb.n[2] && h.mode == pb.mode) {
+            for (int a = 0; a < 3; ++a) chunk[a] = h.chunk[a];
+            return true;
+        }
+    return false;
+}
+
 int batch_plan(const sscn_problem &pb, BPlan &B)
 {
+    int32_t hint[3] = {0, 0, 0};
+    bhint_find(pb, hint);
     std::memset(&B, 0, sizeof(B));
     const bool cplx = pb.mode == SSCN_REAL;
     const size_t S = cplx ? 8 : 4;
@@ -92,9 +156,15 @@ int batch_plan(const sscn_problem &pb, BPlan &B)
             X.s1 = nx;
             X.s2 = nx * ny;
             X.stride = 1;
-            int c = p2ceil(cdiv(n, 64));
-            int wpl = 1;
             const int cmax1 = cplx ? 8 : 16;   // single-wave lines
+            int c = cmax1 + 1;
+            for (int v : kRowChunks)            // fewest points per thread that cover the line
+                if (row_chunk_ok(v, cplx) && (int64_t)v * 64 >= n) {
+                    c = v;
+                    break;
+                }
+            if (hint[a] > 0 && row_chunk_ok(hint[a], cplx) && (int64_t)hint[a] * 64 >= n) c = hint[a];
+            int wpl = 1;
             if (c > cmax1) {
                 c = 8;                          // multi-wave lines, 8 points per thread
                 wpl = p2ceil(cdiv(n, 64 * 8));
@@ -122,16 +192,33 @@ int batch_plan(const sscn_problem &pb, BPlan &B)
             X.s1 = 1;
             X.s2 = (a == 1) ? nx * ny : nx;
             X.stride = (a == 1) ? nx : nx * ny;
-            const int cmax = cplx ? 8 : 16;
-            int c = cplx ? 4 : 8;
-            c = std::min<int64_t>(c, p2ceil(cdiv(n, 16)));
-            c = std::max(c, 2);
-            while (c < cmax && cdiv(n, c) > 16 * 8) c *= 2;
-            const int64_t K = cdiv(n, c);
-            const int L = p2ceil(cdiv(K, 16));
-            if (L > 8) return SSCN_E_UNSUPPORTED;
+            // the cheapest chunk by the cost model (16 only for lines that
+            // need it: it takes the BIG kernel), or the hinted one
+            int c = 0, L = 0, W = 0;
+            double best = 0.0;
+            for (int v : kColChunks) {
+                if (!col_chunk_ok(v, cplx) || (v == 16 && c != 0)) continue;
+                int l, w;
+                double q;
+                if (!col_geometry(n, v, l, w, q)) continue;
+                if (c == 0 || q < best) {
+                    c = v;
+                    L = l;
+                    W = w;
+                    best = q;
+                }
+            }
+            if (hint[a] > 0 && col_chunk_ok(hint[a], cplx)) {
+                int l, w;
+                double q;
+                if (col_geometry(n, hint[a], l, w, q)) {
+                    c = hint[a];
+                    L = l;
+                    W = w;
+                }
+            }
+            if (c == 0) return SSCN_E_UNSUPPORTED;
             if (c == 16) B.big = true;
-            const int W = p2ceil(cdiv(K, L));
             X.C = c;
             X.W = W;
             X.L = L;
@@ -321,6 +408,71 @@ int sscn_batch_workspace_bytes(const sscn_problem *pb, size_t *bytes)
     v = batch_plan(*pb, B);
     if (v != SSCN_OK) return v;
     *bytes = B.ws_bytes;
+    return SSCN_OK;
+}
+
+int sscn_batch_set_tile_hint(const sscn_problem *pb, const int32_t chunk[3])
+{
+    if (!chunk || validate(pb) != SSCN_OK) return SSCN_E_INVALID;
+    const bool cplx = pb->mode == SSCN_REAL;
+    for (int a = 0; a < 3; ++a) {
+        if (chunk[a] == 0) continue;
+        if (a >= pb->dim) return SSCN_E_INVALID;
+        if (a == 0 ? !row_chunk_ok(chunk[a], cplx) : !col_chunk_ok(chunk[a], cplx)) return SSCN_E_INVALID;
+    }
+    BHint h;
+    std::memset(&h, 0, sizeof(h));
+    h.dim = pb->dim;
+    h.mode = pb->mode;
+    for (int a = 0; a < 3; ++a) {
+        h.n[a] = pb->n[a];
+        h.chunk[a] = chunk[a];
+    }
+    try {
+        std::lock_guard<std::mutex> lk(g_bhint_mu);
+        for (BHint &e : g_bhints)
+            if (e.dim == h.dim && e.n[0] == h.n[0] && e.n[1] == h.n[1] && e.n[2] == h.n[2] && e.mode == h.mode) {
+                e = h;
+                return SSCN_OK;
+            }
+        g_bhints.push_back(h);
+    } catch (...) {
+        return SSCN_E_INVALID;
+    }
+    return SSCN_OK;
+}
+
+int sscn_batch_clear_tile_hints(void)
+{
+    std::lock_guard<std::mutex> lk(g_bhint_mu);
+    g_bhints.clear();
+    return SSCN_OK;
+}
+
+int sscn_batch_plan_info(const sscn_problem *pb, int32_t *info, int32_t cap)
+{
+    int v = batch_validate(pb);
+    if (v != SSCN_OK) return v;
+    if (!info || cap < 24) return SSCN_E_INVALID;
+    BPlan B;
+    v = batch_plan(*pb, B);
+    if (v != SSCN_OK) return v;
+    for (int a = 0; a < 3; ++a) {
+        int32_t *o = info + 8 * a;
+        if (a >= pb->dim) {
+            for (int q = 0; q < 8; ++q) o[q] = -1;
+            continue;
+        }
+        const BAxis &X = B.bax[a];
+        o[0] = X.kind == K_ROW ? 0 : 1;
+        o[1] = X.C;
+        o[2] = X.kind == K_ROW ? X.wpl : X.W;
+        o[3] = X.kind == K_ROW ? 1 : X.L;
+        o[4] = X.ntiles;
+        o[5] = X.rep;
+        o[6] = X.lt.depth;
+        o[7] = B.big ? 1 : 0;
+    }
     return SSCN_OK;
 }
 

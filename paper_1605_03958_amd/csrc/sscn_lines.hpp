@@ -196,27 +196,22 @@ __device__ __forceinline__ LTab<T, CPLX> tab_at(const TabEntry *tb, int q)
 
 // ---------------------------------------------------------------------------
 // ROW: one x line per line group.  xs: 4 values per wave of the group (LDS,
-// used when MW).  Returns the thread's sum |v|^2 when `last`.
+// used when MW).  Returns the thread's sum |v|^2 when `last`.  The load of
+// the lane's values (row_load) is apart from the solve (row_solve), so a
+// caller can issue the next line's loads before solving the current one;
+// row_line does both.
 // ---------------------------------------------------------------------------
 template <class T, bool CPLX, int C, bool MW, class TB>
-__device__ __forceinline__ double row_line(typename Alg<T, CPLX>::V *__restrict__ psi, long long line,
-                                           bool active, int n, const TB *tb, int G, int t, int lane, int wl,
-                                           int wpl, typename Alg<T, CPLX>::V *xs, typename Alg<T, CPLX>::V sig,
-                                           T scale, T dt, T g, const PointParams &pp, int ks, bool last)
+__device__ __forceinline__ double row_solve(typename Alg<T, CPLX>::V *__restrict__ psi, long long line,
+                                            bool active, int n, const TB *tb, int G, int t, int lane, int wl,
+                                            int wpl, typename Alg<T, CPLX>::V *xs, typename Alg<T, CPLX>::V sig,
+                                            T scale, T dt, T g, const PointParams &pp, int ks, bool last,
+                                            typename Alg<T, CPLX>::V (&u)[C])
 {
     using A = Alg<T, CPLX>;
     using V = typename A::V;
     const int i0 = t * C;
     const long long base = line * (long long)n;
-
-    V u[C];
-#pragma unroll
-    for (int k = 0; k < C; ++k) {
-        const int i = i0 + k;
-        V v = A::zero();
-        if (active && i < n) v = psi[base + i];
-        u[k] = v;
-    }
 
     // ---- pointwise substep ----
     T vyz = T(0);
@@ -357,30 +352,51 @@ __device__ __forceinline__ double row_line(typename Alg<T, CPLX>::V *__restrict_
     return nacc;
 }
 
+// The C values of this lane's chunk of one line (zero past the end).
+template <class T, bool CPLX, int C>
+__device__ __forceinline__ void row_load(const typename Alg<T, CPLX>::V *__restrict__ psi, long long line,
+                                         bool active, int n, int t, typename Alg<T, CPLX>::V (&u)[C])
+{
+    using A = Alg<T, CPLX>;
+    const int i0 = t * C;
+    const long long base = line * (long long)n;
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+        const int i = i0 + k;
+        u[k] = (active && i < n) ? psi[base + i] : A::zero();
+    }
+}
+
+template <class T, bool CPLX, int C, bool MW, class TB>
+__device__ __forceinline__ double row_line(typename Alg<T, CPLX>::V *__restrict__ psi, long long line,
+                                           bool active, int n, const TB *tb, int G, int t, int lane, int wl,
+                                           int wpl, typename Alg<T, CPLX>::V *xs, typename Alg<T, CPLX>::V sig,
+                                           T scale, T dt, T g, const PointParams &pp, int ks, bool last)
+{
+    typename Alg<T, CPLX>::V u[C];
+    row_load<T, CPLX, C>(psi, line, active, n, t, u);
+    return row_solve<T, CPLX, C, MW, TB>(psi, line, active, n, tb, G, t, lane, wl, wpl, xs, sig, scale, dt, g, pp,
+                                         ks, last, u);
+}
+
 // ---------------------------------------------------------------------------
 // COL: one tile of LPB = 64/L lines, nch = W*L chunks per line.  `line` and
 // `base` are this lane's line and its first point; tb is the staged table;
 // xs0/xs1 hold nch x LPB values each.  Returns sum |v|^2 when `last`.
+// col_load / col_solve split it like row_load / row_solve.
 // ---------------------------------------------------------------------------
 template <class T, bool CPLX, int C>
-__device__ __forceinline__ double col_tile(typename Alg<T, CPLX>::V *__restrict__ psi, bool active,
-                                           long long base, int n, long long st, int nch, int ch, int LPB, int li,
-                                           const LTab<T, CPLX> *tb, typename Alg<T, CPLX>::V *xs0,
-                                           typename Alg<T, CPLX>::V *xs1, typename Alg<T, CPLX>::V sig, int depth,
-                                           bool last)
+__device__ __forceinline__ double col_solve(typename Alg<T, CPLX>::V *__restrict__ psi, bool active,
+                                            long long base, int n, long long st, int nch, int ch, int LPB, int li,
+                                            const LTab<T, CPLX> *tb, typename Alg<T, CPLX>::V *xs0,
+                                            typename Alg<T, CPLX>::V *xs1, typename Alg<T, CPLX>::V sig, int depth,
+                                            bool last, typename Alg<T, CPLX>::V (&u)[C])
 {
     using A = Alg<T, CPLX>;
     using V = typename A::V;
     const int i0 = ch * C;
     const int qlo = max(0, ch - depth);
     const int qhi = min(nch - 1, ch + depth);
-
-    V u[C];
-#pragma unroll
-    for (int k = 0; k < C; ++k) {
-        const int i = i0 + k;
-        u[k] = (active && i < n) ? psi[base + (long long)i * st] : A::zero();
-    }
 
     // neighbours from the adjacent chunks
     xs0[ch * LPB + li] = u[0];
@@ -442,6 +458,33 @@ __device__ __forceinline__ double col_tile(typename Alg<T, CPLX>::V *__restrict_
         }
     }
     return nacc;
+}
+
+// The C values of chunk ch of this lane's line (zero past the end).
+template <class T, bool CPLX, int C>
+__device__ __forceinline__ void col_load(const typename Alg<T, CPLX>::V *__restrict__ psi, bool active,
+                                         long long base, int n, long long st, int ch,
+                                         typename Alg<T, CPLX>::V (&u)[C])
+{
+    using A = Alg<T, CPLX>;
+    const int i0 = ch * C;
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+        const int i = i0 + k;
+        u[k] = (active && i < n) ? psi[base + (long long)i * st] : A::zero();
+    }
+}
+
+template <class T, bool CPLX, int C>
+__device__ __forceinline__ double col_tile(typename Alg<T, CPLX>::V *__restrict__ psi, bool active,
+                                           long long base, int n, long long st, int nch, int ch, int LPB, int li,
+                                           const LTab<T, CPLX> *tb, typename Alg<T, CPLX>::V *xs0,
+                                           typename Alg<T, CPLX>::V *xs1, typename Alg<T, CPLX>::V sig, int depth,
+                                           bool last)
+{
+    typename Alg<T, CPLX>::V u[C];
+    col_load<T, CPLX, C>(psi, active, base, n, st, ch, u);
+    return col_solve<T, CPLX, C>(psi, active, base, n, st, nch, ch, LPB, li, tb, xs0, xs1, sig, depth, last, u);
 }
 
 }  // namespace sscn

@@ -97,6 +97,10 @@ EXPORTS = {
     "sscn_density_2d": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
     "sscn_batch_ctl_bytes": ([ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "sscn_batch_workspace_bytes": ([ctypes.POINTER(CProblem), ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "sscn_batch_set_tile_hint": ([ctypes.POINTER(CProblem), ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+    "sscn_batch_clear_tile_hints": ([], ctypes.c_int),
+    "sscn_batch_plan_info": ([ctypes.POINTER(CProblem), ctypes.POINTER(ctypes.c_int32), ctypes.c_int32],
+                             ctypes.c_int),
     "sscn_batch_create": ([ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
                            ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
     "sscn_batch_admit": ([ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(CProblem), ctypes.c_void_p,
@@ -383,6 +387,30 @@ class SlotStatus:
     steps: int
     last_norm: float
     obs: Obs
+
+
+def batch_plan_info(prob: Problem):
+    """Geometry of prob's instances in the persistent kernel, per axis."""
+    pc = prob.c()
+    info = (ctypes.c_int32 * 24)()
+    _check(lib().sscn_batch_plan_info(ctypes.byref(pc), info, 24), "sscn_batch_plan_info")
+    kinds = {0: "row", 1: "col", -1: None}
+    out = []
+    for a in range(3):
+        o = info[8 * a: 8 * a + 8]
+        out.append(None if o[0] < 0 else dict(kind=kinds[o[0]], chunk=o[1], waves=o[2], lanes=o[3], items=o[4],
+                                              rep=o[5], depth=o[6], big=bool(o[7])))
+    return out
+
+
+def batch_set_tile_hint(prob: Problem, chunks) -> None:
+    pc = prob.c()
+    arr = (ctypes.c_int32 * 3)(*[int(c) for c in chunks])
+    _check(lib().sscn_batch_set_tile_hint(ctypes.byref(pc), arr), "sscn_batch_set_tile_hint")
+
+
+def batch_clear_tile_hints() -> None:
+    lib().sscn_batch_clear_tile_hints()
 
 
 class Batch:

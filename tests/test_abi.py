@@ -188,3 +188,73 @@ def test_one_hip_runtime_in_the_process():
     assert out.returncode == 0, out.stderr
     libs = eval(out.stdout.strip().splitlines()[-1])
     assert len(libs) == 1, libs
+
+
+ROW_CHUNKS = {False: [1, 2, 3, 4, 6, 8, 12, 16], True: [1, 2, 3, 4, 6, 8]}
+COL_CHUNKS = {False: [2, 3, 4, 5, 6, 8, 10, 12, 16], True: [2, 3, 4, 5, 6, 8]}
+
+
+@pytest.mark.parametrize("dim,n", [(3, (152, 152, 152)), (3, (48, 49, 50)), (3, (17, 160, 3)), (2, (919, 919, 1)),
+                                   (2, (267, 1024, 1)), (2, (64, 2048, 1)), (1, (9912, 1, 1)), (1, (700, 1, 1))])
+@pytest.mark.parametrize("mode", [sscn.IMAG, sscn.REAL])
+def test_batch_geometry_covers_lines(dim, n, mode):
+    cplx = mode == sscn.REAL
+    p = sscn.Problem(dim, n, (0.1,) * dim, (1.0, 1.5, 2.0)[:dim], 5.0, 1e-3, mode, sscn.F32,
+                     1 if mode == sscn.IMAG else 0, 10)
+    if cplx and dim == 2 and n[1] > 1024:
+        with pytest.raises(sscn.SSCNError):
+            sscn.batch_plan_info(p)
+        return
+    info = sscn.batch_plan_info(p)
+    for a in range(3):
+        g = info[a]
+        if a >= dim:
+            assert g is None
+            continue
+        if g["kind"] == "row":
+            assert g["chunk"] * 64 * g["waves"] >= n[a]
+            if g["waves"] == 1:
+                assert g["chunk"] in ROW_CHUNKS[cplx]
+                assert (g["chunk"] - 1) * 64 < n[a] or g["chunk"] == 1 or ROW_CHUNKS[cplx].index(g["chunk"]) == 0 \
+                    or ROW_CHUNKS[cplx][ROW_CHUNKS[cplx].index(g["chunk"]) - 1] * 64 < n[a]
+        else:
+            assert a > 0 and g["chunk"] in COL_CHUNKS[cplx]
+            assert g["chunk"] * g["waves"] * g["lanes"] >= n[a]
+            assert 16 % g["waves"] == 0 and g["lanes"] in (1, 2, 4, 8)
+        assert g["items"] >= 1 and g["rep"] >= 1
+    # a 1D instance whose line fits one block runs its whole step as one item
+    if dim == 1:
+        assert info[0]["items"] == 1
+
+
+def test_batch_tile_hints():
+    p = sscn.Problem(3, (40, 44, 36), (0.1,) * 3, (1.0, 1.5, 2.0), 5.0, 1e-3, sscn.IMAG, sscn.F32, 1, 10)
+    q = sscn.Problem(3, (40, 44, 37), (0.1,) * 3, (1.0, 1.5, 2.0), 5.0, 1e-3, sscn.IMAG, sscn.F32, 1, 10)
+    base = sscn.batch_plan_info(p)
+    qbase = sscn.batch_plan_info(q)
+
+    def geo(g):
+        return {k: v for k, v in g.items() if k != "big"}
+    try:
+        sscn.batch_set_tile_hint(p, (6, 3, 12))
+        h = sscn.batch_plan_info(p)
+        assert [h[0]["chunk"], h[1]["chunk"], h[2]["chunk"]] == [6, 3, 12]
+        assert h[1]["chunk"] * h[1]["waves"] * h[1]["lanes"] >= 44
+        assert sscn.batch_plan_info(q) == qbase      # other shapes untouched
+        sscn.batch_set_tile_hint(p, (0, 16, 0))
+        h = sscn.batch_plan_info(p)
+        assert h[1]["chunk"] == 16 and h[1]["big"]
+        assert geo(h[0]) == geo(base[0]) and geo(h[2]) == geo(base[2])
+        for bad in ((5, 0, 0), (0, 7, 0), (0, 0, 32), (-1, 0, 0)):
+            with pytest.raises(sscn.SSCNError) as e:
+                sscn.batch_set_tile_hint(p, bad)
+            assert e.value.code == sscn.E_INVALID
+        r = sscn.Problem(3, (40, 44, 36), (0.1,) * 3, (1.0, 1.5, 2.0), 5.0, 1e-3, sscn.REAL, sscn.F32, 0, 10)
+        with pytest.raises(sscn.SSCNError):
+            sscn.batch_set_tile_hint(r, (12, 0, 0))      # complex lines take at most 8 per thread
+        d2 = sscn.Problem(2, (40, 44, 1), (0.1,) * 2, (1.0, 1.5), 5.0, 1e-3, sscn.IMAG, sscn.F32, 1, 10)
+        with pytest.raises(sscn.SSCNError):
+            sscn.batch_set_tile_hint(d2, (0, 0, 4))      # no z axis
+    finally:
+        sscn.batch_clear_tile_hints()
+    assert sscn.batch_plan_info(p) == base

@@ -70,6 +70,40 @@ def test_batch_matches_oracle_across_tile_variants():
         assert abs(s.obs.mu - orf.mu) <= 1e-5 * max(1.0, abs(orf.mu))
 
 
+def test_every_tile_variant_matches_the_oracle():
+    """Tile hints force each points-per-thread variant of the persistent
+    kernel (x lines 1..16, y and z lines 2..16) on small 3D instances of
+    distinct shapes, in imaginary and real time: 20 steps against the
+    oracle."""
+    row = {IMAG: [1, 2, 3, 4, 6, 8, 12, 16], REAL: [1, 2, 3, 4, 6, 8]}
+    col = {IMAG: [2, 3, 4, 5, 6, 8, 10, 12, 16], REAL: [2, 3, 4, 5, 6, 8]}
+    cases = []
+    i = 0
+    try:
+        for mode in (IMAG, REAL):
+            m = max(len(row[mode]), len(col[mode]))
+            for k in range(m):
+                r = row[mode][k % len(row[mode])]
+                cy = col[mode][k % len(col[mode])]
+                cz = col[mode][(k + 3) % len(col[mode])]
+                n = (25 + 3 * i, 20 + i, 18 + 2 * i)
+                p, psi0 = make(3, n, mode, seed=60 + i)
+                sscn.batch_set_tile_hint(p, (r, cy, cz))
+                g = sscn.batch_plan_info(p)
+                assert [g[0]["chunk"], g[1]["chunk"], g[2]["chunk"]] == [r, cy, cz]
+                cases.append((p, psi0))
+                i += 1
+        got, st = run_batch(cases, 20)
+    finally:
+        sscn.batch_clear_tile_hints()
+    for (p, psi0), gv, s in zip(cases, got, st):
+        assert s.state == sscn.SLOT_DONE and s.steps == 20
+        ref = oracle.run(oprob(p), psi0, 20).psi
+        err = rel_l2(gv, ref)
+        print(f"n={p.n} mode={p.mode}: rel L2 {err:.2e}", flush=True)
+        assert err <= 5e-5, (p.n, p.mode, err)
+
+
 def test_alone_equals_in_the_mix_bitwise():
     a = make(3, (20, 24, 30), IMAG, seed=3)
     r = make(2, (64, 130, 1), REAL, seed=4)
@@ -144,11 +178,15 @@ def test_batch_equals_single_problem_fp32():
 
 
 def test_work_list_capacity_is_enforced():
-    b = sscn.Batch(2, max_items=10)
     p, psi0 = make(3, (20, 24, 30), IMAG)
+    need = sum(g["items"] for g in sscn.batch_plan_info(p)) + -(-p.points // 16384) + 1
+    b = sscn.Batch(2, max_items=need - 1)
     with pytest.raises(sscn.SSCNError) as e:
         b.admit(0, p, psi0)
     assert e.value.code == sscn.E_NOSPACE
+    b.close()
+    b = sscn.Batch(2, max_items=need)
+    b.admit(0, p, psi0)
     b.close()
 
 
