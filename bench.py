@@ -15,7 +15,6 @@ Prints one JSON line (see the design doc for the fields).
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -39,11 +38,17 @@ def c1_problem(prec):
 
 
 def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    for name in ("sscn_dev.hpp", "sscn_kernels.hip"):
-        with open(os.path.join(ROOT, "paper_1605_03958_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
-    return h.hexdigest()[:16]
+    from paper_1605_03958_amd.profiling import source_hash
+    return source_hash()
+
+
+TILES = os.path.join(ROOT, "paper_1605_03958_amd", "tiles_gfx950.json")
+
+
+def apply_tiles(prob, target):
+    """Tile choices the tuner stored for this shape, if any."""
+    from paper_1605_03958_amd import autotune
+    return autotune.apply(prob, target, cache_path=TILES)
 
 
 def load_traffic(kernel_class: str, workload: str):
@@ -134,6 +139,8 @@ def batch_c3(tick: int = 100, cap: int = 300000, time_limit: float = 60.0):
     import torch
     from paper_1605_03958_amd import inputs, sscn
     probs = c3_problems()
+    for _, p in probs:
+        apply_tiles(p, "batch")
     st = torch.cuda.Stream()
     b = sscn.Batch(64, stream=st)
     for i, (d, p) in enumerate(probs):
@@ -236,8 +243,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp32", action="store_true")
-    ap.add_argument("--only", choices=["fp64", "fp32"], default=None,
-                    help="run only one precision (profiling runs)")
+    ap.add_argument("--only", choices=["fp64", "fp32", "batch"], default=None,
+                    help="run only one precision, or only the batch (profiling runs)")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance batch")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving loop")
     ap.add_argument("--serve-requests", type=int, default=512)
@@ -253,6 +260,9 @@ def main():
     from paper_1605_03958_amd import inputs, sscn
 
     torch.cuda.set_device(0)
+    if args.only == "batch":
+        print(json.dumps({"batch": batch_c3()}), flush=True)
+        return
     out = {}
     precs = [sscn.F64, sscn.F32]
     if args.no_fp32 or args.only == "fp64":
@@ -262,6 +272,7 @@ def main():
     psi0 = inputs.thomas_fermi(3, (256, 256, 256), (0.1,) * 3, (1.0, 1.5, 2.0), 100.0, phase_sigma=0.05, seed=1)
     for prec in precs:
         p = c1_problem(prec)
+        apply_tiles(p, "single")
         s = sscn.Solver(p, psi0)
         el = time_steps(s, args.steps, args.warmup)
         kms = s.step_timed(args.steps)

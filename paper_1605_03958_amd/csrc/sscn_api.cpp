@@ -349,16 +349,23 @@ static ColArgs col_args(sscn_solver *s, int a, bool last)
 }
 
 // Kernel classes for timing: 0 x (+pointwise), 1 y, 2 z, 3 norm final, 4 scale.
+// Each timed launch takes a start/stop event pair: the sweep kernels pass it
+// to the launch (the events take the kernel's own begin and end times);
+// other kernels are bracketed by event records on the stream.
 struct Timer {
     std::vector<hipEvent_t> ev;
     std::vector<int> cls;
     size_t used = 0;
     hipStream_t st;
-    hipError_t mark(int c)
+    // next pair for class c, or nulls when the pool is used up
+    void pair(int c, hipEvent_t &a, hipEvent_t &b)
     {
-        if (used >= ev.size()) return hipSuccess;
+        a = b = nullptr;
+        if (used + 2 > ev.size()) return;
         cls[used] = c;
-        return hipEventRecord(ev[used++], st);
+        a = ev[used];
+        b = ev[used + 1];
+        used += 2;
     }
 };
 
@@ -375,9 +382,10 @@ static hipError_t enqueue_step(sscn_solver *s, bool do_renorm, Timer *tm)
     do {                                \
         if ((e = (x)) != hipSuccess) return e; \
     } while (0)
-    if (tm) CHK(tm->mark(-1));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
     // x sweep with the pointwise substep
     {
+        if (tm) tm->pair(0, e0, e1);
         const AxisPlan &X = P.ax[0];
         const bool last = imag && do_renorm && dim == 1 && X.kind == K_ROW;
         if (X.kind == K_ROW) {
@@ -392,34 +400,40 @@ static hipError_t enqueue_step(sscn_solver *s, bool do_renorm, Timer *tm)
             r.pp = point_params(s);
             r.scale = scal;
             r.partial = last ? part : nullptr;
-            CHK(launch_row(P.elem, X.C, last, r, X.grid, X.block, X.lds, s->st));
+            CHK(launch_row(P.elem, X.C, last, r, X.grid, X.block, X.lds, s->st, e0, e1));
         } else {
             PointArgs pa;
             pa.psi = s->psi;
             pa.npts = P.npts;
             pa.pp = point_params(s);
             pa.scale = scal;
+            if (e0) CHK(hipEventRecord(e0, s->st));
             CHK(launch_pointwise(P.elem, pa, P.pw_grid, 256, s->st));
             CHK(launch_stream(P.elem, col_args(s, 0, false), X.grid, X.block, s->st));
+            if (e1) CHK(hipEventRecord(e1, s->st));
         }
-        if (tm) CHK(tm->mark(0));
     }
     for (int a = 1; a < dim; ++a) {
         const AxisPlan &X = P.ax[a];
         const bool last = imag && do_renorm && a == dim - 1 && X.kind == K_COL;
-        if (X.kind == K_COL)
-            CHK(launch_col(P.elem, X.C, last, col_args(s, a, last), X.grid, X.block, X.lds, s->st));
-        else
+        if (tm) tm->pair(a, e0, e1);
+        if (X.kind == K_COL) {
+            CHK(launch_col(P.elem, X.C, last, col_args(s, a, last), X.grid, X.block, X.lds, s->st, e0, e1));
+        } else {
+            if (e0) CHK(hipEventRecord(e0, s->st));
             CHK(launch_stream(P.elem, col_args(s, a, false), X.grid, X.block, s->st));
-        if (tm) CHK(tm->mark(a));
+            if (e1) CHK(hipEventRecord(e1, s->st));
+        }
     }
     if (imag) {
+        if (tm) tm->pair(3, e0, e1);
+        if (e0) CHK(hipEventRecord(e0, s->st));
         if (do_renorm && P.sep_norm)
             CHK(launch_norm_partials(P.elem, s->psi, P.npts, part, P.pw_grid, 256, s->st));
         double dv = 1.0;
         for (int a = 0; a < dim; ++a) dv *= pb.dx[a];
         CHK(launch_norm_final(part, P.np_norm, dv, do_renorm ? 1 : 0, scal, s->st));
-        if (tm) CHK(tm->mark(3));
+        if (e1) CHK(hipEventRecord(e1, s->st));
     }
 #undef CHK
     return hipSuccess;
@@ -439,10 +453,15 @@ static hipError_t enqueue_steps(sscn_solver *s, int64_t nsteps, Timer *tm)
         last_renorm = do_renorm;
     }
     if (imag && last_renorm) {
-        hipError_t e = launch_scale_state(s->P.elem, s->psi, s->P.npts, scal_ptr(s), s->P.pw_grid, 256, s->st);
-        if (e != hipSuccess) return e;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (tm) tm->pair(4, e0, e1);
+        hipError_t e = hipSuccess;
+        if (e0 && (e = hipEventRecord(e0, s->st)) != hipSuccess) return e;
+        if ((e = launch_scale_state(s->P.elem, s->psi, s->P.npts, scal_ptr(s), s->P.pw_grid, 256, s->st)) !=
+            hipSuccess)
+            return e;
         if ((e = launch_set_unit_scale(scal_ptr(s), s->st)) != hipSuccess) return e;
-        if (tm && (e = tm->mark(4)) != hipSuccess) return e;
+        if (e1 && (e = hipEventRecord(e1, s->st)) != hipSuccess) return e;
     }
     return hipSuccess;
 }
@@ -618,7 +637,7 @@ int sscn_step_timed(sscn_solver *s, int64_t nsteps, double *ms)
     if (!s || nsteps < 0 || !ms) return SSCN_E_INVALID;
     Timer tm;
     tm.st = s->st;
-    const size_t need = (size_t)nsteps * 6 + 4;
+    const size_t need = (size_t)nsteps * 8 + 4;   // a pair per kernel class and step
     try {
         tm.ev.resize(need);
         tm.cls.resize(need, -1);
@@ -635,11 +654,11 @@ int sscn_step_timed(sscn_solver *s, int64_t nsteps, double *ms)
     double tot[SSCN_NKERNELS] = {0};
     int cnt[SSCN_NKERNELS] = {0};
     if (rc == SSCN_OK) {
-        for (size_t i = 1; i < tm.used; ++i) {
+        for (size_t i = 0; i + 1 < tm.used; i += 2) {
             const int c = tm.cls[i];
             if (c < 0 || c >= SSCN_NKERNELS) continue;
             float f = 0.f;
-            if (hipEventElapsedTime(&f, tm.ev[i - 1], tm.ev[i]) != hipSuccess) {
+            if (hipEventElapsedTime(&f, tm.ev[i], tm.ev[i + 1]) != hipSuccess) {
                 rc = SSCN_E_HIP;
                 break;
             }

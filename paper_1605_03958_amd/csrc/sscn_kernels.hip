@@ -12,6 +12,8 @@
 // Fallbacks for lines too long to keep in registers: k_pointwise (separate
 // pointwise substep), k_stream (one thread per line, exact Thomas with the
 // forward intermediates stored in place) and k_norm_partials.
+#include <hip/hip_ext.h>
+
 #include "sscn_lines.hpp"
 
 namespace sscn {
@@ -350,34 +352,42 @@ __global__ void __launch_bounds__(256) k_density_2d(const void *psi_, int nx, in
     default: return hipErrorInvalidValue;         \
     }
 
+// The sweep launches go through hipExtLaunchKernelGGL: with a start/stop
+// event pair (timing runs) the events take the kernel's own begin and end
+// times; with null events it is a plain launch.
 template <class T, bool CPLX, int C>
-static void row_launch_c(bool last, const RowArgs &a, int grid, int block, size_t lds, hipStream_t st)
+static void row_launch_c(bool last, const RowArgs &a, int grid, int block, size_t lds, hipStream_t st,
+                         hipEvent_t e0, hipEvent_t e1)
 {
     const bool mw = a.wpl > 1;
-    if (last && mw) hipLaunchKernelGGL((k_row<T, CPLX, C, true, true>), dim3(grid), dim3(block), lds, st, a);
-    else if (last) hipLaunchKernelGGL((k_row<T, CPLX, C, true, false>), dim3(grid), dim3(block), lds, st, a);
-    else if (mw) hipLaunchKernelGGL((k_row<T, CPLX, C, false, true>), dim3(grid), dim3(block), lds, st, a);
-    else hipLaunchKernelGGL((k_row<T, CPLX, C, false, false>), dim3(grid), dim3(block), lds, st, a);
+    if (last && mw)
+        hipExtLaunchKernelGGL((k_row<T, CPLX, C, true, true>), dim3(grid), dim3(block), lds, st, e0, e1, 0, a);
+    else if (last)
+        hipExtLaunchKernelGGL((k_row<T, CPLX, C, true, false>), dim3(grid), dim3(block), lds, st, e0, e1, 0, a);
+    else if (mw)
+        hipExtLaunchKernelGGL((k_row<T, CPLX, C, false, true>), dim3(grid), dim3(block), lds, st, e0, e1, 0, a);
+    else
+        hipExtLaunchKernelGGL((k_row<T, CPLX, C, false, false>), dim3(grid), dim3(block), lds, st, e0, e1, 0, a);
 }
 
 template <class T, bool CPLX>
 static hipError_t row_launch(int C, bool last, const RowArgs &a, int grid, int block, size_t lds,
-                             hipStream_t st)
+                             hipStream_t st, hipEvent_t e0, hipEvent_t e1)
 {
     switch (C) {
-    case 1: row_launch_c<T, CPLX, 1>(last, a, grid, block, lds, st); break;
-    case 2: row_launch_c<T, CPLX, 2>(last, a, grid, block, lds, st); break;
-    case 4: row_launch_c<T, CPLX, 4>(last, a, grid, block, lds, st); break;
-    case 8: row_launch_c<T, CPLX, 8>(last, a, grid, block, lds, st); break;
+    case 1: row_launch_c<T, CPLX, 1>(last, a, grid, block, lds, st, e0, e1); break;
+    case 2: row_launch_c<T, CPLX, 2>(last, a, grid, block, lds, st, e0, e1); break;
+    case 4: row_launch_c<T, CPLX, 4>(last, a, grid, block, lds, st, e0, e1); break;
+    case 8: row_launch_c<T, CPLX, 8>(last, a, grid, block, lds, st, e0, e1); break;
     case 16:
         if constexpr (sizeof(typename Alg<T, CPLX>::V) <= 8) {
-            row_launch_c<T, CPLX, 16>(last, a, grid, block, lds, st);
+            row_launch_c<T, CPLX, 16>(last, a, grid, block, lds, st, e0, e1);
             break;
         }
         return hipErrorInvalidValue;
     case 32:
         if constexpr (sizeof(typename Alg<T, CPLX>::V) <= 4) {
-            row_launch_c<T, CPLX, 32>(last, a, grid, block, lds, st);
+            row_launch_c<T, CPLX, 32>(last, a, grid, block, lds, st, e0, e1);
             break;
         }
         return hipErrorInvalidValue;
@@ -387,39 +397,40 @@ static hipError_t row_launch(int C, bool last, const RowArgs &a, int grid, int b
 }
 
 hipError_t launch_row(int elem, int C, bool last, const RowArgs &a, int grid, int block, size_t lds,
-                      hipStream_t st)
+                      hipStream_t st, hipEvent_t e0, hipEvent_t e1)
 {
-#define ROW_CASE(T, CP) return row_launch<T, CP>(C, last, a, grid, block, lds, st)
+#define ROW_CASE(T, CP) return row_launch<T, CP>(C, last, a, grid, block, lds, st, e0, e1)
     SSCN_ELEM_DISPATCH(elem, ROW_CASE)
 #undef ROW_CASE
 }
 
 template <class T, bool CPLX, int C>
-static void col_launch_c(bool last, const ColArgs &a, int grid, int block, size_t lds, hipStream_t st)
+static void col_launch_c(bool last, const ColArgs &a, int grid, int block, size_t lds, hipStream_t st,
+                         hipEvent_t e0, hipEvent_t e1)
 {
-    if (last) hipLaunchKernelGGL((k_col<T, CPLX, C, true>), dim3(grid), dim3(block), lds, st, a);
-    else hipLaunchKernelGGL((k_col<T, CPLX, C, false>), dim3(grid), dim3(block), lds, st, a);
+    if (last) hipExtLaunchKernelGGL((k_col<T, CPLX, C, true>), dim3(grid), dim3(block), lds, st, e0, e1, 0, a);
+    else hipExtLaunchKernelGGL((k_col<T, CPLX, C, false>), dim3(grid), dim3(block), lds, st, e0, e1, 0, a);
 }
 
 template <class T, bool CPLX>
 static hipError_t col_launch(int C, bool last, const ColArgs &a, int grid, int block, size_t lds,
-                             hipStream_t st)
+                             hipStream_t st, hipEvent_t e0, hipEvent_t e1)
 {
     switch (C) {
-    case 1: col_launch_c<T, CPLX, 1>(last, a, grid, block, lds, st); break;
-    case 2: col_launch_c<T, CPLX, 2>(last, a, grid, block, lds, st); break;
-    case 4: col_launch_c<T, CPLX, 4>(last, a, grid, block, lds, st); break;
-    case 8: col_launch_c<T, CPLX, 8>(last, a, grid, block, lds, st); break;
-    case 16: col_launch_c<T, CPLX, 16>(last, a, grid, block, lds, st); break;
+    case 1: col_launch_c<T, CPLX, 1>(last, a, grid, block, lds, st, e0, e1); break;
+    case 2: col_launch_c<T, CPLX, 2>(last, a, grid, block, lds, st, e0, e1); break;
+    case 4: col_launch_c<T, CPLX, 4>(last, a, grid, block, lds, st, e0, e1); break;
+    case 8: col_launch_c<T, CPLX, 8>(last, a, grid, block, lds, st, e0, e1); break;
+    case 16: col_launch_c<T, CPLX, 16>(last, a, grid, block, lds, st, e0, e1); break;
     case 32:
         if constexpr (sizeof(typename Alg<T, CPLX>::V) <= 8) {
-            col_launch_c<T, CPLX, 32>(last, a, grid, block, lds, st);
+            col_launch_c<T, CPLX, 32>(last, a, grid, block, lds, st, e0, e1);
             break;
         }
         return hipErrorInvalidValue;
     case 64:
         if constexpr (sizeof(typename Alg<T, CPLX>::V) <= 4) {
-            col_launch_c<T, CPLX, 64>(last, a, grid, block, lds, st);
+            col_launch_c<T, CPLX, 64>(last, a, grid, block, lds, st, e0, e1);
             break;
         }
         return hipErrorInvalidValue;
@@ -429,9 +440,9 @@ static hipError_t col_launch(int C, bool last, const ColArgs &a, int grid, int b
 }
 
 hipError_t launch_col(int elem, int C, bool last, const ColArgs &a, int grid, int block, size_t lds,
-                      hipStream_t st)
+                      hipStream_t st, hipEvent_t e0, hipEvent_t e1)
 {
-#define COL_CASE(T, CP) return col_launch<T, CP>(C, last, a, grid, block, lds, st)
+#define COL_CASE(T, CP) return col_launch<T, CP>(C, last, a, grid, block, lds, st, e0, e1)
     SSCN_ELEM_DISPATCH(elem, COL_CASE)
 #undef COL_CASE
 }

@@ -61,10 +61,12 @@ struct PointArgs {
 };
 
 // Kernel launchers.  elem: 0 double, 1 float, 2 complex<double>, 3 complex<float>.
+// e0/e1: optional start/stop events that take the kernel's own begin and
+// end times (null: a plain launch).
 hipError_t launch_row(int elem, int C, bool last, const RowArgs &a, int grid, int block,
-                      size_t lds, hipStream_t st);
+                      size_t lds, hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_col(int elem, int C, bool last, const ColArgs &a, int grid, int block,
-                      size_t lds, hipStream_t st);
+                      size_t lds, hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_stream(int elem, const ColArgs &a, int grid, int block, hipStream_t st);
 hipError_t launch_pointwise(int elem, const PointArgs &a, int grid, int block, hipStream_t st);
 hipError_t launch_norm_partials(int elem, const void *psi, int64_t npts, double *partial,

@@ -5,7 +5,8 @@ Input: three rocprofv3 output directories of the same bench.py command
   fetch  --pmc FETCH_SIZE         (counter_collection.csv)
   write  --pmc WRITE_SIZE         (counter_collection.csv)
 Output: profiles/<name>.md (durations, counters, calibration) and an entry
-in profiles/pmc_traffic.json that bench.py reads as roofline.traffic.
+in profiles/pmc_traffic.json that bench.py reads as roofline.traffic.  With
+--trace alone: the kernel statistics only.
 
 HBM traffic per launch = FETCH_SIZE * f_fetch + WRITE_SIZE * f_write, where
 f_* = (bytes a plain device copy of known size must move) / (what the same
@@ -32,9 +33,13 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 
 
+# the device sources of the single-problem kernels
+KERNEL_SOURCES = ("sscn_dev.hpp", "sscn_lines.hpp", "sscn_launch.hpp", "sscn_kernels.hip")
+
+
 def source_hash() -> str:
     h = hashlib.sha256()
-    for name in ("sscn_dev.hpp", "sscn_kernels.hip"):
+    for name in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_1605_03958_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -87,16 +92,39 @@ def trace_means(path: str):
     return {k: sum(v) / len(v) for k, v in acc.items()}
 
 
+def trace_only(args) -> None:
+    """Kernel statistics of a trace run alone (the persistent batch kernel,
+    whose work per launch varies with the set of running instances)."""
+    stats = list(csv.DictReader(open(_find(args.trace, "kernel_stats.csv"))))
+    lines = [f"# rocprofv3 summary: {args.name}", "", f"Workload: `{args.workload}`.", "",
+             "Command (run from the repository root on the GPU box):", "", "```", args.command.strip(), "```", "",
+             "## Kernel statistics (--kernel-trace --stats)", "",
+             "| kernel | calls | average us | min us | max us | total ms | share % |",
+             "|---|---|---|---|---|---|---|"]
+    for r in stats:
+        lines.append(f"| `{r['Name'][:90]}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | "
+                     f"{float(r['TotalDurationNs']) / 1e6:.1f} | {float(r['Percentage']):.2f} |")
+    lines.append("")
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    with open(os.path.join(ROOT, "profiles", f"{args.name}.md"), "w") as f:
+        f.write("\n".join(lines))
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--trace", required=True)
-    ap.add_argument("--fetch", required=True)
-    ap.add_argument("--write", required=True)
+    ap.add_argument("--fetch")
+    ap.add_argument("--write")
     ap.add_argument("--workload", required=True)
-    ap.add_argument("--state-bytes", type=int, required=True)
+    ap.add_argument("--state-bytes", type=int)
     ap.add_argument("--name", required=True)
     ap.add_argument("--command", default="")
     args = ap.parse_args()
+    if not args.fetch or not args.write:
+        trace_only(args)
+        return
 
     stats = list(csv.DictReader(open(_find(args.trace, "kernel_stats.csv"))))
     dur = trace_means(_find(args.trace, "kernel_trace.csv"))
