@@ -202,17 +202,30 @@ __device__ __forceinline__ void batch_obs(const BInst &I, const BState &S, int t
 __device__ __forceinline__ void batch_fin(const BInst &I, BState &S, double *red)
 {
     const int nt = I.ax[I.last_pass].ntiles;
-    double acc = 0.0;
-    for (int i = threadIdx.x; i < nt; i += blockDim.x) acc += I.norm_part[i];
-    const double nraw = block_sum(acc, red);
     const bool obs_now = batch_observes(I, S);
+    double nraw = 0.0;
     double tot[BATCH_NOBS];
     for (int q = 0; q < BATCH_NOBS; ++q) tot[q] = 0.0;
+    // one partial: thread 0 takes it as it is (the block sum would add
+    // exact zeros to it); several: fixed-order block sums
+    if (nt == 1) {
+        if (threadIdx.x == 0) nraw = I.norm_part[0];
+    } else {
+        double acc = 0.0;
+        for (int i = threadIdx.x; i < nt; i += blockDim.x) acc += I.norm_part[i];
+        nraw = block_sum(acc, red);
+    }
     if (obs_now) {
-        for (int q = 0; q < BATCH_NOBS; ++q) {
-            double a = 0.0;
-            for (int i = threadIdx.x; i < I.obs_tiles; i += blockDim.x) a += I.obs_part[(size_t)i * BATCH_NOBS + q];
-            tot[q] = block_sum(a, red);
+        if (I.obs_tiles == 1) {
+            if (threadIdx.x == 0)
+                for (int q = 0; q < BATCH_NOBS; ++q) tot[q] = I.obs_part[q];
+        } else {
+            for (int q = 0; q < BATCH_NOBS; ++q) {
+                double a = 0.0;
+                for (int i = threadIdx.x; i < I.obs_tiles; i += blockDim.x)
+                    a += I.obs_part[(size_t)i * BATCH_NOBS + q];
+                tot[q] = block_sum(a, red);
+            }
         }
     }
     if (threadIdx.x != 0) return;

@@ -31,6 +31,7 @@ enum { BP_X = 0, BP_Y = 1, BP_Z = 2, BP_OBS = 3, BP_FIN = 4, BP_NPASS = 5, BP_SO
 enum { BS_EMPTY = 0, BS_RUNNING = 1, BS_CONVERGED = 2, BS_DONE = 3, BS_NONFINITE = 4, BS_STALLED = 5 };
 
 constexpr int BATCH_BLOCK = 1024;     // threads per block of the persistent kernel
+constexpr int BATCH_LDS = 64 * 1024;  // dynamic LDS bytes of every persistent block
 constexpr int BATCH_OBS_PTS = 16384;  // grid points per observation tile
 constexpr int BATCH_NOBS = 10;        // FP64 sums per observation tile
 constexpr int BATCH_SOLO_MAX = 256;   // steps of a solo instance per launch, at most

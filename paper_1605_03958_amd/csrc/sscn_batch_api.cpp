@@ -26,7 +26,7 @@ using namespace sscn;
 
 namespace {
 
-constexpr size_t kBatchLds = 64 * 1024;  // dynamic LDS of every persistent block
+constexpr size_t kBatchLds = BATCH_LDS;  // dynamic LDS of every persistent block
 constexpr int kSpinLimit = 1 << 24;      // bounded waits: ~1 s of polling before giving up
 
 size_t a256(size_t v) { return (v + 255) & ~size_t(255); }
