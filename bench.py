@@ -97,24 +97,28 @@ def copy_bandwidth(nbytes: int, reps: int = 20):
 
 def cpu_baseline(target_s: float = 12.0):
     """The FP64 oracle on a bounded sample of the same workload: the full
-    256^3 grid for as many steps as fit in about target_s seconds."""
+    256^3 grid, one untimed step (thread start-up, first touch), then runs of
+    steps until about target_s seconds have been timed."""
     import oracle
     from paper_1605_03958_amd import inputs
     p = c1_problem(0)
     op = oracle.Problem(p.dim, p.n, p.dx, p.omega, p.g, p.dt, p.mode, p.renorm_every)
-    psi0 = inputs.thomas_fermi(3, p.n, p.dx, p.omega, 100.0, phase_sigma=0.05, seed=1)
-    t0 = time.perf_counter()
-    r = oracle.run(op, psi0, 2)
-    t2 = time.perf_counter() - t0
-    steps = max(1, int(2 * target_s / max(t2, 1e-3)) - 2)
-    t0 = time.perf_counter()
-    oracle.run(op, r.psi, steps, first_step=3)
-    dt = time.perf_counter() - t0
-    total = steps + 2
-    return {"value": p.points * total / (dt + t2), "unit": "grid-point-steps/s", "cores": oracle.threads(),
+    psi = inputs.thomas_fermi(3, p.n, p.dx, p.omega, 100.0, phase_sigma=0.05, seed=1)
+    psi = oracle.run(op, psi, 1).psi
+    step, steps, el = 2, 0, 0.0
+    chunk = 2
+    while el < target_s:
+        t0 = time.perf_counter()
+        psi = oracle.run(op, psi, chunk, first_step=step).psi
+        dt = time.perf_counter() - t0
+        el += dt
+        steps += chunk
+        step += chunk
+        chunk = max(1, min(50, int(0.25 * target_s * chunk / max(dt, 1e-3))))
+    return {"value": p.points * steps / el, "unit": "grid-point-steps/s", "cores": oracle.threads(),
             "kind": "oracle",
-            "sample": f"256^3 complex128 real-time workload, first {total} steps ({dt + t2:.1f} s), "
-                      f"FP64 C oracle with OpenMP over lines"}
+            "sample": f"256^3 complex128 real-time workload, steps 2-{step - 1} ({steps} steps, {el:.1f} s "
+                      f"timed after one untimed step), FP64 C oracle with OpenMP over lines"}
 
 
 def c3_problems():
