@@ -14,6 +14,14 @@
 
 namespace sscn {
 
+// Pointers the kernel reads from the instance table are generic, and a
+// generic access is a flat instruction, which counts against the LDS
+// counter as well: every LDS wait of the line solve would then also wait for
+// the state loads in flight.  They all point to device memory, so they are
+// used as global pointers (the compiler then emits global loads and stores).
+template <class P>
+using GP = __attribute__((address_space(1))) P *;
+
 // ---------------------------------------------------------------------------
 // items
 // ---------------------------------------------------------------------------
@@ -23,7 +31,12 @@ __device__ __forceinline__ void batch_row(const BInst &I, const BState &S, int t
 {
     using A = Alg<T, CPLX>;
     using V = typename A::V;
-    const BAxis &X = I.ax[0];
+    // the descriptor in registers: a reference into global memory would be
+    // reloaded after every block barrier (a memory fence), and each reload's
+    // wait would also wait for the loads issued ahead for the next line group
+    const BAxis X = I.ax[0];
+    const GP<const TabEntry> tab = (GP<const TabEntry>)X.lt.tab;
+    const PointParams pp = I.pp;
     const int G = MW ? 64 * X.wpl : 64;
     const int tid = threadIdx.x;
     const int lb = tid / G;
@@ -33,19 +46,20 @@ __device__ __forceinline__ void batch_row(const BInst &I, const BState &S, int t
     LTab<T, CPLX> *tl = reinterpret_cast<LTab<T, CPLX> *>(lds);
     V *xs = reinterpret_cast<V *>(lds) + lb * X.wpl * 4;
     if constexpr (!MW) {
-        stage_table<T, CPLX>(X.lt, tl, C * 64, 64, C);
+        stage_table_from<T, CPLX>(X.lt, tab, tl, C * 64, 64, C);
         __syncthreads();
     }
     const V sig = A::coef(X.sig_re, X.sig_im);
     const T scale = CPLX ? T(1) : T(S.scale);
-    V *psi = reinterpret_cast<V *>(I.psi);
+    const GP<V> psi = (GP<V>)I.psi;
+    const GP<double> norm_part = (GP<double>)I.norm_part;
     double nacc = 0.0;
     const long long line0 = (long long)tile * X.rep * X.lpi + lb;
     if constexpr (MW) {
         for (int r = 0; r < X.rep; ++r) {
             const long long line = line0 + (long long)r * X.lpi;
-            nacc += row_line<T, CPLX, C, true>(psi, line, line < X.nlines, X.lt.n, X.lt.tab, G, t, lane, wl, X.wpl,
-                                               xs, sig, scale, T(I.pp.dt), T(I.pp.g), I.pp, X.lt.depth, last);
+            nacc += row_line<T, CPLX, C, true>(psi, line, line < X.nlines, X.lt.n, tab, G, t, lane, wl, X.wpl,
+                                               xs, sig, scale, T(pp.dt), T(pp.g), pp, X.lt.depth, last);
         }
     } else {
         // one block runs an item, so the loads of the next line group are
@@ -64,7 +78,7 @@ __device__ __forceinline__ void batch_row(const BInst &I, const BState &S, int t
             }
             nacc += row_solve<T, CPLX, C, false>(psi, line, line < X.nlines, X.lt.n,
                                                  static_cast<const LTab<T, CPLX> *>(tl), G, t, lane, wl, 1, xs, sig,
-                                                 scale, T(I.pp.dt), T(I.pp.g), I.pp, X.lt.depth, last, u);
+                                                 scale, T(pp.dt), T(pp.g), pp, X.lt.depth, last, u);
             if constexpr (PF) {
 #pragma unroll
                 for (int k = 0; k < C; ++k) u[k] = nx[k];
@@ -73,7 +87,7 @@ __device__ __forceinline__ void batch_row(const BInst &I, const BState &S, int t
     }
     if (last) {
         const double s = block_sum(nacc, red);
-        if (tid == 0) I.norm_part[tile] = s;
+        if (tid == 0) norm_part[tile] = s;
     }
 }
 
@@ -83,7 +97,9 @@ __device__ __forceinline__ void batch_col(const BInst &I, int axis, int tile, un
 {
     using A = Alg<T, CPLX>;
     using V = typename A::V;
-    const BAxis &X = I.ax[axis];
+    const BAxis X = I.ax[axis];           // in registers (see batch_row)
+    const GP<const TabEntry> tab = (GP<const TabEntry>)X.lt.tab;
+    const GP<double> norm_part = (GP<double>)I.norm_part;
     const int L = X.L, W = X.W;
     const int LPB = 64 / L;
     const int nch = W * L;
@@ -97,8 +113,8 @@ __device__ __forceinline__ void batch_col(const BInst &I, int axis, int tile, un
     LTab<T, CPLX> *tb = reinterpret_cast<LTab<T, CPLX> *>(lds);
     V *xs0 = reinterpret_cast<V *>(tb + nch * C) + st_i * (2 * nch * LPB);
     V *xs1 = xs0 + nch * LPB;
-    stage_table<T, CPLX>(X.lt, tb, nch * C, 0, C);
-    V *psi = reinterpret_cast<V *>(I.psi);
+    stage_table_from<T, CPLX>(X.lt, tab, tb, nch * C, 0, C);
+    const GP<V> psi = (GP<V>)I.psi;
     // this lane's line in set r, and its first point
     auto line_of = [&](int r) { return (((long long)tile * X.rep + r) * X.tpi + st_i) * LPB + li; };
     auto base_of = [&](long long line) {
@@ -137,7 +153,7 @@ __device__ __forceinline__ void batch_col(const BInst &I, int axis, int tile, un
     }
     if (last) {
         const double s = block_sum(nacc, red);
-        if (threadIdx.x == 0) I.norm_part[tile] = s;
+        if (threadIdx.x == 0) norm_part[tile] = s;
     }
 }
 
@@ -154,29 +170,33 @@ __device__ __forceinline__ void batch_obs(const BInst &I, const BState &S, int t
     using A = Alg<T, CPLX>;
     using V = typename A::V;
     if (!batch_observes(I, S)) return;
-    const V *psi = reinterpret_cast<const V *>(I.psi);
-    const long long nx = I.pp.n[0], ny = I.pp.n[1];
-    const int n3[3] = {I.pp.n[0], I.pp.n[1], I.pp.n[2]};
+    const GP<const V> psi = (GP<const V>)I.psi;
+    const PointParams pp = I.pp;
+    const int dim = I.dim;
+    const long long npts = I.npts;
+    const GP<double> obs_part = (GP<double>)I.obs_part;
+    const long long nx = pp.n[0], ny = pp.n[1];
+    const int n3[3] = {pp.n[0], pp.n[1], pp.n[2]};
     const long long sx[3] = {1, nx, nx * ny};
     double acc[BATCH_NOBS];
 #pragma unroll
     for (int q = 0; q < BATCH_NOBS; ++q) acc[q] = 0.0;
     const long long p0 = (long long)tile * BATCH_OBS_PTS;
-    const long long p1 = min((long long)I.npts, p0 + BATCH_OBS_PTS);
+    const long long p1 = min(npts, p0 + BATCH_OBS_PTS);
     for (long long p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
         const int idx[3] = {(int)(p % nx), (int)((p / nx) % ny), (int)(p / (nx * ny))};
-        const V v = psi[p];
+        const V v = ld_elem(psi, p);
         const double q = A::norm2(v);
         double vp = 0.0, kin = 0.0;
-        for (int ax = 0; ax < I.dim; ++ax) {
-            const double x = (double(idx[ax]) - I.pp.cen[ax]) * I.pp.dx[ax];
-            vp += I.pp.w2h[ax] * x * x;
+        for (int ax = 0; ax < dim; ++ax) {
+            const double x = (double(idx[ax]) - pp.cen[ax]) * pp.dx[ax];
+            vp += pp.w2h[ax] * x * x;
             acc[4 + ax] += x * q;
             acc[7 + ax] += x * x * q;
-            const V nb = (idx[ax] + 1 < n3[ax]) ? psi[p + sx[ax]] : A::zero();
+            const V nb = (idx[ax] + 1 < n3[ax]) ? ld_elem(psi, p + sx[ax]) : A::zero();
             double e = A::norm2(A::sub(nb, v));
             if (idx[ax] == 0) e += q;
-            kin += e / (I.pp.dx[ax] * I.pp.dx[ax]);
+            kin += e / (pp.dx[ax] * pp.dx[ax]);
         }
         acc[0] += q;
         acc[1] += kin;
@@ -194,7 +214,7 @@ __device__ __forceinline__ void batch_obs(const BInst &I, const BState &S, int t
         const int q = threadIdx.x;
         double s = 0.0;
         for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += redq[q][w];
-        I.obs_part[(size_t)tile * BATCH_NOBS + q] = s;
+        obs_part[(size_t)tile * BATCH_NOBS + q] = s;
     }
 }
 
@@ -203,27 +223,29 @@ __device__ __forceinline__ void batch_fin(const BInst &I, BState &S, double *red
 {
     const int nt = I.ax[I.last_pass].ntiles;
     const bool obs_now = batch_observes(I, S);
+    const GP<const double> norm_part = (GP<const double>)I.norm_part;
+    const GP<const double> obs_part = (GP<const double>)I.obs_part;
     double nraw = 0.0;
     double tot[BATCH_NOBS];
     for (int q = 0; q < BATCH_NOBS; ++q) tot[q] = 0.0;
     // one partial: thread 0 takes it as it is (the block sum would add
     // exact zeros to it); several: fixed-order block sums
     if (nt == 1) {
-        if (threadIdx.x == 0) nraw = I.norm_part[0];
+        if (threadIdx.x == 0) nraw = norm_part[0];
     } else {
         double acc = 0.0;
-        for (int i = threadIdx.x; i < nt; i += blockDim.x) acc += I.norm_part[i];
+        for (int i = threadIdx.x; i < nt; i += blockDim.x) acc += norm_part[i];
         nraw = block_sum(acc, red);
     }
     if (obs_now) {
         if (I.obs_tiles == 1) {
             if (threadIdx.x == 0)
-                for (int q = 0; q < BATCH_NOBS; ++q) tot[q] = I.obs_part[q];
+                for (int q = 0; q < BATCH_NOBS; ++q) tot[q] = obs_part[q];
         } else {
             for (int q = 0; q < BATCH_NOBS; ++q) {
                 double a = 0.0;
                 for (int i = threadIdx.x; i < I.obs_tiles; i += blockDim.x)
-                    a += I.obs_part[(size_t)i * BATCH_NOBS + q];
+                    a += obs_part[(size_t)i * BATCH_NOBS + q];
                 tot[q] = block_sum(a, red);
             }
         }

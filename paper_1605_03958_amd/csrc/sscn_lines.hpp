@@ -190,8 +190,59 @@ struct LTab<float, CPLX> {
 // group threads; COL: i = q).  Only the head of the table below lt.i_conv
 // is read from memory; the constant tail is written from lt's constant
 // entry and points past the line end get zeros.
-template <class T, bool CPLX>
-__device__ __forceinline__ void stage_table(const LineTab &lt, LTab<T, CPLX> *dst, int cnt, int G, int C)
+// Element access to the state through a generic pointer or a global one
+// (address space 1).  A complex value in global memory moves as a native
+// two-element vector: class types cannot be copied through such pointers.
+template <class V>
+__device__ __forceinline__ V ld_elem(const V *p, long long i)
+{
+    return p[i];
+}
+template <class V>
+__device__ __forceinline__ void st_elem(V *p, long long i, V v)
+{
+    p[i] = v;
+}
+template <class T>
+__device__ __forceinline__ T ld_elem(const __attribute__((address_space(1))) T *p, long long i)
+{
+    return p[i];
+}
+template <class T>
+__device__ __forceinline__ void st_elem(__attribute__((address_space(1))) T *p, long long i, T v)
+{
+    p[i] = v;
+}
+template <class T>
+__device__ __forceinline__ cpx<T> ld_elem(const __attribute__((address_space(1))) cpx<T> *p, long long i)
+{
+    typedef T W __attribute__((ext_vector_type(2)));
+    const W w = reinterpret_cast<const __attribute__((address_space(1))) W *>(p)[i];
+    return cpx<T>{w.x, w.y};
+}
+template <class T>
+__device__ __forceinline__ void st_elem(__attribute__((address_space(1))) cpx<T> *p, long long i, cpx<T> v)
+{
+    typedef T W __attribute__((ext_vector_type(2)));
+    W w;
+    w.x = v.re;
+    w.y = v.im;
+    reinterpret_cast<__attribute__((address_space(1))) W *>(p)[i] = w;
+}
+
+// One FP64 table entry through a generic or a global pointer (field by
+// field: a struct cannot be copied through an address-space pointer).
+__device__ __forceinline__ TabEntry ld_tab(const TabEntry *p, int q) { return p[q]; }
+__device__ __forceinline__ TabEntry ld_tab(const __attribute__((address_space(1))) TabEntry *p, int q)
+{
+    const __attribute__((address_space(1))) double *d = reinterpret_cast<const __attribute__((address_space(1))) double *>(p + q);
+    return TabEntry{d[0], d[1], d[2], d[3]};
+}
+
+// As stage_table, reading the table through tab (a pointer of any address
+// space to lt's table).
+template <class T, bool CPLX, class TP>
+__device__ __forceinline__ void stage_table_from(const LineTab &lt, TP tab, LTab<T, CPLX> *dst, int cnt, int G, int C)
 {
     const LTab<T, CPLX> tail = LTab<T, CPLX>::make(TabEntry{lt.ac_re, lt.ac_im, lt.mc_re, lt.mc_im});
     const LTab<T, CPLX> zero = LTab<T, CPLX>::make(TabEntry{0.0, 0.0, 0.0, 0.0});
@@ -199,9 +250,15 @@ __device__ __forceinline__ void stage_table(const LineTab &lt, LTab<T, CPLX> *ds
         const int i = (G > 0) ? (q % G) * C + q / G : q;
         LTab<T, CPLX> e = tail;
         if (i >= lt.n) e = zero;
-        else if (i < lt.i_conv) e = LTab<T, CPLX>::make(lt.tab[q]);
+        else if (i < lt.i_conv) e = LTab<T, CPLX>::make(ld_tab(tab, q));
         dst[q] = e;
     }
+}
+
+template <class T, bool CPLX>
+__device__ __forceinline__ void stage_table(const LineTab &lt, LTab<T, CPLX> *dst, int cnt, int G, int C)
+{
+    stage_table_from<T, CPLX>(lt, lt.tab, dst, cnt, G, C);
 }
 
 // Table entry q from LDS (staged) or from the FP64 table in global memory.
@@ -217,6 +274,12 @@ __device__ __forceinline__ LTab<T, CPLX> tab_at(const TabEntry *tb, int q)
     return LTab<T, CPLX>::make(tb[q]);
 }
 
+template <class T, bool CPLX>
+__device__ __forceinline__ LTab<T, CPLX> tab_at(const __attribute__((address_space(1))) TabEntry *tb, int q)
+{
+    return LTab<T, CPLX>::make(ld_tab(tb, q));
+}
+
 // ---------------------------------------------------------------------------
 // ROW: one x line per line group.  xs: 4 values per wave of the group (LDS,
 // used when MW).  Returns the thread's sum |v|^2 when `last`.  The load of
@@ -224,8 +287,8 @@ __device__ __forceinline__ LTab<T, CPLX> tab_at(const TabEntry *tb, int q)
 // caller can issue the next line's loads before solving the current one;
 // row_line does both.
 // ---------------------------------------------------------------------------
-template <class T, bool CPLX, int C, bool MW, class TB>
-__device__ __forceinline__ double row_solve(typename Alg<T, CPLX>::V *__restrict__ psi, long long line,
+template <class T, bool CPLX, int C, bool MW, class TB, class PV>
+__device__ __forceinline__ double row_solve(PV __restrict__ psi, long long line,
                                             bool active, int n, const TB *tb, int G, int t, int lane, int wl,
                                             int wpl, typename Alg<T, CPLX>::V *xs, typename Alg<T, CPLX>::V sig,
                                             T scale, T dt, T g, const PointParams &pp, int ks, bool last,
@@ -368,7 +431,7 @@ __device__ __forceinline__ double row_solve(typename Alg<T, CPLX>::V *__restrict
     for (int k = 0; k < C; ++k) {
         const int i = i0 + k;
         if (active && i < n) {
-            psi[base + i] = be[k];
+            st_elem(psi, base + i, be[k]);
             if (last) nacc += A::norm2(be[k]);
         }
     }
@@ -376,8 +439,8 @@ __device__ __forceinline__ double row_solve(typename Alg<T, CPLX>::V *__restrict
 }
 
 // The C values of this lane's chunk of one line (zero past the end).
-template <class T, bool CPLX, int C>
-__device__ __forceinline__ void row_load(const typename Alg<T, CPLX>::V *__restrict__ psi, long long line,
+template <class T, bool CPLX, int C, class PV>
+__device__ __forceinline__ void row_load(PV __restrict__ psi, long long line,
                                          bool active, int n, int t, typename Alg<T, CPLX>::V (&u)[C])
 {
     using A = Alg<T, CPLX>;
@@ -386,19 +449,19 @@ __device__ __forceinline__ void row_load(const typename Alg<T, CPLX>::V *__restr
 #pragma unroll
     for (int k = 0; k < C; ++k) {
         const int i = i0 + k;
-        u[k] = (active && i < n) ? psi[base + i] : A::zero();
+        u[k] = (active && i < n) ? ld_elem(psi, base + i) : A::zero();
     }
 }
 
-template <class T, bool CPLX, int C, bool MW, class TB>
-__device__ __forceinline__ double row_line(typename Alg<T, CPLX>::V *__restrict__ psi, long long line,
+template <class T, bool CPLX, int C, bool MW, class TB, class PV>
+__device__ __forceinline__ double row_line(PV __restrict__ psi, long long line,
                                            bool active, int n, const TB *tb, int G, int t, int lane, int wl,
                                            int wpl, typename Alg<T, CPLX>::V *xs, typename Alg<T, CPLX>::V sig,
                                            T scale, T dt, T g, const PointParams &pp, int ks, bool last)
 {
     typename Alg<T, CPLX>::V u[C];
     row_load<T, CPLX, C>(psi, line, active, n, t, u);
-    return row_solve<T, CPLX, C, MW, TB>(psi, line, active, n, tb, G, t, lane, wl, wpl, xs, sig, scale, dt, g, pp,
+    return row_solve<T, CPLX, C, MW, TB, PV>(psi, line, active, n, tb, G, t, lane, wl, wpl, xs, sig, scale, dt, g, pp,
                                          ks, last, u);
 }
 
@@ -408,8 +471,8 @@ __device__ __forceinline__ double row_line(typename Alg<T, CPLX>::V *__restrict_
 // xs0/xs1 hold nch x LPB values each.  Returns sum |v|^2 when `last`.
 // col_load / col_solve split it like row_load / row_solve.
 // ---------------------------------------------------------------------------
-template <class T, bool CPLX, int C>
-__device__ __forceinline__ double col_solve(typename Alg<T, CPLX>::V *__restrict__ psi, bool active,
+template <class T, bool CPLX, int C, class PV>
+__device__ __forceinline__ double col_solve(PV __restrict__ psi, bool active,
                                             long long base, int n, long long st, int nch, int ch, int LPB, int li,
                                             const LTab<T, CPLX> *tb, typename Alg<T, CPLX>::V *xs0,
                                             typename Alg<T, CPLX>::V *xs1, typename Alg<T, CPLX>::V sig, int depth,
@@ -476,7 +539,7 @@ __device__ __forceinline__ double col_solve(typename Alg<T, CPLX>::V *__restrict
     for (int k = 0; k < C; ++k) {
         const int i = i0 + k;
         if (active && i < n) {
-            psi[base + (long long)i * st] = be[k];
+            st_elem(psi, base + (long long)i * st, be[k]);
             if (last) nacc += A::norm2(be[k]);
         }
     }
@@ -484,8 +547,8 @@ __device__ __forceinline__ double col_solve(typename Alg<T, CPLX>::V *__restrict
 }
 
 // The C values of chunk ch of this lane's line (zero past the end).
-template <class T, bool CPLX, int C>
-__device__ __forceinline__ void col_load(const typename Alg<T, CPLX>::V *__restrict__ psi, bool active,
+template <class T, bool CPLX, int C, class PV>
+__device__ __forceinline__ void col_load(PV __restrict__ psi, bool active,
                                          long long base, int n, long long st, int ch,
                                          typename Alg<T, CPLX>::V (&u)[C])
 {
@@ -494,12 +557,12 @@ __device__ __forceinline__ void col_load(const typename Alg<T, CPLX>::V *__restr
 #pragma unroll
     for (int k = 0; k < C; ++k) {
         const int i = i0 + k;
-        u[k] = (active && i < n) ? psi[base + (long long)i * st] : A::zero();
+        u[k] = (active && i < n) ? ld_elem(psi, base + (long long)i * st) : A::zero();
     }
 }
 
-template <class T, bool CPLX, int C>
-__device__ __forceinline__ double col_tile(typename Alg<T, CPLX>::V *__restrict__ psi, bool active,
+template <class T, bool CPLX, int C, class PV>
+__device__ __forceinline__ double col_tile(PV __restrict__ psi, bool active,
                                            long long base, int n, long long st, int nch, int ch, int LPB, int li,
                                            const LTab<T, CPLX> *tb, typename Alg<T, CPLX>::V *xs0,
                                            typename Alg<T, CPLX>::V *xs1, typename Alg<T, CPLX>::V sig, int depth,
