@@ -258,3 +258,14 @@ def test_batch_tile_hints():
     finally:
         sscn.batch_clear_tile_hints()
     assert sscn.batch_plan_info(p) == base
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py runs on one GPU; --gpus above 1 exits with a message before
+    touching a device."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], cwd=root,
+                         capture_output=True, text=True, timeout=300)
+    assert out.returncode == 2 and "one GPU" in out.stderr and out.stdout == ""
