@@ -4,7 +4,7 @@
 // ordering and waiting scheme is described in sscn_batch.hpp).  Work items:
 //   x tile    ROW line solve (pointwise substep + pending scale fused)
 //   y/z tile  COL line solve; the last sweep writes one FP64 norm partial
-//   obs tile  FP64 sums of the observables over 16384 points, on
+//   obs tile  FP64 sums of the observables over a block of points, on
 //             observation steps only
 //   fin       fixed-order sums -> renormalisation factor, mu, E, the
 //             convergence test and the instance's step count
@@ -181,8 +181,8 @@ __device__ __forceinline__ void batch_obs(const BInst &I, const BState &S, int t
     double acc[BATCH_NOBS];
 #pragma unroll
     for (int q = 0; q < BATCH_NOBS; ++q) acc[q] = 0.0;
-    const long long p0 = (long long)tile * BATCH_OBS_PTS;
-    const long long p1 = min(npts, p0 + BATCH_OBS_PTS);
+    const long long p0 = (long long)tile * I.obs_pts;
+    const long long p1 = min(npts, p0 + (long long)I.obs_pts);
     for (long long p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
         const int idx[3] = {(int)(p % nx), (int)((p / nx) % ny), (int)(p / (nx * ny))};
         const V v = ld_elem(psi, p);

@@ -32,7 +32,7 @@ enum { BS_EMPTY = 0, BS_RUNNING = 1, BS_CONVERGED = 2, BS_DONE = 3, BS_NONFINITE
 
 constexpr int BATCH_BLOCK = 1024;     // threads per block of the persistent kernel
 constexpr int BATCH_LDS = 64 * 1024;  // dynamic LDS bytes of every persistent block
-constexpr int BATCH_OBS_PTS = 16384;  // grid points per observation tile
+constexpr int BATCH_OBS_PTS = 16384;  // grid points per observation tile, at least
 constexpr int BATCH_NOBS = 10;        // FP64 sums per observation tile
 constexpr int BATCH_SOLO_MAX = 256;   // steps of a solo instance per launch, at most
 constexpr int BATCH_SOLO_ONLY = 64;   // ... and at least, once only solo instances run
@@ -66,6 +66,7 @@ struct BInst {
     double *norm_part;     // one FP64 per tile of the last sweep
     double *obs_part;      // BATCH_NOBS FP64 per observation tile
     int32_t obs_tiles;
+    int64_t obs_pts;       // grid points per observation tile
     int32_t observe_every;
     double mu_tol;         // > 0: stop at |mu - mu_prev| < mu_tol between observations
     int64_t max_steps;

@@ -66,6 +66,7 @@ struct BPlan {
     size_t lds;
     size_t off_tab[3], off_norm, off_obs, ws_bytes;
     int obs_tiles;
+    int64_t obs_pts;
 };
 
 size_t ltab_size(bool cplx) { return cplx ? 32 : 16; }  // (alpha, m) hi/lo pairs of float / complex<float>
@@ -131,6 +132,15 @@ bool bhint_find(const sscn_problem &pb, int32_t chunk[3])
     return false;
 }
 
+// Grid points per work item of an instance: about 1/32 of the instance per
+// pass, at least 32K and at most 256K.  Each item pays a claim, a wait and
+// a release (an L2 write-back); large instances take fewer, larger items,
+// small ones still spread over several blocks.  Depends on the shape only.
+int64_t item_points(int64_t npts)
+{
+    return std::min<int64_t>(262144, std::max<int64_t>(32768, npts / 32));
+}
+
 int batch_plan(const sscn_problem &pb, BPlan &B)
 {
     int32_t hint[3] = {0, 0, 0};
@@ -180,9 +190,9 @@ int batch_plan(const sscn_problem &pb, BPlan &B)
             X.lpb = 16 / wpl;
             X.tab_entries = (size_t)c * 64 * wpl;
             Y.lpi = X.lpb;
-            // items of about 32K points: several line groups per item
+            // several line groups per item (item_points)
             const int64_t units = cdiv(X.nlines, X.lpb);
-            Y.rep = (int)std::max<int64_t>(1, std::min<int64_t>(8, 32768 / std::max<int64_t>(1, (int64_t)X.lpb * n)));
+            Y.rep = (int)std::max<int64_t>(1, std::min<int64_t>(64, item_points(npts) / std::max<int64_t>(1, (int64_t)X.lpb * n)));
             Y.rep = (int)std::min<int64_t>(Y.rep, units);
             Y.ntiles = (int)cdiv(units, Y.rep);
             lds = std::max(lds, wpl == 1 ? (size_t)c * 64 * ltab_size(cplx) : (size_t)16 * 4 * S);
@@ -226,7 +236,7 @@ int batch_plan(const sscn_problem &pb, BPlan &B)
             Y.tpi = 16 / W;
             const int64_t lines_per_set = (int64_t)Y.tpi * (64 / L);
             const int64_t units = cdiv(X.nlines, lines_per_set);
-            Y.rep = (int)std::max<int64_t>(1, std::min<int64_t>(8, 32768 / std::max<int64_t>(1, lines_per_set * n)));
+            Y.rep = (int)std::max<int64_t>(1, std::min<int64_t>(64, item_points(npts) / std::max<int64_t>(1, lines_per_set * n)));
             Y.rep = (int)std::min<int64_t>(Y.rep, units);
             Y.ntiles = (int)cdiv(units, Y.rep);
             lds = std::max(lds, (size_t)W * L * c * ltab_size(cplx) + (size_t)Y.tpi * 2 * W * 64 * S);
@@ -254,7 +264,8 @@ int batch_plan(const sscn_problem &pb, BPlan &B)
     }
     if (lds > kBatchLds) return SSCN_E_UNSUPPORTED;
     B.lds = lds;
-    B.obs_tiles = (int)cdiv(npts, BATCH_OBS_PTS);
+    B.obs_pts = std::max<int64_t>(BATCH_OBS_PTS, item_points(npts));
+    B.obs_tiles = (int)cdiv(npts, B.obs_pts);
     size_t off = 0;
     for (int a = 0; a < pb.dim; ++a) {
         B.off_tab[a] = off;
@@ -584,6 +595,7 @@ int sscn_batch_admit(sscn_batch *b, int32_t slot, const sscn_problem *pb, void *
     I.norm_part = reinterpret_cast<double *>(ws + B.off_norm);
     I.obs_part = reinterpret_cast<double *>(ws + B.off_obs);
     I.obs_tiles = B.obs_tiles;
+    I.obs_pts = B.obs_pts;
     I.observe_every = pb->observe_every;
     I.mu_tol = mu_tol;
     I.max_steps = max_steps;
