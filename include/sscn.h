@@ -239,7 +239,8 @@ int sscn_batch_workspace_bytes(const sscn_problem *pb, size_t *bytes);
 int sscn_batch_set_tile_hint(const sscn_problem *pb, const int32_t chunk[3]);
 int sscn_batch_clear_tile_hints(void);
 
-/* Geometry of pb's instances in the persistent kernel, 8 ints per axis (x,
+/* Geometry of pb's instances in the persistent kernel at the default split,
+ * 8 ints per axis (x,
  * y, z): kind (0 ROW, 1 COL, -1 unused axis), points per thread, waves per
  * line (ROW) or per sub-tile (COL), lanes per line (COL; 1 otherwise), work
  * items per step, line groups (ROW) or sub-tile sets (COL) per item, scan
@@ -252,6 +253,17 @@ int sscn_batch_plan_info(const sscn_problem *pb, int32_t *info, int32_t cap);
  * Allocates pinned host mirrors only. */
 int sscn_batch_create(int32_t max_slots, int64_t max_items, void *d_ctl, size_t ctl_bytes, void *hip_stream,
                       sscn_batch **out);
+
+/* Work-item split of the batch: every pass of an instance is cut into items
+ * of about (points / parts) grid points (at least 32K, at most 256K).  Each
+ * item pays a claim, a dependency wait and a release, so fewer, larger
+ * items (small parts) cost less per point when many instances fill the
+ * device, and more, smaller ones (large parts) finish a few running
+ * instances sooner.  Default 32; 1 <= parts <= 4096.  Only while the batch
+ * holds no instance (SSCN_E_INVALID otherwise): an instance's geometry, and
+ * so its results, depend only on its shape and this setting.  Workspace
+ * sizes do not depend on it. */
+int sscn_batch_set_split(sscn_batch *b, int32_t parts);
 
 /* Admit an instance into an empty slot: d_psi holds its initial state (layout
  * and dtype as for sscn_create), d_ws is its workspace.  Uploads its FP64

@@ -67,6 +67,7 @@ struct BPlan {
     size_t off_tab[3], off_norm, off_obs, ws_bytes;
     int obs_tiles;
     int64_t obs_pts;
+    int64_t units[3];      // line groups (x) or sub-tile sets (y, z) per pass
 };
 
 size_t ltab_size(bool cplx) { return cplx ? 32 : 16; }  // (alpha, m) hi/lo pairs of float / complex<float>
@@ -132,16 +133,21 @@ bool bhint_find(const sscn_problem &pb, int32_t chunk[3])
     return false;
 }
 
-// Grid points per work item of an instance: about 1/32 of the instance per
-// pass, at least 32K and at most 256K.  Each item pays a claim, a wait and
-// a release (an L2 write-back); large instances take fewer, larger items,
-// small ones still spread over several blocks.  Depends on the shape only.
-int64_t item_points(int64_t npts)
+// Grid points per work item of an instance: about 1/parts of the instance
+// per pass, at least 32K and at most 256K.  Each item pays a claim, a wait
+// and a release (an L2 write-back): fewer, larger items cost less per point
+// when the batch fills the device; more, smaller ones spread a few running
+// instances over more blocks (latency).  parts is a setting of the batch
+// (sscn_batch_set_split), fixed while it holds instances, so an instance's
+// geometry depends only on its shape and that setting.
+constexpr int kDefaultSplit = 32;
+
+int64_t item_points(int64_t npts, int parts)
 {
-    return std::min<int64_t>(262144, std::max<int64_t>(32768, npts / 32));
+    return std::min<int64_t>(262144, std::max<int64_t>(32768, npts / parts));
 }
 
-int batch_plan(const sscn_problem &pb, BPlan &B)
+int batch_plan(const sscn_problem &pb, BPlan &B, int parts = kDefaultSplit)
 {
     int32_t hint[3] = {0, 0, 0};
     bhint_find(pb, hint);
@@ -192,7 +198,8 @@ int batch_plan(const sscn_problem &pb, BPlan &B)
             Y.lpi = X.lpb;
             // several line groups per item (item_points)
             const int64_t units = cdiv(X.nlines, X.lpb);
-            Y.rep = (int)std::max<int64_t>(1, std::min<int64_t>(64, item_points(npts) / std::max<int64_t>(1, (int64_t)X.lpb * n)));
+            Y.rep = (int)std::max<int64_t>(1, std::min<int64_t>(64, item_points(npts, parts) / std::max<int64_t>(1, (int64_t)X.lpb * n)));
+            B.units[a] = units;
             Y.rep = (int)std::min<int64_t>(Y.rep, units);
             Y.ntiles = (int)cdiv(units, Y.rep);
             lds = std::max(lds, wpl == 1 ? (size_t)c * 64 * ltab_size(cplx) : (size_t)16 * 4 * S);
@@ -236,7 +243,8 @@ int batch_plan(const sscn_problem &pb, BPlan &B)
             Y.tpi = 16 / W;
             const int64_t lines_per_set = (int64_t)Y.tpi * (64 / L);
             const int64_t units = cdiv(X.nlines, lines_per_set);
-            Y.rep = (int)std::max<int64_t>(1, std::min<int64_t>(64, item_points(npts) / std::max<int64_t>(1, lines_per_set * n)));
+            Y.rep = (int)std::max<int64_t>(1, std::min<int64_t>(64, item_points(npts, parts) / std::max<int64_t>(1, lines_per_set * n)));
+            B.units[a] = units;
             Y.rep = (int)std::min<int64_t>(Y.rep, units);
             Y.ntiles = (int)cdiv(units, Y.rep);
             lds = std::max(lds, (size_t)W * L * c * ltab_size(cplx) + (size_t)Y.tpi * 2 * W * 64 * S);
@@ -264,17 +272,20 @@ int batch_plan(const sscn_problem &pb, BPlan &B)
     }
     if (lds > kBatchLds) return SSCN_E_UNSUPPORTED;
     B.lds = lds;
-    B.obs_pts = std::max<int64_t>(BATCH_OBS_PTS, item_points(npts));
+    B.obs_pts = std::max<int64_t>(BATCH_OBS_PTS, item_points(npts, parts));
     B.obs_tiles = (int)cdiv(npts, B.obs_pts);
+    // the partials are sized for the finest split (one line group or set
+    // per item, BATCH_OBS_PTS per observation tile), so the workspace of a
+    // shape does not depend on the batch's setting
     size_t off = 0;
     for (int a = 0; a < pb.dim; ++a) {
         B.off_tab[a] = off;
         off = a256(off + B.ax[a].tab_entries * sizeof(TabEntry));
     }
     B.off_norm = off;
-    off = a256(off + sizeof(double) * (size_t)B.bax[pb.dim - 1].ntiles);
+    off = a256(off + sizeof(double) * (size_t)B.units[pb.dim - 1]);
     B.off_obs = off;
-    off = a256(off + sizeof(double) * BATCH_NOBS * (size_t)B.obs_tiles);
+    off = a256(off + sizeof(double) * BATCH_NOBS * (size_t)cdiv(npts, BATCH_OBS_PTS));
     B.ws_bytes = off;
     return SSCN_OK;
 }
@@ -293,6 +304,7 @@ int batch_validate(const sscn_problem *pb)
 
 struct sscn_batch {
     int max_slots;
+    int parts;                      // item split (item_points), fixed while instances are admitted
     int64_t max_items;
     char *ctl;
     CtlLayout lay;
@@ -497,6 +509,7 @@ int sscn_batch_create(int32_t max_slots, int64_t max_items, void *d_ctl, size_t 
     sscn_batch *b = new (std::nothrow) sscn_batch;
     if (!b) return SSCN_E_INVALID;
     b->max_slots = max_slots;
+    b->parts = kDefaultSplit;
     b->max_items = max_items;
     b->ctl = static_cast<char *>(d_ctl);
     b->lay = ctl_layout(max_slots, max_items);
@@ -557,6 +570,15 @@ int sscn_batch_create(int32_t max_slots, int64_t max_items, void *d_ctl, size_t 
     return SSCN_OK;
 }
 
+int sscn_batch_set_split(sscn_batch *b, int32_t parts)
+{
+    if (!b || parts < 1 || parts > 4096) return SSCN_E_INVALID;
+    for (int i = 0; i < b->max_slots; ++i)
+        if (b->used[i]) return SSCN_E_INVALID;
+    b->parts = parts;
+    return SSCN_OK;
+}
+
 int sscn_batch_admit(sscn_batch *b, int32_t slot, const sscn_problem *pb, void *d_psi, void *d_ws, double mu_tol,
                      int64_t max_steps)
 {
@@ -568,7 +590,7 @@ int sscn_batch_admit(sscn_batch *b, int32_t slot, const sscn_problem *pb, void *
         return SSCN_E_INVALID;
     if (!(mu_tol >= 0.0) || !std::isfinite(mu_tol) || max_steps < 1) return SSCN_E_INVALID;
     BPlan B;
-    v = batch_plan(*pb, B);
+    v = batch_plan(*pb, B, b->parts);
     if (v != SSCN_OK) return v;
 
     BInst I;

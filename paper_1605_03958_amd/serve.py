@@ -86,14 +86,20 @@ def footprint(prob: Problem) -> int:
     return state_bytes(prob) + batch_workspace_bytes(prob)
 
 
+# Work-item split of the serving batch: a serving batch usually holds a few
+# tens of requests, so each instance is cut finer than in a batch that fills
+# the device, which finishes the running requests sooner (sscn_batch_set_split).
+SERVE_SPLIT = 64
+
+
 class BatchExecutor:
     """The device side of the server: one ``sscn.Batch`` on its own stream."""
 
-    def __init__(self, max_slots: int, max_items: int = 1 << 20, device: str = "cuda"):
+    def __init__(self, max_slots: int, max_items: int = 1 << 20, device: str = "cuda", split: int = SERVE_SPLIT):
         import torch
         from .sscn import Batch
         self.stream = torch.cuda.Stream(device=device)
-        self.batch = Batch(max_slots, max_items=max_items, device=device, stream=self.stream)
+        self.batch = Batch(max_slots, max_items=max_items, device=device, stream=self.stream, split=split)
 
     def footprint(self, prob: Problem) -> int:
         return footprint(prob)

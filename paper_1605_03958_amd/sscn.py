@@ -101,6 +101,7 @@ EXPORTS = {
     "sscn_batch_clear_tile_hints": ([], ctypes.c_int),
     "sscn_batch_plan_info": ([ctypes.POINTER(CProblem), ctypes.POINTER(ctypes.c_int32), ctypes.c_int32],
                              ctypes.c_int),
+    "sscn_batch_set_split": ([ctypes.c_void_p, ctypes.c_int32], ctypes.c_int),
     "sscn_batch_create": ([ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
                            ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
     "sscn_batch_admit": ([ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(CProblem), ctypes.c_void_p,
@@ -419,7 +420,10 @@ class Batch:
     Owns (as torch tensors) the control block and, per admitted slot, the
     instance state and workspace."""
 
-    def __init__(self, max_slots: int, max_items: int = 1 << 20, device: str = "cuda", stream=None):
+    def __init__(self, max_slots: int, max_items: int = 1 << 20, device: str = "cuda", stream=None,
+                 split: int = 0):
+        """split > 0: the work-item split (sscn_batch_set_split); 0 keeps
+        the library's default."""
         import torch
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
@@ -435,6 +439,8 @@ class Batch:
                                        ctypes.c_size_t(nb), ctypes.c_void_p(self.stream.cuda_stream),
                                        ctypes.byref(h)), "sscn_batch_create")
         self._h = h
+        if split:
+            _check(lib().sscn_batch_set_split(self._h, int(split)), "sscn_batch_set_split")
 
     def footprint(self, prob: Problem) -> int:
         """HBM bytes a slot of this problem keeps resident (state + workspace)."""

@@ -227,3 +227,36 @@ def test_solo_instance_steps_and_mix_independence():
     assert np.array_equal(alone, mix)
     ref = oracle.run(oprob(one[0]), one[1], 300).psi
     assert rel_l2(mix, ref) <= 5e-5
+
+
+def test_item_split_setting():
+    """The work-item split is a batch setting: refused once instances are
+    admitted; at any split results match the oracle, and within one split an
+    instance is bitwise the same alone and in a mix."""
+    big = make(3, (60, 64, 56), IMAG, seed=70)
+    other = [make(d, n, m, seed=71 + i) for i, (d, n, m) in enumerate(MIX[8:13])]
+    b = sscn.Batch(2, split=8)
+    b.admit(0, big[0], big[1], mu_tol=0.0, max_steps=20)
+    with pytest.raises(sscn.SSCNError) as e:
+        lib_rc = sscn.lib().sscn_batch_set_split(b._h, 64)
+        sscn._check(lib_rc, "sscn_batch_set_split")
+    assert e.value.code == sscn.E_INVALID
+    b.close()
+    ref = oracle.run(oprob(big[0]), big[1], 20).psi
+    for split in (1, 8, 64, 4096):
+        def run(cases, slots):
+            bb = sscn.Batch(max(slots) + 1, split=split)
+            for s_, (p, psi0) in zip(slots, cases):
+                bb.admit(s_, p, psi0, mu_tol=0.0, max_steps=20)
+            bb.step(20)
+            bb.poll(wait=True)
+            assert not bb.error()
+            out = [bb.evict(s_).cpu().numpy() for s_ in slots]
+            bb.close()
+            return out
+        alone = run([big], [3])[0]
+        mix = run(other[:2] + [big] + other[2:], list(range(6)))[2]
+        assert np.array_equal(alone, mix), split
+        err = rel_l2(alone, ref)
+        print(f"split {split}: rel L2 vs oracle {err:.2e}", flush=True)
+        assert err <= 5e-5
