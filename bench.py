@@ -121,6 +121,27 @@ def cpu_baseline(target_s: float = 12.0):
                       f"timed after one untimed step), FP64 C oracle with OpenMP over lines"}
 
 
+def c0_timing(steps: int = 500):
+    """The 64^3 FP64 imaginary-time ground-state workload (dx = 0.2,
+    dt = 0.1 dx^2, g = 22, renormalised every step): launch-bound, so it
+    shows the per-step overhead (graph replay of runs of steps)."""
+    import torch
+    from paper_1605_03958_amd import inputs, sscn
+    dx = 0.2
+    p = sscn.Problem(3, (64, 64, 64), (dx,) * 3, (1.0, 1.5, 2.0), 22.0, 0.1 * dx * dx, sscn.IMAG, sscn.F64, 1)
+    s = sscn.Solver(p, inputs.ho_gaussian(3, p.n, p.dx, p.omega, noise=1e-3, seed=0))
+    s.step(64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    mu = s.observe().mu
+    s.close()
+    return {"workload": "64^3 FP64 imaginary time, dx=0.2, dt=0.1*dx^2, g=22", "steps": steps,
+            "ms_per_step": 1e3 * el / steps, "ptsteps_per_s": p.points * steps / el, "mu": mu}
+
+
 def c3_problems():
     """The 64-instance uneven batch: 22 1D, 21 2D, 21 3D draws (seeds 100+i),
     imaginary time in FP32 with FP64 reductions, dt = 0.1 dx^2."""
@@ -324,6 +345,8 @@ def main():
                        "speedup_vs_fp64": f["pts"] / m["pts"], "kernel_ms": {k: round(v, 5) for k, v in f["kernels"].items()},
                        "state": "complex64"}
     res["copy_gbs"] = copy_bandwidth(m["S"] * m["points"])
+    if args.only is None:
+        res["c0"] = c0_timing()
     if args.only is None and not args.no_batch:
         res["batch"] = batch_c3()
     if args.only is None and not args.no_serve:

@@ -127,7 +127,11 @@ int sscn_create(const sscn_problem *pb, void *d_psi, void *d_ws, void *hip_strea
 
 /* Enqueue nsteps >= 0 SSCN steps on the stream and return.  When the stream
  * reaches the end of the call the state is complete: in imaginary time it is
- * renormalised if the last step was a renormalisation step. */
+ * renormalised if the last step was a renormalisation step.  On a stream
+ * other than the legacy default stream, runs of 32 steps are replayed from
+ * hipGraphs captured on first use (one per renormalisation phase; dropped
+ * by sscn_set_g and sscn_destroy); the kernels and results are those of
+ * direct launches. */
 int sscn_step(sscn_solver *s, int64_t nsteps);
 
 /* Observables of the current state; waits for the stream.  Returns

@@ -10,6 +10,7 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <new>
 #include <vector>
@@ -295,7 +296,17 @@ struct sscn_solver {
     int64_t step;
     double g;
     double host_obs[16];
+    // captured runs of kGraphSteps steps, keyed by the renormalisation phase
+    // (step mod renorm_every) they start at; their kernel arguments hold g
+    std::map<int64_t, hipGraphExec_t> graphs;
+    bool graphs_off;          // capture failed once on this stream: launch directly
 };
+
+static void drop_graphs(sscn_solver *s)
+{
+    for (auto &kv : s->graphs) (void)hipGraphExecDestroy(kv.second);
+    s->graphs.clear();
+}
 
 static double *scal_ptr(sscn_solver *s) { return reinterpret_cast<double *>(s->ws + s->P.off_scal); }
 
@@ -439,11 +450,58 @@ static hipError_t enqueue_step(sscn_solver *s, bool do_renorm, Timer *tm)
     return hipSuccess;
 }
 
+// Steps per captured graph.  Small problems are bound by launch overhead
+// (four kernels of a few microseconds per step); a graph replay issues a
+// run of steps with one call.  The replayed kernels and arguments are those
+// the direct path would launch, so results are the same.
+constexpr int64_t kGraphSteps = 32;
+
+static hipError_t capture_run(sscn_solver *s, hipGraphExec_t *out)
+{
+    const bool imag = s->pb.mode == SSCN_IMAG;
+    hipError_t e = hipStreamBeginCapture(s->st, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipError_t le = hipSuccess;
+    for (int64_t k = 1; k <= kGraphSteps && le == hipSuccess; ++k) {
+        const int64_t step = s->step + k;
+        le = enqueue_step(s, imag && (step % s->pb.renorm_every == 0), nullptr);
+    }
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(s->st, &g);
+    if (le != hipSuccess || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return le != hipSuccess ? le : e;
+    }
+    e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    return e;
+}
+
 static hipError_t enqueue_steps(sscn_solver *s, int64_t nsteps, Timer *tm)
 {
     if (nsteps <= 0) return hipSuccess;
     const bool imag = s->pb.mode == SSCN_IMAG;
     bool last_renorm = false;
+    // whole runs of kGraphSteps from captured graphs (not on the legacy
+    // default stream, which cannot be captured, and not when timing)
+    while (!tm && s->st != nullptr && !s->graphs_off && nsteps >= kGraphSteps) {
+        const int64_t phase = imag ? s->step % s->pb.renorm_every : 0;
+        auto it = s->graphs.find(phase);
+        if (it == s->graphs.end()) {
+            hipGraphExec_t ex = nullptr;
+            if (capture_run(s, &ex) != hipSuccess) {
+                (void)hipGetLastError();
+                s->graphs_off = true;
+                break;
+            }
+            it = s->graphs.emplace(phase, ex).first;
+        }
+        hipError_t e = hipGraphLaunch(it->second, s->st);
+        if (e != hipSuccess) return e;
+        s->step += kGraphSteps;
+        nsteps -= kGraphSteps;
+        last_renorm = imag && (s->step % s->pb.renorm_every == 0);
+    }
     for (int64_t t = 0; t < nsteps; ++t) {
         const int64_t step = s->step + 1;
         const bool do_renorm = imag && (step % s->pb.renorm_every == 0);
@@ -588,9 +646,8 @@ int sscn_create(const sscn_problem *pb, void *d_psi, void *d_ws, void *hip_strea
     if (!d_psi || !d_ws || !out) return SSCN_E_INVALID;
     if (reinterpret_cast<uintptr_t>(d_ws) % 256 != 0) return SSCN_E_INVALID;
     if (reinterpret_cast<uintptr_t>(d_psi) % 16 != 0) return SSCN_E_INVALID;
-    sscn_solver *s = new (std::nothrow) sscn_solver;
+    sscn_solver *s = new (std::nothrow) sscn_solver();   // value-initialised: members zero, map empty
     if (!s) return SSCN_E_INVALID;
-    std::memset(s, 0, sizeof(*s));
     s->pb = *pb;
     s->psi = d_psi;
     s->ws = static_cast<char *>(d_ws);
@@ -753,6 +810,7 @@ int sscn_set_g(sscn_solver *s, double g)
 {
     if (!s || !std::isfinite(g)) return SSCN_E_INVALID;
     s->g = g;
+    drop_graphs(s);           // captured arguments hold the old g
     return SSCN_OK;
 }
 
@@ -760,6 +818,7 @@ int sscn_destroy(sscn_solver *s)
 {
     if (!s) return SSCN_E_INVALID;
     (void)hipStreamSynchronize(s->st);
+    drop_graphs(s);
     delete s;
     return SSCN_OK;
 }

@@ -270,7 +270,11 @@ class Obs:
 
 
 class Solver:
-    """One SSCN problem bound to torch-owned device memory on a stream."""
+    """One SSCN problem bound to torch-owned device memory on a stream.
+
+    Without a stream argument the solver gets a stream of its own (not the
+    legacy default stream, so the library can replay its steps from captured
+    graphs); state(), observe() and the densities wait for it."""
 
     def __init__(self, prob: Problem, psi0=None, device: str = "cuda", stream=None):
         import torch
@@ -281,7 +285,7 @@ class Solver:
         self._pc = prob.c()
         _check(L.sscn_validate(ctypes.byref(self._pc)), "sscn_validate")
         self.device = torch.device(device)
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
         self.psi = torch.zeros(prob.shape, dtype=prob.torch_dtype(), device=self.device)
         wsb = workspace_bytes(prob)
         self.ws = torch.zeros(wsb // 8 + 32, dtype=torch.float64, device=self.device)

@@ -295,3 +295,33 @@ def test_c2_fp32_error_against_stored_oracle():
     assert err <= 1e-3
     assert dE <= 1e-5
     assert dN <= 1e-5
+
+
+def test_graph_replay_equals_direct_launches():
+    """Runs of steps replayed from captured graphs give bitwise the state
+    of direct launches: imaginary time with renormalisation every 3 steps
+    (runs start at every phase), real time with a quench between runs, and a
+    solver on the legacy default stream (always direct)."""
+    import torch
+    for mode, every in ((IMAG, 3), (REAL, 0)):
+        p = Problem(3, (20, 24, 18), (0.2, 0.2, 0.2), (1.0, 1.5, 2.0), 8.0, 0.004 if mode == IMAG else 0.0008,
+                    mode, F64, every)
+        if mode == IMAG:
+            psi0 = inputs.ho_gaussian(3, p.n, p.dx, p.omega, noise=1e-3, seed=5)
+        else:
+            psi0 = inputs.thomas_fermi(3, p.n, p.dx, p.omega, 10.0, phase_sigma=0.05, seed=5)
+        plan = [(70, None), (101, 6.0), (33, None)]      # 70 = 2 runs + 6; quench; ...
+        outs = []
+        for how in ("graph", "direct", "default"):
+            s = sscn.Solver(p, psi0, stream=torch.cuda.default_stream() if how == "default" else None)
+            for n, g in plan:
+                if g is not None:
+                    s.set_g(g)
+                if how == "direct":
+                    for _ in range(n):
+                        s.step(1)
+                else:
+                    s.step(n)
+            outs.append(s.state())
+            s.close()
+        assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2]), mode
