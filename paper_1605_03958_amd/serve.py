@@ -255,22 +255,21 @@ class Server:
                 for e in todo:
                     self._admit(e)
                 if not self._running:
-                    # the head does not fit yet although nothing runs: it
-                    # can only be a failed admission; wait for more work
-                    if self._pending and not todo:
-                        with self._cv:
-                            self._cv.wait(0.001)
+                    # every admission of this round failed (their futures
+                    # hold the errors): look at the queue again
                     continue
                 self.ex.step(self.tick)
                 st = self.ex.poll()
                 self.ticks += 1
-                if self.error_every and self.ticks % self.error_every == 0 and self.ex.error():
-                    raise ServerError("a bounded wait of the persistent step gave up; results of the batch are void")
                 now = self.clock()
-                for slot, e in list(self._running.items()):
-                    s = st[slot]
-                    if s.state != SLOT_RUNNING:
-                        self._retire(e, s, now)
+                done = [(slot, e) for slot, e in self._running.items() if st[slot].state != SLOT_RUNNING]
+                # the launch error flag (a bounded wait that gave up voids the
+                # batch's results) is checked before anything is handed out,
+                # and every error_every ticks otherwise
+                if (done or (self.error_every and self.ticks % self.error_every == 0)) and self.ex.error():
+                    raise ServerError("a bounded wait of the persistent step gave up; results of the batch are void")
+                for slot, e in done:
+                    self._retire(e, st[slot], now)
         except Exception as exc:
             self._fail_running(exc)
             with self._cv:

@@ -244,3 +244,22 @@ def test_latency_stats():
     assert s["p99_s"] == pytest.approx(np.percentile(lat, 99))
     assert s["req_per_s"] == pytest.approx(10.0) and s["ptsteps_per_s"] == pytest.approx(100 * 10 * 100 / 10.0)
     assert s["wait_p50_s"] == pytest.approx(0.5)
+
+
+def test_voided_launch_results_are_not_handed_out():
+    """When the batch reports that a bounded wait gave up, the server hands
+    out no result: running and queued requests fail with the error."""
+    class Broken(FakeExecutor):
+        def error(self):
+            return any(s["steps"] >= 10 for s in self.slots.values())
+
+    ex = Broken(1)
+    srv = serve.Server(budget_bytes=1 << 30, max_slots=1, tick_steps=10, executor=ex)
+    futs = [srv.submit(job(0, 100, 10)), srv.submit(job(1, 100, 10))]
+    srv.close()
+    with pytest.raises(serve.ServerError):
+        srv.run()
+    for f in futs:
+        with pytest.raises(serve.ServerError):
+            f.result(timeout=1)
+    assert not srv.results
