@@ -115,8 +115,14 @@ def cpu_baseline(target_s: float = 12.0):
         steps += chunk
         step += chunk
         chunk = max(1, min(50, int(0.25 * target_s * chunk / max(dt, 1e-3))))
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": p.points * steps / el, "unit": "grid-point-steps/s", "cores": oracle.threads(),
-            "kind": "oracle",
+            "kind": "oracle", "cpu": model,
             "sample": f"256^3 complex128 real-time workload, steps 2-{step - 1} ({steps} steps, {el:.1f} s "
                       f"timed after one untimed step), FP64 C oracle with OpenMP over lines"}
 
@@ -345,6 +351,7 @@ def main():
                        "speedup_vs_fp64": f["pts"] / m["pts"], "kernel_ms": {k: round(v, 5) for k, v in f["kernels"].items()},
                        "state": "complex64"}
     res["copy_gbs"] = copy_bandwidth(m["S"] * m["points"])
+    res["roofline"]["frac_of_copy"] = achieved / res["copy_gbs"]
     if args.only is None:
         res["c0"] = c0_timing()
     if args.only is None and not args.no_batch:
