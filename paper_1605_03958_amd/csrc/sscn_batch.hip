@@ -181,27 +181,51 @@ __device__ __forceinline__ void batch_obs(const BInst &I, const BState &S, int t
     double acc[BATCH_NOBS];
 #pragma unroll
     for (int q = 0; q < BATCH_NOBS; ++q) acc[q] = 0.0;
+    double inv2[3];                       // 1 / dx_a^2
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) inv2[ax] = ax < dim ? 1.0 / (pp.dx[ax] * pp.dx[ax]) : 0.0;
+    // grid indices of a point: two divisions, in 32 bits when the point
+    // count allows (64-bit divisions are long instruction sequences)
+    const bool narrow = npts < (1LL << 31);
     const long long p0 = (long long)tile * I.obs_pts;
     const long long p1 = min(npts, p0 + (long long)I.obs_pts);
     for (long long p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
-        const int idx[3] = {(int)(p % nx), (int)((p / nx) % ny), (int)(p / (nx * ny))};
+        int idx[3];
+        if (dim == 1) {
+            idx[0] = (int)p;
+            idx[1] = idx[2] = 0;
+        } else if (narrow) {
+            const unsigned up = (unsigned)p, r = up / (unsigned)nx, r2 = r / (unsigned)ny;
+            idx[0] = (int)(up - r * (unsigned)nx);
+            idx[1] = (int)(r - r2 * (unsigned)ny);
+            idx[2] = (int)r2;
+        } else {
+            const long long r = p / nx, r2 = r / ny;
+            idx[0] = (int)(p - r * nx);
+            idx[1] = (int)(r - r2 * ny);
+            idx[2] = (int)r2;
+        }
         const V v = ld_elem(psi, p);
         const double q = A::norm2(v);
         double vp = 0.0, kin = 0.0;
-        for (int ax = 0; ax < dim; ++ax) {
+        // unrolled over the three axes so that every index is static (the
+        // arrays stay in registers); explicit FMAs fix the rounding
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            if (ax >= dim) break;
             const double x = (double(idx[ax]) - pp.cen[ax]) * pp.dx[ax];
-            vp += pp.w2h[ax] * x * x;
-            acc[4 + ax] += x * q;
-            acc[7 + ax] += x * x * q;
+            vp = fmaT(pp.w2h[ax] * x, x, vp);
+            acc[4 + ax] = fmaT(x, q, acc[4 + ax]);
+            acc[7 + ax] = fmaT(x * x, q, acc[7 + ax]);
             const V nb = (idx[ax] + 1 < n3[ax]) ? ld_elem(psi, p + sx[ax]) : A::zero();
             double e = A::norm2(A::sub(nb, v));
             if (idx[ax] == 0) e += q;
-            kin += e / (pp.dx[ax] * pp.dx[ax]);
+            kin = fmaT(e, inv2[ax], kin);
         }
         acc[0] += q;
         acc[1] += kin;
-        acc[2] += vp * q;
-        acc[3] += q * q;
+        acc[2] = fmaT(vp, q, acc[2]);
+        acc[3] = fmaT(q, q, acc[3]);
     }
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
@@ -216,6 +240,52 @@ __device__ __forceinline__ void batch_obs(const BInst &I, const BState &S, int t
         for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += redq[q][w];
         obs_part[(size_t)tile * BATCH_NOBS + q] = s;
     }
+}
+
+// The finalisation arithmetic of one step, given the step's raw norm sum
+// and, on observation steps, the observation sums (thread 0 only).  S may be
+// the instance state in memory or a copy of it in LDS.
+__device__ __forceinline__ void fin_core(const BInst &I, BState &S, double nraw, const double *tot, bool obs_now)
+{
+    const double dv = I.dvol;
+    const double N = dv * nraw;
+    const double s = I.imag ? 1.0 / sqrt(N) : 1.0;   // renormalisation every step in imaginary time
+    int32_t status = S.status;
+    if (!__builtin_isfinite(N) || !(N > 0.0)) status = BS_NONFINITE;
+    if (obs_now && status == BS_RUNNING) {
+        // observables of the step's state, renormalised in imaginary time:
+        // K and P scale with s^2, I with s^4, the norm with s^2
+        const double s2 = s * s;
+        const double Nq = dv * tot[0] * s2;
+        const double K = 0.5 * dv * tot[1] * s2;
+        const double P = dv * tot[2] * s2;
+        const double In = dv * tot[3] * s2 * s2;
+        const double g = I.pp.g;
+        const double mu = fmaT(g, In, K + P) / Nq;
+        S.obs[0] = Nq;
+        S.obs[1] = mu;
+        S.obs[2] = fmaT(0.5 * g, In, K + P) / Nq;
+        S.obs[3] = K;
+        S.obs[4] = P;
+        S.obs[5] = In;
+        for (int ax = 0; ax < 3; ++ax) {
+            S.obs[6 + ax] = dv * tot[4 + ax] * s2 / Nq;
+            S.obs[9 + ax] = dv * tot[7 + ax] * s2 / Nq;
+        }
+        S.obs_step = S.step + 1;
+        if (!__builtin_isfinite(mu)) {
+            status = BS_NONFINITE;
+        } else if (I.mu_tol > 0.0 && ((S.step + 1) % I.observe_every) == 0) {
+            if (S.have_prev && fabs(mu - S.mu_prev) < I.mu_tol) status = BS_CONVERGED;
+            S.mu_prev = mu;
+            S.have_prev = 1;
+        }
+    }
+    S.norm = N;
+    S.scale = s;
+    S.step += 1;
+    if (status == BS_RUNNING && S.step >= I.max_steps) status = BS_DONE;
+    S.status = status;
 }
 
 // Finalisation of one instance's step (one block).
@@ -250,46 +320,139 @@ __device__ __forceinline__ void batch_fin(const BInst &I, BState &S, double *red
             }
         }
     }
-    if (threadIdx.x != 0) return;
-    const double dv = I.dvol;
-    const double N = dv * nraw;
-    const double s = I.imag ? 1.0 / sqrt(N) : 1.0;   // renormalisation every step in imaginary time
-    int32_t status = S.status;
-    if (!__builtin_isfinite(N) || !(N > 0.0)) status = BS_NONFINITE;
-    if (obs_now && status == BS_RUNNING) {
-        // observables of the step's state, renormalised in imaginary time:
-        // K and P scale with s^2, I with s^4, the norm with s^2
-        const double s2 = s * s;
-        const double Nq = dv * tot[0] * s2;
-        const double K = 0.5 * dv * tot[1] * s2;
-        const double P = dv * tot[2] * s2;
-        const double In = dv * tot[3] * s2 * s2;
-        const double g = I.pp.g;
-        const double mu = (K + P + g * In) / Nq;
-        S.obs[0] = Nq;
-        S.obs[1] = mu;
-        S.obs[2] = (K + P + 0.5 * g * In) / Nq;
-        S.obs[3] = K;
-        S.obs[4] = P;
-        S.obs[5] = In;
-        for (int ax = 0; ax < 3; ++ax) {
-            S.obs[6 + ax] = dv * tot[4 + ax] * s2 / Nq;
-            S.obs[9 + ax] = dv * tot[7 + ax] * s2 / Nq;
+    if (threadIdx.x == 0) fin_core(I, S, nraw, tot, obs_now);
+}
+
+// ---------------------------------------------------------------------------
+// solo instances: whole steps of one 1D line inside one block
+// ---------------------------------------------------------------------------
+// A solo instance's steps with its line in registers for the whole call:
+// the state is read once and written once (and on observation steps), the
+// table head is staged in LDS (the tail is one constant entry), the norm
+// and the finalisation pass through LDS between block barriers, and thread 0
+// keeps the instance state in LDS (sS), writing it back at the end.  Each
+// step is the split items' line solve, observation sums and finalisation,
+// so the results are theirs bit for bit.  Runs `steps` steps, fewer if the
+// instance stops.
+template <class T, bool CPLX, int C, bool MW>
+__device__ void solo_run(const BInst &I, BState &S, BState &sS, int steps,
+                         unsigned char *lds, double *red, double (*redq)[16], int *s_go)
+{
+    using A = Alg<T, CPLX>;
+    using V = typename A::V;
+    const BAxis X = I.ax[0];
+    const PointParams pp = I.pp;
+    const GP<const TabEntry> tab = (GP<const TabEntry>)X.lt.tab;
+    const GP<V> psi = (GP<V>)I.psi;
+    const int G = MW ? 64 * X.wpl : 64;
+    const int tid = threadIdx.x;
+    const int lb = tid / G;
+    const int t = tid - lb * G;
+    const int lane = tid & 63;
+    const int wl = t >> 6;
+    const bool active = lb == 0;          // the line is line 0 of group 0
+    const int n = X.lt.n;
+    const int H = min(X.lt.i_conv, n);
+    LTab<T, CPLX> *head = reinterpret_cast<LTab<T, CPLX> *>(lds);
+    V *xs = reinterpret_cast<V *>(head + H) + lb * X.wpl * 4;
+    // the table is lane-major: point i = t*C + k sits at slot k*G + t
+    for (int i = tid; i < H; i += blockDim.x) head[i] = LTab<T, CPLX>::make(ld_tab(tab, (i % C) * G + i / C));
+    HeadTab<T, CPLX> ht;
+    ht.head = head + t * C;
+    ht.hk = active ? H - t * C : 0;
+    ht.zk = active ? n - t * C : 0;
+    ht.tail = LTab<T, CPLX>::make(TabEntry{X.lt.ac_re, X.lt.ac_im, X.lt.mc_re, X.lt.mc_im});
+    const V sig = A::coef(X.sig_re, X.sig_im);
+    const GP<const double> obs_part = (GP<const double>)I.obs_part;
+    auto store_line = [&](const V (&v)[C]) {
+#pragma unroll
+        for (int k = 0; k < C; ++k) {
+            const int i = t * C + k;
+            if (active && i < n) st_elem(psi, (long long)i, v[k]);
         }
-        S.obs_step = S.step + 1;
-        if (!__builtin_isfinite(mu)) {
-            status = BS_NONFINITE;
-        } else if (I.mu_tol > 0.0 && ((S.step + 1) % I.observe_every) == 0) {
-            if (S.have_prev && fabs(mu - S.mu_prev) < I.mu_tol) status = BS_CONVERGED;
-            S.mu_prev = mu;
-            S.have_prev = 1;
+    };
+    V u[C];
+    row_load<T, CPLX, C>(psi, 0, active, n, t, u);
+    if (tid == 0) sS = S;
+    __syncthreads();
+    for (int k = 1;; ++k) {
+        const T scale = CPLX ? T(1) : T(sS.scale);
+        const bool obs_now = batch_observes(I, sS);
+        const double nacc = row_solve<T, CPLX, C, MW>(psi, 0, active, n, &ht, G, t, lane, wl, X.wpl, xs, sig, scale,
+                                                      T(pp.dt), T(pp.g), pp, X.lt.depth, true, u, true);
+        const double nraw = block_sum(nacc, red);
+        if (obs_now) {
+            // the observation item's own sums over the stored line, so the
+            // observables are those of the split items bit for bit
+            store_line(u);
+            __syncthreads();
+            batch_obs<T, CPLX>(I, sS, 0, redq);
+            __syncthreads();
+        }
+        if (tid == 0) {
+            double tot[BATCH_NOBS];
+            for (int q = 0; q < BATCH_NOBS; ++q) tot[q] = obs_now ? obs_part[q] : 0.0;
+            fin_core(I, sS, nraw, tot, obs_now);
+            *s_go = sS.status == BS_RUNNING && k < steps;
+        }
+        __syncthreads();
+        if (!*s_go) break;
+    }
+    store_line(u);
+    if (tid == 0) S = sS;
+}
+
+// The register-resident solo steps of an instance; false (nothing done) if
+// its geometry has none.
+template <bool BIG>
+__device__ __forceinline__ bool solo_fast(const BInst &I, BState &S, BState &sS, int steps,
+                                         unsigned char *lds, double *red, double (*redq)[16], int *s_go)
+{
+    const BAxis &X = I.ax[0];
+    if (min(X.lt.i_conv, X.lt.n) > BATCH_SOLO_HEAD) return false;
+#define SOLO(CPLX, C, MW) solo_run<float, CPLX, C, MW>(I, S, sS, steps, lds, red, redq, s_go)
+    if (I.elem == 1) {
+        if (X.wpl > 1) {
+            switch (X.C) {
+            case 8: SOLO(false, 8, true); return true;
+            case 16:
+                if constexpr (BIG) { SOLO(false, 16, true); return true; }
+                return false;
+            default: return false;
+            }
+        }
+        switch (X.C) {
+        case 1: SOLO(false, 1, false); return true;
+        case 2: SOLO(false, 2, false); return true;
+        case 3: SOLO(false, 3, false); return true;
+        case 4: SOLO(false, 4, false); return true;
+        case 6: SOLO(false, 6, false); return true;
+        case 8: SOLO(false, 8, false); return true;
+        case 12: SOLO(false, 12, false); return true;
+        case 16: SOLO(false, 16, false); return true;
+        default: return false;
         }
     }
-    S.norm = N;
-    S.scale = s;
-    S.step += 1;
-    if (status == BS_RUNNING && S.step >= I.max_steps) status = BS_DONE;
-    S.status = status;
+    if (X.wpl > 1) {
+        // complex lines of 16 points per thread need more registers than a
+        // 1024-thread block has (they spill): those run the persistent
+        // kernel's solo cycle
+        if (X.C == 8) {
+            SOLO(true, 8, true);
+            return true;
+        }
+        return false;
+    }
+    switch (X.C) {
+    case 1: SOLO(true, 1, false); return true;
+    case 2: SOLO(true, 2, false); return true;
+    case 3: SOLO(true, 3, false); return true;
+    case 4: SOLO(true, 4, false); return true;
+    case 6: SOLO(true, 6, false); return true;
+    case 8: SOLO(true, 8, false); return true;
+    default: return false;
+    }
+#undef SOLO
 }
 
 // ---------------------------------------------------------------------------
@@ -468,6 +631,26 @@ __global__ void __launch_bounds__(BATCH_BLOCK) k_batch_step(BatchArgs a)
     }
 }
 
+// Launches while every instance of the batch is solo: block b runs the solo
+// instance of work item b (the work list then holds only solo items) for up
+// to BATCH_SOLO_ONLY steps with its line in registers.  The blocks share
+// nothing, so no counter is touched.
+template <bool BIG>
+__global__ void __launch_bounds__(BATCH_BLOCK) k_batch_solo(BatchArgs a)
+{
+    extern __shared__ unsigned char lds_raw[];
+    __shared__ double red[16];
+    __shared__ double redq[BATCH_NOBS][16];
+    __shared__ int s_go;
+    __shared__ BState sS;
+    const BItem w = a.items[blockIdx.x];
+    const BInst &I = a.inst[w.slot];
+    BState &S = a.state[w.slot];
+    if (w.pass != BP_SOLO || S.status != BS_RUNNING) return;
+    if (!solo_fast<BIG>(I, S, sS, BATCH_SOLO_ONLY, lds_raw, red, redq, &s_go) && threadIdx.x == 0)
+        atomicOr(&a.ctl->error, 2);
+}
+
 // Apply the pending renormalisation factor of a finished instance and clear it.
 template <class T, bool CPLX>
 __global__ void __launch_bounds__(256) k_batch_scale(void *psi_, long long npts, const double *scale)
@@ -490,6 +673,13 @@ hipError_t launch_batch_step(const BatchArgs &a, bool big, int grid, size_t lds,
 {
     if (big) hipLaunchKernelGGL(k_batch_step<true>, dim3(grid), dim3(BATCH_BLOCK), lds, st, a);
     else hipLaunchKernelGGL(k_batch_step<false>, dim3(grid), dim3(BATCH_BLOCK), lds, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_solo(const BatchArgs &a, bool big, int grid, size_t lds, hipStream_t st)
+{
+    if (big) hipLaunchKernelGGL(k_batch_solo<true>, dim3(grid), dim3(BATCH_BLOCK), lds, st, a);
+    else hipLaunchKernelGGL(k_batch_solo<false>, dim3(grid), dim3(BATCH_BLOCK), lds, st, a);
     return hipGetLastError();
 }
 

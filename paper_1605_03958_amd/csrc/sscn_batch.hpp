@@ -16,8 +16,12 @@
 // its whole step (line solve, observation sums, finalisation) inside one
 // block, with block barriers in place of the counters, and repeats steps
 // while other items of the launch are still unclaimed (at least
-// BCtl::solo_min and at most BATCH_SOLO_MAX steps per launch).  The steps are the same arithmetic
-// either way, so only the number of steps a launch advances it varies.
+// BCtl::solo_min and at most BATCH_SOLO_MAX steps per launch).  While every
+// instance of the batch is solo, a launch is k_batch_solo instead: one block
+// per instance, BATCH_SOLO_ONLY steps with the line held in registers.  The
+// line solve, the observation sums and the finalisation are the same
+// arithmetic either way, so only the number of steps a launch advances an
+// instance varies.
 #pragma once
 
 #include <stdint.h>
@@ -36,6 +40,7 @@ constexpr int BATCH_OBS_PTS = 16384;  // grid points per observation tile, at le
 constexpr int BATCH_NOBS = 10;        // FP64 sums per observation tile
 constexpr int BATCH_SOLO_MAX = 256;   // steps of a solo instance per launch, at most
 constexpr int BATCH_SOLO_ONLY = 64;   // ... and at least, once only solo instances run
+constexpr int BATCH_SOLO_HEAD = 1024; // table head entries (i < i_conv) of a register-resident solo line, at most
 
 // Geometry of one axis of one instance (see sscn_lines.hpp for ROW / COL).
 struct BAxis {
@@ -102,7 +107,7 @@ struct BCtl {
     int32_t ticket;
     int32_t exited;
     int32_t total_items;
-    int32_t error;         // set when a bounded wait gave up
+    int32_t error;         // bit 0: a bounded wait gave up; bit 1: a solo line had no register-resident form
     int32_t max_slots;
     int32_t solo_min;      // steps a solo item takes before it may stop early
     int32_t pad_[2];
@@ -118,6 +123,7 @@ struct BatchArgs {
 };
 
 hipError_t launch_batch_step(const BatchArgs &a, bool big, int grid, size_t lds, hipStream_t st);
+hipError_t launch_batch_solo(const BatchArgs &a, bool big, int grid, size_t lds, hipStream_t st);
 hipError_t batch_step_occupancy(bool big, size_t lds, int *blocks_per_cu);
 hipError_t launch_batch_scale(int elem, void *psi, int64_t npts, double *scale, hipStream_t st);
 

@@ -319,6 +319,7 @@ struct sscn_batch {
     BItem *h_items;                 // pinned work list
     int32_t *h_total;
     bool dirty;
+    bool solo_only;                 // every instance solo with a short table head: k_batch_solo launches
     int32_t total;
     std::map<std::pair<int, int>, hipGraphExec_t> graphs;
     hipEvent_t ev;
@@ -383,10 +384,16 @@ static hipError_t upload_items(sscn_batch *b)
     if (e != hipSuccess) return e;
     build_items(b);
     *b->h_total = b->total;
-    bool regular = false;
-    for (int i = 0; i < b->max_slots; ++i)
-        if (b->used[i] && !b->h_inst[i].solo) regular = true;
+    bool regular = false, all_fast = true;
+    for (int i = 0; i < b->max_slots; ++i) {
+        if (!b->used[i]) continue;
+        const BInst &I = b->h_inst[i];
+        if (!I.solo) regular = true;
+        else if (std::min(I.ax[0].lt.i_conv, I.ax[0].lt.n) > BATCH_SOLO_HEAD || (I.elem == 3 && I.ax[0].C == 16))
+            all_fast = false;   // the solo kernel has no form for these (k_batch_solo)
+    }
     b->h_total[2] = regular ? 1 : BATCH_SOLO_ONLY;
+    b->solo_only = !regular && all_fast;
     if (b->total > 0) {
         e = hipMemcpyAsync(b->ctl + b->lay.items, b->h_items, sizeof(BItem) * (size_t)b->total,
                            hipMemcpyHostToDevice, b->st);
@@ -515,6 +522,7 @@ int sscn_batch_create(int32_t max_slots, int64_t max_items, void *d_ctl, size_t 
     b->lay = ctl_layout(max_slots, max_items);
     b->st = static_cast<hipStream_t>(hip_stream);
     b->dirty = true;
+    b->solo_only = false;
     b->total = 0;
     b->ev_valid = false;
     b->h_inst = nullptr;
@@ -713,14 +721,20 @@ int sscn_batch_step(sscn_batch *b, int32_t nsteps)
     if (nsteps > 0 && b->total > 0) {
         const bool big = batch_big(b);
         // no more blocks than items: a block that finds no item still costs a
-        // dispatch and two atomics on the shared counters
-        const int grid = std::min(big ? b->grid_big : b->grid_small, (int)b->total);
+        // dispatch and two atomics on the shared counters.  Solo-only
+        // batches: one block per instance, nothing shared.
+        const bool solo = b->solo_only;
+        const int grid = solo ? (int)b->total : std::min(big ? b->grid_big : b->grid_small, (int)b->total);
         const BatchArgs a = batch_args(b);
+        auto launch = [&]() {
+            return solo ? launch_batch_solo(a, big, grid, kBatchLds, b->st)
+                        : launch_batch_step(a, big, grid, kBatchLds, b->st);
+        };
         if (b->st == nullptr) {
             for (int k = 0; k < nsteps; ++k)
-                if (launch_batch_step(a, big, grid, kBatchLds, b->st) != hipSuccess) return SSCN_E_HIP;
+                if (launch() != hipSuccess) return SSCN_E_HIP;
         } else {
-            const auto key = std::make_pair(nsteps, big ? -grid : grid);
+            const auto key = std::make_pair(nsteps, 4 * grid + (big ? 2 : 0) + (solo ? 1 : 0));
             auto it = b->graphs.find(key);
             if (it == b->graphs.end() && b->graphs.size() >= 16) {
                 for (auto &kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
@@ -731,7 +745,7 @@ int sscn_batch_step(sscn_batch *b, int32_t nsteps)
                 hipGraphExec_t ex = nullptr;
                 if (hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal) != hipSuccess) return SSCN_E_HIP;
                 hipError_t le = hipSuccess;
-                for (int k = 0; k < nsteps && le == hipSuccess; ++k) le = launch_batch_step(a, big, grid, kBatchLds, b->st);
+                for (int k = 0; k < nsteps && le == hipSuccess; ++k) le = launch();
                 if (hipStreamEndCapture(b->st, &g) != hipSuccess || le != hipSuccess) return SSCN_E_HIP;
                 const hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
                 (void)hipGraphDestroy(g);

@@ -83,10 +83,12 @@ struct Alg<T, true> {
     __device__ __forceinline__ static V add(V a, V b) { return V{a.re + b.re, a.im + b.im}; }
     __device__ __forceinline__ static V sub(V a, V b) { return V{a.re - b.re, a.im - b.im}; }
     __device__ __forceinline__ static V scal(T s, V a) { return V{s * a.re, s * a.im}; }
+    // explicit FMAs: a contractible a*b + c*d could be fused either way, and
+    // differently in different kernels; every path must round alike
     __device__ __forceinline__ static double norm2(V a) {
-        return double(a.re) * double(a.re) + double(a.im) * double(a.im);
+        return fmaT(double(a.re), double(a.re), double(a.im) * double(a.im));
     }
-    __device__ __forceinline__ static T norm2t(V a) { return a.re * a.re + a.im * a.im; }
+    __device__ __forceinline__ static T norm2t(V a) { return fmaT(a.re, a.re, a.im * a.im); }
     __device__ __forceinline__ static V coef(double re, double im) { return V{T(re), T(im)}; }
     __device__ __forceinline__ static V shfl_up(V a, int d) {
         return V{__shfl_up(a.re, d, 64), __shfl_up(a.im, d, 64)};

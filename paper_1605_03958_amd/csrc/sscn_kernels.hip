@@ -155,7 +155,8 @@ __global__ void __launch_bounds__(256) k_pointwise(PointArgs a)
         const T x = coord<T>(i, a.pp.cen[0], a.pp.dx[0]);
         const T y = coord<T>(j, a.pp.cen[1], a.pp.dx[1]);
         const T z = coord<T>(k, a.pp.cen[2], a.pp.dx[2]);
-        const T vp = T(a.pp.w2h[0]) * x * x + (T(a.pp.w2h[1]) * y * y + T(a.pp.w2h[2]) * z * z);
+        // the potential rounded as in the x sweep (row_solve)
+        const T vp = fmaT(T(a.pp.w2h[0]) * x, x, fmaT(T(a.pp.w2h[2]) * z, z, T(a.pp.w2h[1]) * y * y));
         psi[p] = apply_point<T, CPLX>(psi[p], scale, vp, dt, g);
     }
 }
@@ -239,9 +240,9 @@ __global__ void __launch_bounds__(256) k_obs_partials(ObsArgs a)
         for (int ax = 0; ax < 3; ++ax) {
             if (ax >= a.dim) break;
             const double x = (double(idx[ax]) - a.cen[ax]) * a.dx[ax];
-            vp += a.w2h[ax] * x * x;
-            acc[4 + ax] += x * q;
-            acc[7 + ax] += x * x * q;
+            vp = fmaT(a.w2h[ax] * x, x, vp);
+            acc[4 + ax] = fmaT(x, q, acc[4 + ax]);
+            acc[7 + ax] = fmaT(x * x, q, acc[7 + ax]);
             const V nb = (idx[ax] + 1 < a.n[ax]) ? psi[p + sx[ax]] : A::zero();
             double e = A::norm2(A::sub(nb, v));
             if (idx[ax] == 0) e += q;
@@ -249,8 +250,8 @@ __global__ void __launch_bounds__(256) k_obs_partials(ObsArgs a)
         }
         acc[0] += q;
         acc[1] += kin;
-        acc[2] += vp * q;
-        acc[3] += q * q;
+        acc[2] = fmaT(vp, q, acc[2]);
+        acc[3] = fmaT(q, q, acc[3]);
     }
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
@@ -283,8 +284,8 @@ __global__ void __launch_bounds__(256) k_obs_final(const double *partial, int np
         const double P = dvol * tot[2];
         const double I = dvol * tot[3];
         out[0] = N;
-        out[1] = (K + P + g * I) / N;
-        out[2] = (K + P + 0.5 * g * I) / N;
+        out[1] = fmaT(g, I, K + P) / N;
+        out[2] = fmaT(0.5 * g, I, K + P) / N;
         out[3] = K;
         out[4] = P;
         out[5] = I;

@@ -280,19 +280,48 @@ __device__ __forceinline__ LTab<T, CPLX> tab_at(const __attribute__((address_spa
     return LTab<T, CPLX>::make(ld_tab(tb, q));
 }
 
+// Entry k of thread t's chunk in a ROW line group of G threads: slot k*G + t
+// of a lane-major table (staged or in memory) ...
+template <class T, bool CPLX, class TB>
+__device__ __forceinline__ LTab<T, CPLX> row_tab(const TB *tb, int k, int G, int t)
+{
+    return tab_at<T, CPLX>(tb, k * G + t);
+}
+
+// ... or from a table held as its head, its constant tail and the line end,
+// seen from one thread's chunk: entries k < hk are head[k] (the head is
+// staged in LDS from the chunk's first point on), entries k >= zk lie past
+// the line end (zero), the rest equal the tail.  No memory is read for the
+// tail, which is nearly the whole line.
+template <class T, bool CPLX>
+struct HeadTab {
+    const LTab<T, CPLX> *head;
+    int hk, zk;
+    LTab<T, CPLX> tail;
+};
+
+template <class T, bool CPLX>
+__device__ __forceinline__ LTab<T, CPLX> row_tab(const HeadTab<T, CPLX> *tb, int k, int, int)
+{
+    if (k < tb->hk) return tb->head[k];
+    if (k >= tb->zk) return LTab<T, CPLX>::make(TabEntry{0.0, 0.0, 0.0, 0.0});
+    return tb->tail;
+}
+
 // ---------------------------------------------------------------------------
 // ROW: one x line per line group.  xs: 4 values per wave of the group (LDS,
 // used when MW).  Returns the thread's sum |v|^2 when `last`.  The load of
 // the lane's values (row_load) is apart from the solve (row_solve), so a
 // caller can issue the next line's loads before solving the current one;
-// row_line does both.
+// row_line does both.  With `keep` the solution replaces u instead of being
+// stored (a caller that holds its line in registers across steps).
 // ---------------------------------------------------------------------------
 template <class T, bool CPLX, int C, bool MW, class TB, class PV>
 __device__ __forceinline__ double row_solve(PV __restrict__ psi, long long line,
                                             bool active, int n, const TB *tb, int G, int t, int lane, int wl,
                                             int wpl, typename Alg<T, CPLX>::V *xs, typename Alg<T, CPLX>::V sig,
                                             T scale, T dt, T g, const PointParams &pp, int ks, bool last,
-                                            typename Alg<T, CPLX>::V (&u)[C])
+                                            typename Alg<T, CPLX>::V (&u)[C], bool keep = false)
 {
     using A = Alg<T, CPLX>;
     using V = typename A::V;
@@ -306,13 +335,13 @@ __device__ __forceinline__ double row_solve(PV __restrict__ psi, long long line,
         const int k = (int)(line / pp.n[1]);
         const T y = coord<T>(j, pp.cen[1], pp.dx[1]);
         const T z = coord<T>(k, pp.cen[2], pp.dx[2]);
-        vyz = T(pp.w2h[1]) * y * y + T(pp.w2h[2]) * z * z;
+        vyz = fmaT(T(pp.w2h[2]) * z, z, T(pp.w2h[1]) * y * y);
     }
 #pragma unroll
     for (int k = 0; k < C; ++k) {
         const int i = i0 + k;
         const T x = coord<T>(i, pp.cen[0], pp.dx[0]);
-        u[k] = apply_point<T, CPLX>(u[k], scale, T(pp.w2h[0]) * x * x + vyz, dt, g);
+        u[k] = apply_point<T, CPLX>(u[k], scale, fmaT(T(pp.w2h[0]) * x, x, vyz), dt, g);
     }
 
     // ---- neighbours across chunk boundaries ----
@@ -339,7 +368,7 @@ __device__ __forceinline__ double row_solve(PV __restrict__ psi, long long line,
             const V nxt = (k + 1 < C) ? u[k + 1] : right;
             const V r = cn_rhs<T, CPLX>(prev, u[k], nxt, sig);
             prev = u[k];
-            const LTab<T, CPLX> e = tab_at<T, CPLX>(tb, k * G + t);
+            const LTab<T, CPLX> e = row_tab<T, CPLX>(tb, k, G, t);
             be[k] = e.mmul(r);
             d = e.afma(d, be[k]);
             Ac = A::mul(e.alpha(), Ac);
@@ -369,8 +398,11 @@ __device__ __forceinline__ double row_solve(PV __restrict__ psi, long long line,
                 xs[wl * 4 + 3] = PB;
             }
             __syncthreads();
+            // a truncated scan (ks < 6) reaches back fewer than 64 chunks, so
+            // only the previous wave feeds this one: the earlier waves' terms
+            // carry more chunk factors than the truncation keeps
             V Dw = A::zero();
-            for (int q = 0; q < wl; ++q) Dw = A::fma(xs[q * 4 + 2], Dw, xs[q * 4 + 3]);
+            for (int q = ks < 6 ? max(0, wl - 1) : 0; q < wl; ++q) Dw = A::fma(xs[q * 4 + 2], Dw, xs[q * 4 + 3]);
             __syncthreads();
             din = A::fma(EA, Dw, EB);
         } else {
@@ -380,14 +412,14 @@ __device__ __forceinline__ double row_solve(PV __restrict__ psi, long long line,
     d = din;
 #pragma unroll
     for (int k = 0; k < C; ++k) {
-        d = tab_at<T, CPLX>(tb, k * G + t).afma(d, be[k]);
+        d = row_tab<T, CPLX>(tb, k, G, t).afma(d, be[k]);
         be[k] = d;
     }
 
     // ---- backward ----
     V v = A::zero();
 #pragma unroll
-    for (int k = C - 1; k >= 0; --k) v = tab_at<T, CPLX>(tb, k * G + t).afma(v, be[k]);
+    for (int k = C - 1; k >= 0; --k) v = row_tab<T, CPLX>(tb, k, G, t).afma(v, be[k]);
     V vin;
     {
         V PA = Ac, PB = v;
@@ -411,7 +443,8 @@ __device__ __forceinline__ double row_solve(PV __restrict__ psi, long long line,
             }
             __syncthreads();
             V Vw = A::zero();
-            for (int q = wpl - 1; q > wl; --q) Vw = A::fma(xs[q * 4 + 2], Vw, xs[q * 4 + 3]);
+            for (int q = ks < 6 ? min(wpl - 1, wl + 1) : wpl - 1; q > wl; --q)
+                Vw = A::fma(xs[q * 4 + 2], Vw, xs[q * 4 + 3]);
             __syncthreads();
             vin = A::fma(EA, Vw, EB);
         } else {
@@ -421,7 +454,7 @@ __device__ __forceinline__ double row_solve(PV __restrict__ psi, long long line,
     v = vin;
 #pragma unroll
     for (int k = C - 1; k >= 0; --k) {
-        v = tab_at<T, CPLX>(tb, k * G + t).afma(v, be[k]);
+        v = row_tab<T, CPLX>(tb, k, G, t).afma(v, be[k]);
         be[k] = v;
     }
 
@@ -430,8 +463,9 @@ __device__ __forceinline__ double row_solve(PV __restrict__ psi, long long line,
 #pragma unroll
     for (int k = 0; k < C; ++k) {
         const int i = i0 + k;
+        if (keep) u[k] = be[k];
         if (active && i < n) {
-            st_elem(psi, base + i, be[k]);
+            if (!keep) st_elem(psi, base + i, be[k]);
             if (last) nacc += A::norm2(be[k]);
         }
     }

@@ -190,11 +190,13 @@ def test_work_list_capacity_is_enforced():
     b.close()
 
 
-def test_solo_instance_steps_and_mix_independence():
-    """A 1D instance runs whole steps inside one block: alone it advances 64
-    steps per launch; next to a 3D instance it advances at least one per
-    launch, and its state is bitwise the same either way."""
-    one = make(1, (5000, 1, 1), IMAG, seed=50)
+@pytest.mark.parametrize("n,mode", [(5000, IMAG), (2048, REAL), (9912, IMAG), (12000, REAL)])
+def test_solo_instance_steps_and_mix_independence(n, mode):
+    """A 1D instance runs whole steps inside one block: alone (the solo
+    kernel, line held in registers) it advances 64 steps per launch; next to
+    a 3D instance (the persistent kernel's solo cycle) it advances at least
+    one per launch, and its state is bitwise the same either way."""
+    one = make(1, (n, 1, 1), mode, seed=50)
     big = make(3, (48, 49, 50), IMAG, seed=51)
     b = sscn.Batch(2)
     b.admit(0, one[0], one[1], mu_tol=0.0, max_steps=300)
@@ -204,6 +206,7 @@ def test_solo_instance_steps_and_mix_independence():
     b.step(3)
     st = b.poll(wait=True)[0]
     assert st.state == sscn.SLOT_DONE and st.steps == 300
+    alone_obs = st.obs
     alone = b.evict(0).cpu().numpy()
     b.close()
 
@@ -222,9 +225,11 @@ def test_solo_instance_steps_and_mix_independence():
     assert not b.error()
     assert st[0].state == sscn.SLOT_DONE and st[0].steps == 300
     print(f"solo finished 300 steps in {launches} launches beside a 48x49x50 instance", flush=True)
+    mix_obs = st[0].obs
     mix = b.evict(0).cpu().numpy()
     b.close()
     assert np.array_equal(alone, mix)
+    assert alone_obs == mix_obs
     ref = oracle.run(oprob(one[0]), one[1], 300).psi
     assert rel_l2(mix, ref) <= 5e-5
 
