@@ -333,9 +333,10 @@ __device__ __forceinline__ void batch_fin(const BInst &I, BState &S, double *red
 // keeps the instance state in LDS (sS), writing it back at the end.  Each
 // step is the split items' line solve, observation sums and finalisation,
 // so the results are theirs bit for bit.  Runs `steps` steps, fewer if the
-// instance stops.
+// instance stops or (target >= 0) once the persistent launches that run
+// beside it have all finished (BCtl::reg_epoch reaches target).
 template <class T, bool CPLX, int C, bool MW>
-__device__ void solo_run(const BInst &I, BState &S, BState &sS, int steps,
+__device__ void solo_run(const BInst &I, BState &S, BState &sS, int steps, int target, BCtl *ctl,
                          unsigned char *lds, double *red, double (*redq)[16], int *s_go)
 {
     using A = Alg<T, CPLX>;
@@ -376,6 +377,9 @@ __device__ void solo_run(const BInst &I, BState &S, BState &sS, int steps,
     if (tid == 0) sS = S;
     __syncthreads();
     for (int k = 1;; ++k) {
+        // the launch count is read early: its latency overlaps the step
+        int re = 0;
+        if (target >= 0 && tid == 0) re = __hip_atomic_load(&ctl->reg_epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const T scale = CPLX ? T(1) : T(sS.scale);
         const bool obs_now = batch_observes(I, sS);
         const double nacc = row_solve<T, CPLX, C, MW>(psi, 0, active, n, &ht, G, t, lane, wl, X.wpl, xs, sig, scale,
@@ -393,7 +397,7 @@ __device__ void solo_run(const BInst &I, BState &S, BState &sS, int steps,
             double tot[BATCH_NOBS];
             for (int q = 0; q < BATCH_NOBS; ++q) tot[q] = obs_now ? obs_part[q] : 0.0;
             fin_core(I, sS, nraw, tot, obs_now);
-            *s_go = sS.status == BS_RUNNING && k < steps;
+            *s_go = sS.status == BS_RUNNING && k < steps && (target < 0 || (int)((unsigned)re - (unsigned)target) < 0);
         }
         __syncthreads();
         if (!*s_go) break;
@@ -405,12 +409,12 @@ __device__ void solo_run(const BInst &I, BState &S, BState &sS, int steps,
 // The register-resident solo steps of an instance; false (nothing done) if
 // its geometry has none.
 template <bool BIG>
-__device__ __forceinline__ bool solo_fast(const BInst &I, BState &S, BState &sS, int steps,
+__device__ __forceinline__ bool solo_fast(const BInst &I, BState &S, BState &sS, int steps, int target, BCtl *ctl,
                                          unsigned char *lds, double *red, double (*redq)[16], int *s_go)
 {
     const BAxis &X = I.ax[0];
     if (min(X.lt.i_conv, X.lt.n) > BATCH_SOLO_HEAD) return false;
-#define SOLO(CPLX, C, MW) solo_run<float, CPLX, C, MW>(I, S, sS, steps, lds, red, redq, s_go)
+#define SOLO(CPLX, C, MW) solo_run<float, CPLX, C, MW>(I, S, sS, steps, target, ctl, lds, red, redq, s_go)
     if (I.elem == 1) {
         if (X.wpl > 1) {
             switch (X.C) {
@@ -628,15 +632,17 @@ __global__ void __launch_bounds__(BATCH_BLOCK) k_batch_step(BatchArgs a)
         a.ctl->ticket = 0;
         a.ctl->exited = 0;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        atomicAdd(&a.ctl->reg_epoch, 1);
     }
 }
 
-// Launches while every instance of the batch is solo: block b runs the solo
-// instance of work item b (the work list then holds only solo items) for up
-// to BATCH_SOLO_ONLY steps with its line in registers.  The blocks share
-// nothing, so no counter is touched.
+// Solo launches: block b runs the solo instance of work item b (the solo
+// items lead the work list) for up to `steps` steps with its line in
+// registers; with target >= 0 (beside persistent launches on another
+// stream) only until reg_epoch reaches target, and at least one step.  The
+// blocks share nothing.
 template <bool BIG>
-__global__ void __launch_bounds__(BATCH_BLOCK) k_batch_solo(BatchArgs a)
+__global__ void __launch_bounds__(BATCH_BLOCK) k_batch_solo(BatchArgs a, int steps, int target)
 {
     extern __shared__ unsigned char lds_raw[];
     __shared__ double red[16];
@@ -646,8 +652,8 @@ __global__ void __launch_bounds__(BATCH_BLOCK) k_batch_solo(BatchArgs a)
     const BItem w = a.items[blockIdx.x];
     const BInst &I = a.inst[w.slot];
     BState &S = a.state[w.slot];
-    if (w.pass != BP_SOLO || S.status != BS_RUNNING) return;
-    if (!solo_fast<BIG>(I, S, sS, BATCH_SOLO_ONLY, lds_raw, red, redq, &s_go) && threadIdx.x == 0)
+    if (w.pass == BP_SOLO && S.status == BS_RUNNING &&
+        !solo_fast<BIG>(I, S, sS, steps, target, a.ctl, lds_raw, red, redq, &s_go) && threadIdx.x == 0)
         atomicOr(&a.ctl->error, 2);
 }
 
@@ -676,10 +682,11 @@ hipError_t launch_batch_step(const BatchArgs &a, bool big, int grid, size_t lds,
     return hipGetLastError();
 }
 
-hipError_t launch_batch_solo(const BatchArgs &a, bool big, int grid, size_t lds, hipStream_t st)
+hipError_t launch_batch_solo(const BatchArgs &a, bool big, int grid, size_t lds, hipStream_t st, int steps,
+                             int target)
 {
-    if (big) hipLaunchKernelGGL(k_batch_solo<true>, dim3(grid), dim3(BATCH_BLOCK), lds, st, a);
-    else hipLaunchKernelGGL(k_batch_solo<false>, dim3(grid), dim3(BATCH_BLOCK), lds, st, a);
+    if (big) hipLaunchKernelGGL(k_batch_solo<true>, dim3(grid), dim3(BATCH_BLOCK), lds, st, a, steps, target);
+    else hipLaunchKernelGGL(k_batch_solo<false>, dim3(grid), dim3(BATCH_BLOCK), lds, st, a, steps, target);
     return hipGetLastError();
 }
 

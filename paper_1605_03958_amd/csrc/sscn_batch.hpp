@@ -18,7 +18,13 @@
 // while other items of the launch are still unclaimed (at least
 // BCtl::solo_min and at most BATCH_SOLO_MAX steps per launch).  While every
 // instance of the batch is solo, a launch is k_batch_solo instead: one block
-// per instance, BATCH_SOLO_ONLY steps with the line held in registers.  The
+// per instance, BATCH_SOLO_ONLY steps with the line held in registers.  In a
+// mixed batch on a stream, one launch of the same kernel per sscn_batch_step
+// call runs the solo instances on a second stream beside that call's
+// persistent launches (which leave them out of their work list, and whose
+// grid leaves their CUs free), stepping until the last of those launches has
+// finished (the persistent kernel counts its launches in reg_epoch), and at
+// least once.  The
 // line solve, the observation sums and the finalisation are the same
 // arithmetic either way, so only the number of steps a launch advances an
 // instance varies.
@@ -110,7 +116,8 @@ struct BCtl {
     int32_t error;         // bit 0: a bounded wait gave up; bit 1: a solo line had no register-resident form
     int32_t max_slots;
     int32_t solo_min;      // steps a solo item takes before it may stop early
-    int32_t pad_[2];
+    int32_t reg_epoch;     // persistent launches completed since the work list was uploaded
+    int32_t pad_[9];
 };
 
 struct BatchArgs {
@@ -123,7 +130,8 @@ struct BatchArgs {
 };
 
 hipError_t launch_batch_step(const BatchArgs &a, bool big, int grid, size_t lds, hipStream_t st);
-hipError_t launch_batch_solo(const BatchArgs &a, bool big, int grid, size_t lds, hipStream_t st);
+hipError_t launch_batch_solo(const BatchArgs &a, bool big, int grid, size_t lds, hipStream_t st, int steps,
+                             int target);
 hipError_t batch_step_occupancy(bool big, size_t lds, int *blocks_per_cu);
 hipError_t launch_batch_scale(int elem, void *psi, int64_t npts, double *scale, hipStream_t st);
 

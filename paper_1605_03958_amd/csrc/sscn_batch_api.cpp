@@ -319,14 +319,32 @@ struct sscn_batch {
     BItem *h_items;                 // pinned work list
     int32_t *h_total;
     bool dirty;
-    bool solo_only;                 // every instance solo with a short table head: k_batch_solo launches
+    int mode;                       // MODE_* of the current work list
+    int32_t n_fast;                 // solo items at the head of the list that the solo kernel runs
+    hipStream_t st2;                // second stream of MODE_SPLIT (null without a caller stream)
+    hipEvent_t ev_fork, ev_join;
     int32_t total;
-    std::map<std::pair<int, int>, hipGraphExec_t> graphs;
+    std::map<std::pair<int, int64_t>, hipGraphExec_t> graphs;
+    int64_t reg_launched;           // persistent launches enqueued since the list was uploaded
     hipEvent_t ev;
     bool ev_valid;
 };
 
+// How a step is launched:
+//   UNION      one persistent launch runs everything (solo items cycle in it)
+//   SOLO_ONLY  every instance is a fast solo one: k_batch_solo alone
+//   SPLIT      k_batch_solo for the fast solo instances on the second stream
+//              beside the persistent launch of the rest (caller stream only)
+enum { MODE_UNION = 0, MODE_SOLO_ONLY = 1, MODE_SPLIT = 2 };
+
 static BCtl *ctl_of(sscn_batch *b) { return reinterpret_cast<BCtl *>(b->ctl); }
+
+// A solo instance the solo kernel has a register-resident form for: a table
+// head that fits its LDS, and not a complex line of 16 points per thread.
+static bool solo_fast_ok(const BInst &I)
+{
+    return I.solo && std::min(I.ax[0].lt.i_conv, I.ax[0].lt.n) <= BATCH_SOLO_HEAD && !(I.elem == 3 && I.ax[0].C == 16);
+}
 static BInst *dinst(sscn_batch *b) { return reinterpret_cast<BInst *>(b->ctl + b->lay.inst); }
 static BState *dstate(sscn_batch *b) { return reinterpret_cast<BState *>(b->ctl + b->lay.state); }
 
@@ -362,9 +380,13 @@ static void build_items(sscn_batch *b)
     // larger instances first inside each pass (longest-processing-time order)
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return b->work[x] > b->work[y]; });
     int32_t t = 0;
-    // solo instances first: their items never wait and overlap the rest
+    // solo instances first (those the solo kernel runs at the very head):
+    // their items never wait and overlap the rest
     for (int i : order)
-        if (b->h_inst[i].solo) b->h_items[t++] = BItem{(uint16_t)i, (uint8_t)BP_SOLO, 0, 0};
+        if (solo_fast_ok(b->h_inst[i])) b->h_items[t++] = BItem{(uint16_t)i, (uint8_t)BP_SOLO, 0, 0};
+    b->n_fast = t;
+    for (int i : order)
+        if (b->h_inst[i].solo && !solo_fast_ok(b->h_inst[i])) b->h_items[t++] = BItem{(uint16_t)i, (uint8_t)BP_SOLO, 0, 0};
     for (int pass = BP_X; pass <= BP_FIN; ++pass)
         for (int i : order) {
             const BInst &I = b->h_inst[i];
@@ -383,17 +405,17 @@ static hipError_t upload_items(sscn_batch *b)
     hipError_t e = hipStreamSynchronize(b->st);
     if (e != hipSuccess) return e;
     build_items(b);
-    *b->h_total = b->total;
-    bool regular = false, all_fast = true;
-    for (int i = 0; i < b->max_slots; ++i) {
-        if (!b->used[i]) continue;
-        const BInst &I = b->h_inst[i];
-        if (!I.solo) regular = true;
-        else if (std::min(I.ax[0].lt.i_conv, I.ax[0].lt.n) > BATCH_SOLO_HEAD || (I.elem == 3 && I.ax[0].C == 16))
-            all_fast = false;   // the solo kernel has no form for these (k_batch_solo)
-    }
+    bool regular = false;
+    for (int i = 0; i < b->max_slots; ++i)
+        if (b->used[i] && !b->h_inst[i].solo) regular = true;
     b->h_total[2] = regular ? 1 : BATCH_SOLO_ONLY;
-    b->solo_only = !regular && all_fast;
+    if (b->total > 0 && b->n_fast == b->total) b->mode = MODE_SOLO_ONLY;
+    else if (b->n_fast > 0 && b->st2 && b->n_fast <= b->grid_small / 2) b->mode = MODE_SPLIT;
+    else b->mode = MODE_UNION;
+    // the persistent kernel's list: without the fast solo items in SPLIT
+    *b->h_total = b->mode == MODE_SPLIT ? b->total - b->n_fast : b->total;
+    b->h_total[3] = 0;                                     // the launch count restarts with the list
+    b->reg_launched = 0;
     if (b->total > 0) {
         e = hipMemcpyAsync(b->ctl + b->lay.items, b->h_items, sizeof(BItem) * (size_t)b->total,
                            hipMemcpyHostToDevice, b->st);
@@ -402,6 +424,8 @@ static hipError_t upload_items(sscn_batch *b)
     e = hipMemcpyAsync(&ctl_of(b)->total_items, b->h_total, sizeof(int32_t), hipMemcpyHostToDevice, b->st);
     if (e != hipSuccess) return e;
     e = hipMemcpyAsync(&ctl_of(b)->solo_min, b->h_total + 2, sizeof(int32_t), hipMemcpyHostToDevice, b->st);
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(&ctl_of(b)->reg_epoch, b->h_total + 3, sizeof(int32_t), hipMemcpyHostToDevice, b->st);
     if (e != hipSuccess) return e;
     b->dirty = false;
     return hipStreamSynchronize(b->st);
@@ -522,7 +546,11 @@ int sscn_batch_create(int32_t max_slots, int64_t max_items, void *d_ctl, size_t 
     b->lay = ctl_layout(max_slots, max_items);
     b->st = static_cast<hipStream_t>(hip_stream);
     b->dirty = true;
-    b->solo_only = false;
+    b->mode = MODE_UNION;
+    b->n_fast = 0;
+    b->reg_launched = 0;
+    b->st2 = nullptr;
+    b->ev_fork = b->ev_join = nullptr;
     b->total = 0;
     b->ev_valid = false;
     b->h_inst = nullptr;
@@ -531,6 +559,9 @@ int sscn_batch_create(int32_t max_slots, int64_t max_items, void *d_ctl, size_t 
     b->h_items = nullptr;
     b->h_total = nullptr;
     auto fail = [&](int code) {
+        if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+        if (b->ev_join) (void)hipEventDestroy(b->ev_join);
+        if (b->st2) (void)hipStreamDestroy(b->st2);
         if (b->h_inst) (void)hipHostFree(b->h_inst);
         if (b->h_state) (void)hipHostFree(b->h_state);
         if (b->h_state_init) (void)hipHostFree(b->h_state_init);
@@ -549,7 +580,7 @@ int sscn_batch_create(int32_t max_slots, int64_t max_items, void *d_ctl, size_t 
     if (hipHostMalloc((void **)&b->h_inst, sizeof(BInst) * max_slots) != hipSuccess ||
         hipHostMalloc((void **)&b->h_state, sizeof(BState) * max_slots) != hipSuccess ||
         hipHostMalloc((void **)&b->h_state_init, sizeof(BState) * max_slots) != hipSuccess ||
-        hipHostMalloc((void **)&b->h_items, sizeof(BItem) * (size_t)max_items) != hipSuccess ||
+        hipHostMalloc((void **)&b->h_items, std::max(sizeof(BItem) * (size_t)max_items, sizeof(BCtl))) != hipSuccess ||
         hipHostMalloc((void **)&b->h_total, sizeof(int32_t) * 64) != hipSuccess)
         return fail(SSCN_E_HIP);
     std::memset(b->h_inst, 0, sizeof(BInst) * max_slots);
@@ -564,8 +595,13 @@ int sscn_batch_create(int32_t max_slots, int64_t max_items, void *d_ctl, size_t 
         return fail(SSCN_E_HIP);
     b->grid_small = std::max(1, cus * std::max(1, per_small));
     b->grid_big = std::max(1, cus * std::max(1, per_big));
+    // the second stream of MODE_SPLIT (default priority, like the caller's)
+    if (b->st && (hipStreamCreateWithFlags(&b->st2, hipStreamNonBlocking) != hipSuccess ||
+                  hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) != hipSuccess ||
+                  hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming) != hipSuccess))
+        return fail(SSCN_E_HIP);
     // clear the control block (not captured: plain memset)
-    BCtl *hc = reinterpret_cast<BCtl *>(b->h_items);  // scratch use of the pinned buffer
+    BCtl *hc = reinterpret_cast<BCtl *>(b->h_items);  // scratch use of the pinned buffer (sized for it)
     if (hipMemsetAsync(b->ctl, 0, need, b->st) != hipSuccess) return fail(SSCN_E_HIP);
     BCtl c0;
     std::memset(&c0, 0, sizeof(c0));
@@ -720,21 +756,46 @@ int sscn_batch_step(sscn_batch *b, int32_t nsteps)
     if (b->dirty && upload_items(b) != hipSuccess) return SSCN_E_HIP;
     if (nsteps > 0 && b->total > 0) {
         const bool big = batch_big(b);
-        // no more blocks than items: a block that finds no item still costs a
-        // dispatch and two atomics on the shared counters.  Solo-only
-        // batches: one block per instance, nothing shared.
-        const bool solo = b->solo_only;
-        const int grid = solo ? (int)b->total : std::min(big ? b->grid_big : b->grid_small, (int)b->total);
-        const BatchArgs a = batch_args(b);
+        const bool solo = b->mode == MODE_SOLO_ONLY;
+        const bool split = b->mode == MODE_SPLIT;
+        // the launches on the caller's stream: the persistent kernel over the
+        // list (in SPLIT, the part after the fast solo items, with a grid that
+        // leaves the solo blocks' CUs free), or the solo kernel alone.  No
+        // more blocks than items: a block that finds no item still costs a
+        // dispatch and two atomics on the shared counters.
+        BatchArgs a = batch_args(b);
+        const BatchArgs a_solo = a;
+        int items = (int)b->total, cap = big ? b->grid_big : b->grid_small;
+        if (split) {
+            a.items += b->n_fast;
+            items -= b->n_fast;
+            cap -= b->n_fast;
+        }
+        const int grid = solo ? items : std::max(1, std::min(cap, items));
         auto launch = [&]() {
-            return solo ? launch_batch_solo(a, big, grid, kBatchLds, b->st)
+            return solo ? launch_batch_solo(a, big, grid, kBatchLds, b->st, BATCH_SOLO_ONLY, -1)
                         : launch_batch_step(a, big, grid, kBatchLds, b->st);
         };
+        if (split) {
+            // the solo kernel on the second stream, once for the whole call:
+            // its blocks step until the persistent kernel has counted this
+            // call's launches (and at most a bounded number of steps, so they
+            // end even if those launches were held back)
+            b->reg_launched += nsteps;
+            const int steps = (int)std::min<int64_t>(1 << 30, (int64_t)nsteps * BATCH_SOLO_MAX);
+            if (hipEventRecord(b->ev_fork, b->st) != hipSuccess || hipStreamWaitEvent(b->st2, b->ev_fork, 0) != hipSuccess ||
+                launch_batch_solo(a_solo, big, b->n_fast, kBatchLds, b->st2, steps, (int32_t)b->reg_launched) !=
+                    hipSuccess ||
+                hipEventRecord(b->ev_join, b->st2) != hipSuccess)
+                return SSCN_E_HIP;
+        }
         if (b->st == nullptr) {
             for (int k = 0; k < nsteps; ++k)
                 if (launch() != hipSuccess) return SSCN_E_HIP;
         } else {
-            const auto key = std::make_pair(nsteps, 4 * grid + (big ? 2 : 0) + (solo ? 1 : 0));
+            // replayed from a graph per (steps, launch shape, list offset)
+            const auto key = std::make_pair(nsteps, (int64_t)(4 * grid + (big ? 2 : 0) + (solo ? 1 : 0)) * 65536 +
+                                                        (split ? b->n_fast : 0));
             auto it = b->graphs.find(key);
             if (it == b->graphs.end() && b->graphs.size() >= 16) {
                 for (auto &kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
@@ -754,6 +815,7 @@ int sscn_batch_step(sscn_batch *b, int32_t nsteps)
             }
             if (hipGraphLaunch(it->second, b->st) != hipSuccess) return SSCN_E_HIP;
         }
+        if (split && hipStreamWaitEvent(b->st, b->ev_join, 0) != hipSuccess) return SSCN_E_HIP;
     }
     if (hipMemcpyAsync(b->h_state, dstate(b), sizeof(BState) * b->max_slots, hipMemcpyDeviceToHost, b->st) !=
             hipSuccess ||
@@ -814,8 +876,12 @@ int sscn_batch_destroy(sscn_batch *b)
 {
     if (!b) return SSCN_E_INVALID;
     (void)hipStreamSynchronize(b->st);
+    if (b->st2) (void)hipStreamSynchronize(b->st2);
     for (auto &kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
     (void)hipEventDestroy(b->ev);
+    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+    if (b->ev_join) (void)hipEventDestroy(b->ev_join);
+    if (b->st2) (void)hipStreamDestroy(b->st2);
     (void)hipHostFree(b->h_inst);
     (void)hipHostFree(b->h_state);
     (void)hipHostFree(b->h_state_init);

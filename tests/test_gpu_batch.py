@@ -4,6 +4,7 @@ the batch; graph replays equal direct launches; isolation of a blown-up
 instance."""
 import numpy as np
 import pytest
+import torch
 
 import oracle
 from paper_1605_03958_amd import inputs, sscn
@@ -210,26 +211,30 @@ def test_solo_instance_steps_and_mix_independence(n, mode):
     alone = b.evict(0).cpu().numpy()
     b.close()
 
-    b = sscn.Batch(2)
-    b.admit(1, big[0], big[1], mu_tol=0.0, max_steps=1 << 30)
-    b.admit(0, one[0], one[1], mu_tol=0.0, max_steps=300)
-    launches = 0
-    while True:
-        b.step(1)
-        launches += 1
-        st = b.poll(wait=True)
-        assert st[1].steps == launches and st[0].steps >= min(launches, 300)
-        if st[0].state != sscn.SLOT_RUNNING:
-            break
-        assert launches < 300
-    assert not b.error()
-    assert st[0].state == sscn.SLOT_DONE and st[0].steps == 300
-    print(f"solo finished 300 steps in {launches} launches beside a 48x49x50 instance", flush=True)
-    mix_obs = st[0].obs
-    mix = b.evict(0).cpu().numpy()
-    b.close()
-    assert np.array_equal(alone, mix)
-    assert alone_obs == mix_obs
+    # on the default stream the persistent kernel runs the solo instance's
+    # steps itself; on a stream of its own the solo kernel runs them beside it
+    for stream in (None, torch.cuda.Stream()):
+        b = sscn.Batch(2, stream=stream)
+        b.admit(1, big[0], big[1], mu_tol=0.0, max_steps=1 << 30)
+        b.admit(0, one[0], one[1], mu_tol=0.0, max_steps=300)
+        launches = 0
+        while True:
+            b.step(1)
+            launches += 1
+            st = b.poll(wait=True)
+            assert st[1].steps == launches and st[0].steps >= min(launches, 300)
+            if st[0].state != sscn.SLOT_RUNNING:
+                break
+            assert launches < 300
+        assert not b.error()
+        assert st[0].state == sscn.SLOT_DONE and st[0].steps == 300
+        print(f"solo finished 300 steps in {launches} launches beside a 48x49x50 instance "
+              f"({'default' if stream is None else 'own'} stream)", flush=True)
+        mix_obs = st[0].obs
+        mix = b.evict(0).cpu().numpy()
+        b.close()
+        assert np.array_equal(alone, mix)
+        assert alone_obs == mix_obs
     ref = oracle.run(oprob(one[0]), one[1], 300).psi
     assert rel_l2(mix, ref) <= 5e-5
 
