@@ -173,9 +173,16 @@ int make_plan(const sscn_problem &pb, const TileOverride *ov, Plan &P)
                 X.lpb = std::max(1, 4 / wpl);
                 X.block = 64 * wpl * X.lpb;
                 X.grid = (int)std::min<int64_t>(ceil_div(X.nlines, X.lpb), 4096);
-                // single-wave lines stage their table in LDS; multi-wave
-                // lines exchange 4 values per wave
-                X.lds = (wpl == 1) ? (size_t)c * 64 * ltab_bytes(P) : (size_t)X.lpb * wpl * 4 * P.S;
+                // single-wave lines stage their table in LDS and move their
+                // values through a per-wave buffer of c*64 + 64 values when
+                // both fit 64 KB (k_row decides alike); multi-wave lines
+                // exchange 4 values per wave
+                if (wpl == 1) {
+                    const size_t tab = (size_t)c * 64 * ltab_bytes(P), tr = (size_t)X.lpb * (c * 64 + 64) * P.S;
+                    X.lds = (P.S >= 16 && tab + tr <= 65536) ? tab + tr : tab;
+                } else {
+                    X.lds = (size_t)X.lpb * wpl * 4 * P.S;
+                }
                 X.tab_entries = (size_t)c * 64 * wpl;
             }
         } else {
@@ -406,6 +413,7 @@ static hipError_t enqueue_step(sscn_solver *s, bool do_renorm, Timer *tm)
             r.nlines = (int32_t)X.nlines;
             r.wpl = X.wpl;
             r.lpb = X.lpb;
+            r.pairs = (X.n % 2 == 0) && (reinterpret_cast<uintptr_t>(s->psi) % 16 == 0);
             r.sig_re = X.sig_re;
             r.sig_im = X.sig_im;
             r.pp = point_params(s);

@@ -50,16 +50,41 @@ __global__ void __launch_bounds__(MW ? 1024 : 256) k_row(RowArgs a)
         stage_table<T, CPLX>(a.lt, tl, C * G, G, C);
         __syncthreads();
     }
+    // single-wave lines move their values through a per-wave LDS buffer
+    // after the table (row_load_tr), so every global access is coalesced,
+    // when table and buffers fit 64 KB (the host sizes the LDS alike)
+    constexpr bool TR = sizeof(V) >= 16 &&
+                        (size_t)C * 64 * sizeof(LTab<T, CPLX>) + 4 * ((size_t)C * 64 + 64) * sizeof(V) <= 65536;
+    V *buf = reinterpret_cast<V *>(tl + C * G) + lb * (C * 64 + 64);
+    // 8-byte values (complex FP32) move as 16-byte pairs where alignment allows
+    constexpr bool PAIRS = sizeof(V) == 8 && C % 2 == 0;
     for (long long gb = (long long)blockIdx.x * a.lpb; gb < a.nlines;
          gb += (long long)gridDim.x * a.lpb) {
         const long long line = gb + lb;
         const bool active = line < a.nlines;
-        if constexpr (MW)
+        if constexpr (MW) {
             nacc += row_line<T, CPLX, C, true>(psi, line, active, a.lt.n, a.lt.tab, G, t, lane, wl, a.wpl, xs,
                                                sig, scale, dt, g, a.pp, a.lt.depth, LAST);
-        else
+        } else if constexpr (PAIRS) {
+            V u[C];
+            if (a.pairs) row_load_pairs<T, CPLX, C>(psi, line, active, a.lt.n, t, u);
+            else row_load<T, CPLX, C>(psi, line, active, a.lt.n, t, u);
+            nacc += row_solve<T, CPLX, C, false>(psi, line, active, a.lt.n, static_cast<const LTab<T, CPLX> *>(tl),
+                                                 G, t, lane, wl, 1, xs, sig, scale, dt, g, a.pp, a.lt.depth, LAST, u,
+                                                 true);
+            if (a.pairs) row_store_pairs<T, CPLX, C>(psi, line, active, a.lt.n, t, u);
+            else row_store<T, CPLX, C>(psi, line, active, a.lt.n, t, u);
+        } else if constexpr (TR) {
+            V u[C];
+            row_load_tr<T, CPLX, C>(psi, line, active, a.lt.n, lane, buf, u);
+            nacc += row_solve<T, CPLX, C, false>(psi, line, active, a.lt.n, static_cast<const LTab<T, CPLX> *>(tl),
+                                                 G, t, lane, wl, 1, xs, sig, scale, dt, g, a.pp, a.lt.depth, LAST, u,
+                                                 true);
+            row_store_tr<T, CPLX, C>(psi, line, active, a.lt.n, lane, buf, u);
+        } else {
             nacc += row_line<T, CPLX, C, false>(psi, line, active, a.lt.n, static_cast<const LTab<T, CPLX> *>(tl),
                                                 G, t, lane, wl, 1, xs, sig, scale, dt, g, a.pp, a.lt.depth, LAST);
+        }
     }
     if constexpr (LAST) {
         const double s = block_sum(nacc, red);

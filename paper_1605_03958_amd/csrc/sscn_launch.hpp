@@ -31,6 +31,7 @@ struct RowArgs {
     int32_t nlines;        // n_y * n_z
     int32_t wpl;           // waves per line (power of two, <= 16)
     int32_t lpb;           // lines per block
+    int32_t pairs;         // 1: lines of even length, psi 16-byte aligned (paired accesses of 8-byte values)
     double sig_re, sig_im; // CN coefficient s
     PointParams pp;
     const double *scale;   // pending renormalisation factor (imaginary time)

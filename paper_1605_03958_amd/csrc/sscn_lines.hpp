@@ -487,6 +487,106 @@ __device__ __forceinline__ void row_load(PV __restrict__ psi, long long line,
     }
 }
 
+// A lane's chunk of 8-byte values moved as 16-byte pairs (C even, the chunk
+// 16-byte aligned: even line length and an aligned state): half the memory
+// instructions of element-wise accesses.
+template <class V>
+__device__ __forceinline__ void pair_split(const float4 &w, V &a, V &b)
+{
+    static_assert(sizeof(V) == 8, "8-byte values");
+    __builtin_memcpy(&a, &w, 8);
+    __builtin_memcpy(&b, reinterpret_cast<const char *>(&w) + 8, 8);
+}
+
+template <class T, bool CPLX, int C>
+__device__ __forceinline__ void row_load_pairs(const typename Alg<T, CPLX>::V *__restrict__ psi, long long line,
+                                               bool active, int n, int t, typename Alg<T, CPLX>::V (&u)[C])
+{
+    using A = Alg<T, CPLX>;
+    const int i0 = t * C;
+    const float4 *q = reinterpret_cast<const float4 *>(psi + line * (long long)n + i0);
+#pragma unroll
+    for (int j = 0; j < C / 2; ++j) {
+        if (active && i0 + 2 * j < n) {
+            pair_split(q[j], u[2 * j], u[2 * j + 1]);
+        } else {
+            u[2 * j] = A::zero();
+            u[2 * j + 1] = A::zero();
+        }
+    }
+}
+
+template <class T, bool CPLX, int C>
+__device__ __forceinline__ void row_store_pairs(typename Alg<T, CPLX>::V *__restrict__ psi, long long line,
+                                                bool active, int n, int t, const typename Alg<T, CPLX>::V (&v)[C])
+{
+    const int i0 = t * C;
+    float4 *q = reinterpret_cast<float4 *>(psi + line * (long long)n + i0);
+#pragma unroll
+    for (int j = 0; j < C / 2; ++j) {
+        if (active && i0 + 2 * j < n) {
+            float4 w;
+            __builtin_memcpy(&w, &v[2 * j], 8);
+            __builtin_memcpy(reinterpret_cast<char *>(&w) + 8, &v[2 * j + 1], 8);
+            q[j] = w;
+        }
+    }
+}
+
+// Coalesced ROW load and store for single-wave lines (G = 64) through a
+// per-wave LDS buffer: lane l moves points k*64 + l (each wave access is one
+// contiguous run), and the buffer regroups them into the lane's chunk of C
+// consecutive points.  Point i sits at buf[i + i / C]: one pad slot per
+// chunk, so the chunk reads of the 64 lanes spread over the banks.  The
+// buffer holds C*64 + 64 values; only this wave touches it, and a wave's LDS
+// accesses complete in order.
+template <class T, bool CPLX, int C, class PV>
+__device__ __forceinline__ void row_load_tr(PV __restrict__ psi, long long line, bool active, int n, int lane,
+                                            typename Alg<T, CPLX>::V *buf, typename Alg<T, CPLX>::V (&u)[C])
+{
+    using A = Alg<T, CPLX>;
+    const long long base = line * (long long)n;
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+        const int e = k * 64 + lane;
+        buf[e + e / C] = (active && e < n) ? ld_elem(psi, base + e) : A::zero();
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int k = 0; k < C; ++k) u[k] = buf[lane * (C + 1) + k];
+}
+
+template <class T, bool CPLX, int C, class PV>
+__device__ __forceinline__ void row_store_tr(PV __restrict__ psi, long long line, bool active, int n, int lane,
+                                             typename Alg<T, CPLX>::V *buf, const typename Alg<T, CPLX>::V (&v)[C])
+{
+    const long long base = line * (long long)n;
+#pragma unroll
+    for (int k = 0; k < C; ++k) buf[lane * (C + 1) + k] = v[k];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+        const int e = k * 64 + lane;
+        if (active && e < n) st_elem(psi, base + e, buf[e + e / C]);
+    }
+}
+
+// The C values of this lane's chunk back to the line (the store of row_solve).
+template <class T, bool CPLX, int C, class PV>
+__device__ __forceinline__ void row_store(PV __restrict__ psi, long long line, bool active, int n, int t,
+                                          const typename Alg<T, CPLX>::V (&v)[C])
+{
+    const int i0 = t * C;
+    const long long base = line * (long long)n;
+#pragma unroll
+    for (int k = 0; k < C; ++k)
+        if (active && i0 + k < n) st_elem(psi, base + i0 + k, v[k]);
+}
+
 template <class T, bool CPLX, int C, bool MW, class TB, class PV>
 __device__ __forceinline__ double row_line(PV __restrict__ psi, long long line,
                                            bool active, int n, const TB *tb, int G, int t, int lane, int wl,
