@@ -197,7 +197,15 @@ int sscn_density_2d(sscn_solver *s, int drop, void *d_out);
  * persistent kernel whose blocks take tiles of all instances from a work
  * list in dependency order (x tiles, then y, z, observation tiles, then one
  * finalisation per instance); on a non-null stream a call's launches are
- * captured once into a hipGraph and replayed.  Every instance uses the same
+ * captured once into a hipGraph and replayed.  A 1D instance whose line
+ * fits one block (a solo instance) takes whole steps inside one block and
+ * may advance several steps per launch: 64 per launch while every instance
+ * is solo; in a batch on a non-null stream that also holds larger
+ * instances, a kernel of its own on a second stream (created with the
+ * batch) steps the solo instances for as long as the call's persistent
+ * launches run, at least once per call.  The steps taken are reported per
+ * instance (sscn_batch_slot.steps); the arithmetic of a step is the same
+ * either way.  Every instance uses the same
  * method as sscn_step with prec = SSCN_F32 and renorm_every = 1 (imaginary
  * time) and is observed every observe_every steps; a ground-state instance
  * stops at the first observation with |mu - mu_prev| < mu_tol (mu_tol > 0),
@@ -254,7 +262,9 @@ int sscn_batch_plan_info(const sscn_problem *pb, int32_t *info, int32_t cap);
 
 /* Create a batch over a caller-owned, 256-byte aligned device control block
  * of at least sscn_batch_ctl_bytes bytes, on hip_stream.  Clears the block.
- * Allocates pinned host mirrors only. */
+ * Allocates pinned host mirrors only (no device memory); on a non-null
+ * stream it also creates one HIP stream and two events, released by
+ * sscn_batch_destroy.  SSCN_E_HIP if any of these fails. */
 int sscn_batch_create(int32_t max_slots, int64_t max_items, void *d_ctl, size_t ctl_bytes, void *hip_stream,
                       sscn_batch **out);
 
@@ -281,8 +291,10 @@ int sscn_batch_admit(sscn_batch *b, int32_t slot, const sscn_problem *pb, void *
  * pending factor of its last step is applied).  Waits for the stream. */
 int sscn_batch_evict(sscn_batch *b, int32_t slot);
 
-/* Enqueue nsteps persistent launches (one per step) and an asynchronous copy
- * of the per-instance status to a pinned host mirror. */
+/* Enqueue nsteps persistent launches (one step of every running non-solo
+ * instance each; solo instances as described above) and an asynchronous
+ * copy of the per-instance status to a pinned host mirror.  All work of
+ * the call is ordered before that copy on the batch's stream. */
 int sscn_batch_step(sscn_batch *b, int32_t nsteps);
 
 /* Copy the status of slots 0..nslots-1 from the mirror written by the last
@@ -290,8 +302,10 @@ int sscn_batch_step(sscn_batch *b, int32_t nsteps);
  * wait != 0: waits for it. */
 int sscn_batch_poll(sscn_batch *b, sscn_batch_slot *out, int32_t nslots, int32_t wait);
 
-/* 1 in *flag if a bounded wait inside the persistent kernel ever gave up
- * (results of that launch are then invalid); waits for the stream. */
+/* Nonzero *flag if a bounded wait inside the persistent kernel ever gave
+ * up (bit 0; results of that launch are then invalid) or a solo instance
+ * met the solo kernel without a form for its line (bit 1; it did not
+ * advance); waits for the stream. */
 int sscn_batch_error(sscn_batch *b, int32_t *flag);
 
 /* Free the batch's host state (device buffers belong to the caller). */
