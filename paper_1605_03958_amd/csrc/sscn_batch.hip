@@ -353,16 +353,35 @@ __device__ void solo_run(const BInst &I, BState &S, BState &sS, int steps, int t
     const int wl = t >> 6;
     const bool active = lb == 0;          // the line is line 0 of group 0
     const int n = X.lt.n;
-    const int H = min(X.lt.i_conv, n);
-    LTab<T, CPLX> *head = reinterpret_cast<LTab<T, CPLX> *>(lds);
-    V *xs = reinterpret_cast<V *>(head + H) + lb * X.wpl * 4;
-    // the table is lane-major: point i = t*C + k sits at slot k*G + t
-    for (int i = tid; i < H; i += blockDim.x) head[i] = LTab<T, CPLX>::make(ld_tab(tab, (i % C) * G + i / C));
-    HeadTab<T, CPLX> ht;
-    ht.head = head + t * C;
-    ht.hk = active ? H - t * C : 0;
-    ht.zk = active ? n - t * C : 0;
-    ht.tail = LTab<T, CPLX>::make(TabEntry{X.lt.ac_re, X.lt.ac_im, X.lt.mc_re, X.lt.mc_im});
+    // table entries: wave 0 (the head, i < i_conv <= 64*C) and the wave that
+    // holds the line end read an LDS copy of their entries (slots 0 and 1,
+    // lane-major); the waves between read the tail entry, those past the end
+    // a zero entry, without memory accesses
+    const int W = MW ? X.wpl : 1;
+    const int span = 64 * C;                   // points per wave
+    const int wb = n / span;                   // the wave holding the line end (== W: none)
+    const int nslot = (W > 1 && wb < W) ? 2 : 1;
+    const LTab<T, CPLX> tail = LTab<T, CPLX>::make(TabEntry{X.lt.ac_re, X.lt.ac_im, X.lt.mc_re, X.lt.mc_im});
+    const LTab<T, CPLX> zero = LTab<T, CPLX>::make(TabEntry{0.0, 0.0, 0.0, 0.0});
+    LTab<T, CPLX> *etab = reinterpret_cast<LTab<T, CPLX> *>(lds);
+    V *xs = reinterpret_cast<V *>(etab + nslot * span) + lb * X.wpl * 4;
+    for (int q = tid; q < nslot * span; q += blockDim.x) {
+        const int slot = q / span, r = q - slot * span;
+        const int i = ((slot == 0 ? 0 : wb) * 64 + (r & 63)) * C + (r >> 6);
+        LTab<T, CPLX> e = tail;
+        if (i >= n) e = zero;
+        else if (i < X.lt.i_conv) e = LTab<T, CPLX>::make(ld_tab(tab, (i % C) * G + i / C));  // lane-major: k*G + t
+        etab[q] = e;
+    }
+    EdgeTab<T, CPLX> ht;
+    {
+        int slot = -1;
+        if (active && wl == 0) slot = 0;
+        else if (active && wl == wb) slot = 1;
+        ht.uniform = __builtin_amdgcn_readfirstlane(slot < 0 ? 1 : 0);
+        ht.p = etab + (slot < 0 ? 0 : slot) * span + lane;
+        ht.e = (!active || wl > wb) ? zero : tail;
+    }
     const V sig = A::coef(X.sig_re, X.sig_im);
     const GP<const double> obs_part = (GP<const double>)I.obs_part;
     auto store_line = [&](const V (&v)[C]) {
@@ -413,7 +432,7 @@ __device__ __forceinline__ bool solo_fast(const BInst &I, BState &S, BState &sS,
                                          unsigned char *lds, double *red, double (*redq)[16], int *s_go)
 {
     const BAxis &X = I.ax[0];
-    if (min(X.lt.i_conv, X.lt.n) > BATCH_SOLO_HEAD) return false;
+    if (min(X.lt.i_conv, X.lt.n) > BATCH_SOLO_HEAD || X.lt.i_conv > 64 * X.C) return false;
 #define SOLO(CPLX, C, MW) solo_run<float, CPLX, C, MW>(I, S, sS, steps, target, ctl, lds, red, redq, s_go)
     if (I.elem == 1) {
         if (X.wpl > 1) {

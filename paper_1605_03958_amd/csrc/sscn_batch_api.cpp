@@ -340,10 +340,12 @@ enum { MODE_UNION = 0, MODE_SOLO_ONLY = 1, MODE_SPLIT = 2 };
 static BCtl *ctl_of(sscn_batch *b) { return reinterpret_cast<BCtl *>(b->ctl); }
 
 // A solo instance the solo kernel has a register-resident form for: a table
-// head that fits its LDS, and not a complex line of 16 points per thread.
+// head within the first wave's points, and not a complex line of 16 points
+// per thread.
 static bool solo_fast_ok(const BInst &I)
 {
-    return I.solo && std::min(I.ax[0].lt.i_conv, I.ax[0].lt.n) <= BATCH_SOLO_HEAD && !(I.elem == 3 && I.ax[0].C == 16);
+    return I.solo && std::min(I.ax[0].lt.i_conv, I.ax[0].lt.n) <= BATCH_SOLO_HEAD && I.ax[0].lt.i_conv <= 64 * I.ax[0].C &&
+           !(I.elem == 3 && I.ax[0].C == 16);
 }
 static BInst *dinst(sscn_batch *b) { return reinterpret_cast<BInst *>(b->ctl + b->lay.inst); }
 static BState *dstate(sscn_batch *b) { return reinterpret_cast<BState *>(b->ctl + b->lay.state); }

@@ -288,24 +288,24 @@ __device__ __forceinline__ LTab<T, CPLX> row_tab(const TB *tb, int k, int G, int
     return tab_at<T, CPLX>(tb, k * G + t);
 }
 
-// ... or from a table held as its head, its constant tail and the line end,
-// seen from one thread's chunk: entries k < hk are head[k] (the head is
-// staged in LDS from the chunk's first point on), entries k >= zk lie past
-// the line end (zero), the rest equal the tail.  No memory is read for the
-// tail, which is nearly the whole line.
+// ... or, for a line whose table is a head (i < i_conv), a constant tail
+// entry and zeros past the line end: the waves that hold head entries or
+// the line end read their entries from an LDS copy in the lane-major order
+// (p = the lane's first slot, entry k at p[k*64]); every other wave uses one
+// entry for all its points (the tail, or zero past the line end), chosen
+// per wave, so it reads no memory for its table.
 template <class T, bool CPLX>
-struct HeadTab {
-    const LTab<T, CPLX> *head;
-    int hk, zk;
-    LTab<T, CPLX> tail;
+struct EdgeTab {
+    const LTab<T, CPLX> *p;
+    int uniform;                 // the same for all lanes of the wave
+    LTab<T, CPLX> e;             // the entry of a uniform wave
 };
 
 template <class T, bool CPLX>
-__device__ __forceinline__ LTab<T, CPLX> row_tab(const HeadTab<T, CPLX> *tb, int k, int, int)
+__device__ __forceinline__ LTab<T, CPLX> row_tab(const EdgeTab<T, CPLX> *tb, int k, int, int)
 {
-    if (k < tb->hk) return tb->head[k];
-    if (k >= tb->zk) return LTab<T, CPLX>::make(TabEntry{0.0, 0.0, 0.0, 0.0});
-    return tb->tail;
+    if (tb->uniform) return tb->e;
+    return tb->p[k * 64];
 }
 
 // ---------------------------------------------------------------------------
