@@ -326,6 +326,26 @@ __device__ __forceinline__ void batch_fin(const BInst &I, BState &S, double *red
 // ---------------------------------------------------------------------------
 // solo instances: whole steps of one 1D line inside one block
 // ---------------------------------------------------------------------------
+// The ROW table of a solo line (a row_tab overload): a head (i < i_conv), a
+// constant tail entry and zeros past the line end.  The waves that hold head
+// entries or the line end read their entries from an LDS copy in the
+// lane-major order (p = the lane's first slot, entry k at p[k*64]); every
+// other wave uses one entry for all its points (the tail, or zero past the
+// line end), chosen per wave, so it reads no memory for its table.
+template <class T, bool CPLX>
+struct EdgeTab {
+    const LTab<T, CPLX> *p;
+    int uniform;                 // the same for all lanes of the wave
+    LTab<T, CPLX> e;             // the entry of a uniform wave
+};
+
+template <class T, bool CPLX>
+__device__ __forceinline__ LTab<T, CPLX> row_tab(const EdgeTab<T, CPLX> *tb, int k, int, int)
+{
+    if (tb->uniform) return tb->e;
+    return tb->p[k * 64];
+}
+
 // A solo instance's steps with its line in registers for the whole call:
 // the state is read once and written once (and on observation steps), the
 // table head is staged in LDS (the tail is one constant entry), the norm

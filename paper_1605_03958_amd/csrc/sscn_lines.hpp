@@ -281,31 +281,12 @@ __device__ __forceinline__ LTab<T, CPLX> tab_at(const __attribute__((address_spa
 }
 
 // Entry k of thread t's chunk in a ROW line group of G threads: slot k*G + t
-// of a lane-major table (staged or in memory) ...
+// of a lane-major table (staged or in memory).  Other table forms add their
+// own overload (found by argument-dependent lookup).
 template <class T, bool CPLX, class TB>
 __device__ __forceinline__ LTab<T, CPLX> row_tab(const TB *tb, int k, int G, int t)
 {
     return tab_at<T, CPLX>(tb, k * G + t);
-}
-
-// ... or, for a line whose table is a head (i < i_conv), a constant tail
-// entry and zeros past the line end: the waves that hold head entries or
-// the line end read their entries from an LDS copy in the lane-major order
-// (p = the lane's first slot, entry k at p[k*64]); every other wave uses one
-// entry for all its points (the tail, or zero past the line end), chosen
-// per wave, so it reads no memory for its table.
-template <class T, bool CPLX>
-struct EdgeTab {
-    const LTab<T, CPLX> *p;
-    int uniform;                 // the same for all lanes of the wave
-    LTab<T, CPLX> e;             // the entry of a uniform wave
-};
-
-template <class T, bool CPLX>
-__device__ __forceinline__ LTab<T, CPLX> row_tab(const EdgeTab<T, CPLX> *tb, int k, int, int)
-{
-    if (tb->uniform) return tb->e;
-    return tb->p[k * 64];
 }
 
 // ---------------------------------------------------------------------------
