@@ -421,8 +421,18 @@ __device__ void solo_run(const BInst &I, BState &S, BState &sS, int steps, int t
         if (target >= 0 && tid == 0) re = __hip_atomic_load(&ctl->reg_epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const T scale = CPLX ? T(1) : T(sS.scale);
         const bool obs_now = batch_observes(I, sS);
-        const double nacc = row_solve<T, CPLX, C, MW>(psi, 0, active, n, &ht, G, t, lane, wl, X.wpl, xs, sig, scale,
-                                                      T(pp.dt), T(pp.g), pp, X.lt.depth, true, u, true);
+        // a single-wave line reads its staged table directly (slot 0 is the
+        // whole lane-major table), as the persistent kernel's x item does:
+        // through the per-wave form the compiler rounded some lines of few
+        // points per thread differently (last-bit differences, measured)
+        double nacc;
+        if constexpr (MW)
+            nacc = row_solve<T, CPLX, C, MW>(psi, 0, active, n, &ht, G, t, lane, wl, X.wpl, xs, sig, scale, T(pp.dt),
+                                             T(pp.g), pp, X.lt.depth, true, u, true);
+        else
+            nacc = row_solve<T, CPLX, C, MW>(psi, 0, active, n, static_cast<const LTab<T, CPLX> *>(etab), G, t, lane,
+                                             wl, X.wpl, xs, sig, scale, T(pp.dt), T(pp.g), pp, X.lt.depth, true, u,
+                                             true);
         const double nraw = block_sum(nacc, red);
         if (obs_now) {
             // the observation item's own sums over the stored line, so the

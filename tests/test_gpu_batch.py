@@ -270,3 +270,101 @@ def test_item_split_setting():
         err = rel_l2(alone, ref)
         print(f"split {split}: rel L2 vs oracle {err:.2e}", flush=True)
         assert err <= 5e-5
+
+
+def _run_alone(case, mu_tol, max_steps, stream=None):
+    b = sscn.Batch(1, stream=stream)
+    b.admit(0, case[0], case[1], mu_tol=mu_tol, max_steps=max_steps)
+    while True:
+        b.step(20)
+        st = b.poll(wait=True)[0]
+        if st.state != sscn.SLOT_RUNNING:
+            break
+    assert not b.error()
+    out = (st.state, st.steps, st.obs, b.evict(0).cpu().numpy())
+    b.close()
+    return out
+
+
+def test_concurrent_solo_launches_converge_like_alone():
+    """On a stream of its own, a batch of solo lines (a fast real one, a fast
+    complex one, a complex line of 16 points per thread that the persistent
+    kernel keeps) and two larger instances runs the solo kernel beside the
+    persistent launches.  Every instance stops at the same step with the same
+    state and observables as alone, and the ground-state line converges."""
+    cases = [make(1, (3000, 1, 1), IMAG, seed=80), make(1, (2048, 1, 1), REAL, seed=81),
+             make(1, (12000, 1, 1), REAL, seed=82), make(3, (40, 44, 36), IMAG, seed=83),
+             make(2, (120, 96, 1), IMAG, seed=84)]
+    tol = [1e-6, 0.0, 0.0, 1e-6, 1e-6]
+    cap = [60000, 700, 700, 3000, 3000]
+    alone = [_run_alone(c, t, m) for c, t, m in zip(cases, tol, cap)]
+    b = sscn.Batch(len(cases), stream=torch.cuda.Stream())
+    for i, (c, t, m) in enumerate(zip(cases, tol, cap)):
+        b.admit(i, c[0], c[1], mu_tol=t, max_steps=m)
+    done = {}
+    while len(done) < len(cases):
+        b.step(20)
+        st = b.poll(wait=True)
+        for i, x in enumerate(st):
+            if i not in done and x.state != sscn.SLOT_RUNNING:
+                done[i] = (x.state, x.steps, x.obs, b.evict(i).cpu().numpy())
+    assert not b.error()
+    b.close()
+    for i in range(len(cases)):
+        a, m = alone[i], done[i]
+        print(f"case {i} n={cases[i][0].n} mode={cases[i][0].mode}: state {m[0]} steps {m[1]}", flush=True)
+        assert a[0] == m[0] and a[1] == m[1]
+        assert a[2] == m[2]
+        assert np.array_equal(a[3], m[3])
+    assert done[0][0] == sscn.SLOT_CONVERGED
+
+
+def test_many_solo_lines_beside_a_larger_instance():
+    """More solo lines than the solo kernel may take CUs for (over half the
+    persistent grid) keep running inside the persistent kernel; the results
+    are those of each line alone."""
+    lines = [make(1, (64 + 8 * (i % 5), 1, 1), IMAG, seed=90 + i) for i in range(200)]
+    big = make(3, (24, 20, 28), IMAG, seed=89)
+    b = sscn.Batch(len(lines) + 1, stream=torch.cuda.Stream())
+    b.admit(len(lines), big[0], big[1], mu_tol=0.0, max_steps=40)
+    for i, c in enumerate(lines):
+        b.admit(i, c[0], c[1], mu_tol=0.0, max_steps=40)
+    b.step(40)
+    st = b.poll(wait=True)
+    assert not b.error()
+    assert all(x.state == sscn.SLOT_DONE and x.steps == 40 for x in st)
+    got = [b.evict(i).cpu().numpy() for i in (0, 7, 199)]
+    b.close()
+    for i, g in zip((0, 7, 199), got):
+        a = _run_alone(lines[i], 0.0, 40)
+        assert np.array_equal(a[3], g)
+        assert rel_l2(g, oracle.run(oprob(lines[i][0]), lines[i][1], 40).psi) <= 5e-5
+
+
+@pytest.mark.parametrize("n,mode,sigma", [(3000, IMAG, 0.1), (9912, IMAG, 2.0), (3000, REAL, 0.5), (96, IMAG, 0.025),
+                                          (300, IMAG, 0.025)])
+def test_solo_lines_with_deeper_scans(n, mode, sigma):
+    """Solo lines whose row scans need several Kogge-Stone steps (larger
+    sigma, or few points per thread) are bitwise the same in the solo kernel
+    (alone) as in the persistent kernel (beside a 3D instance)."""
+    h = 0.1
+    p = Problem(1, (n, 1, 1), (h,), (1.0,), 5.0, sigma * 4 * h * h, mode, F32, 1 if mode == IMAG else 0, 10)
+    psi0 = inputs.ho_gaussian(1, p.n, p.dx, p.omega, noise=1e-3, seed=7)
+    if mode == REAL:
+        psi0 = psi0.astype(np.complex128)
+    alone = _run_alone((p, psi0), 0.0, 30)
+    big = make(3, (24, 20, 28), IMAG, seed=8)
+    b = sscn.Batch(2)
+    b.admit(1, big[0], big[1], mu_tol=0.0, max_steps=1 << 30)
+    b.admit(0, p, psi0, mu_tol=0.0, max_steps=30)
+    while True:
+        b.step(1)
+        st = b.poll(wait=True)[0]
+        if st.state != sscn.SLOT_RUNNING:
+            break
+    assert not b.error()
+    mix = b.evict(0).cpu().numpy()
+    b.close()
+    assert alone[1] == st.steps == 30 and alone[2] == st.obs
+    assert np.array_equal(alone[3], mix)
+    assert rel_l2(mix, oracle.run(oprob(p), psi0, 30).psi) <= 5e-5
