@@ -419,7 +419,9 @@ def batch_clear_tile_hints() -> None:
 
 
 class Batch:
-    """A batch of FP32 instances advanced by one persistent launch per step.
+    """A batch of FP32 instances advanced by one persistent launch per step
+    (1D lines that fit one block take whole steps in a solo kernel, several
+    per launch; on a stream of its own beside the persistent launches).
 
     Owns (as torch tensors) the control block and, per admitted slot, the
     instance state and workspace."""
