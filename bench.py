@@ -10,7 +10,9 @@ Beside them: the 64-instance uneven batch run to convergence (aggregate
 grid-point-steps/s), and the serving loop under Poisson arrivals (p50/p99
 latency and throughput).
 
-Prints one JSON line (see the design doc for the fields).
+Prints one JSON line: the metric and its value for the complex128 run, the
+roofline of its dominant sweep, the complex64 run, the 64^3 ground-state
+time per step, the batch and serving results and the CPU oracle's rate.
 """
 from __future__ import annotations
 
@@ -31,7 +33,7 @@ HBM_PEAK_GBS = 8000.0
 SERVE_RATE = 19.0
 
 
-def c1_problem(prec):
+def cube256_problem(prec):
     from paper_1605_03958_amd.sscn import Problem, REAL
     dx = 0.1
     return Problem(3, (256, 256, 256), (dx, dx, dx), (1.0, 1.5, 2.0), 80.0, 0.02 * dx * dx, REAL, prec, 0)
@@ -101,7 +103,7 @@ def cpu_baseline(target_s: float = 12.0):
     steps until about target_s seconds have been timed."""
     import oracle
     from paper_1605_03958_amd import inputs
-    p = c1_problem(0)
+    p = cube256_problem(0)
     op = oracle.Problem(p.dim, p.n, p.dx, p.omega, p.g, p.dt, p.mode, p.renorm_every)
     psi = inputs.thomas_fermi(3, p.n, p.dx, p.omega, 100.0, phase_sigma=0.05, seed=1)
     psi = oracle.run(op, psi, 1).psi
@@ -127,7 +129,7 @@ def cpu_baseline(target_s: float = 12.0):
                       f"timed after one untimed step), FP64 C oracle with OpenMP over lines"}
 
 
-def c0_timing(steps: int = 500):
+def ground64_timing(steps: int = 500):
     """The 64^3 FP64 imaginary-time ground-state workload (dx = 0.2,
     dt = 0.1 dx^2, g = 22, renormalised every step): launch-bound, so it
     shows the per-step overhead (graph replay of runs of steps)."""
@@ -148,7 +150,7 @@ def c0_timing(steps: int = 500):
             "ms_per_step": 1e3 * el / steps, "ptsteps_per_s": p.points * steps / el, "mu": mu}
 
 
-def c3_problems():
+def mix64_problems():
     """The 64-instance uneven batch: 22 1D, 21 2D, 21 3D draws (seeds 100+i),
     imaginary time in FP32 with FP64 reductions, dt = 0.1 dx^2."""
     from paper_1605_03958_amd import inputs
@@ -162,14 +164,14 @@ def c3_problems():
     return out
 
 
-def batch_c3(tick: int = 100, cap: int = 300000, time_limit: float = 60.0):
+def batch_mix64(tick: int = 100, cap: int = 300000, time_limit: float = 60.0):
     """All 64 instances admitted at once and run to |delta mu| < 1e-6; each
     is evicted when it stops.  Also times the first steps, while all 64 run,
     against the HBM roofline (2 d S bytes per point-step)."""
     import numpy as np
     import torch
     from paper_1605_03958_amd import inputs, sscn
-    probs = c3_problems()
+    probs = mix64_problems()
     for _, p in probs:
         apply_tiles(p, "batch")
     st = torch.cuda.Stream()
@@ -230,7 +232,7 @@ def batch_c3(tick: int = 100, cap: int = 300000, time_limit: float = 60.0):
     }
 
 
-def serving_c4(count: int, rate: float, budget_gib: float, tick: int = 20, slots: int = 64):
+def serving_poisson(count: int, rate: float, budget_gib: float, tick: int = 20, slots: int = 64):
     """Poisson arrivals of ground-state (70 %) and dynamics (30 %) requests
     drawn like the batch mix, served with continuous batching under an HBM
     budget; latency is submission -> completion seen by the server."""
@@ -283,8 +285,9 @@ def main():
     ap.add_argument("--serve-budget-gib", type=float, default=32.0, help="HBM budget of the serving loop")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(independent problems shard trivially across GPUs, see DESIGN.md)", file=sys.stderr)
+        print(f"bench.py: runs on one GPU; --gpus {args.gpus} is not supported "
+              "(independent problems would shard across GPUs with no exchange; one large grid would need "
+              "a z-slab split of the z sweep)", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -292,7 +295,7 @@ def main():
 
     torch.cuda.set_device(0)
     if args.only == "batch":
-        print(json.dumps({"batch": batch_c3()}), flush=True)
+        print(json.dumps({"batch": batch_mix64()}), flush=True)
         return
     out = {}
     precs = [sscn.F64, sscn.F32]
@@ -302,7 +305,7 @@ def main():
         precs = [sscn.F32]
     psi0 = inputs.thomas_fermi(3, (256, 256, 256), (0.1,) * 3, (1.0, 1.5, 2.0), 100.0, phase_sigma=0.05, seed=1)
     for prec in precs:
-        p = c1_problem(prec)
+        p = cube256_problem(prec)
         apply_tiles(p, "single")
         s = sscn.Solver(p, psi0)
         el = time_steps(s, args.steps, args.warmup)
@@ -320,7 +323,7 @@ def main():
     dom = max(sweeps, key=sweeps.get)
     alg_bytes = 2 * m["S"] * m["points"]            # one read + one write of psi per sweep
     achieved = alg_bytes / (sweeps[dom] * 1e-3) / 1e9
-    workload = "c1_256cube_c128" if main_prec == sscn.F64 else "c2_256cube_c64"
+    workload = "256cube_complex128" if main_prec == sscn.F64 else "256cube_complex64"
     traffic = load_traffic(dom, workload)
     res = {
         "metric": METRIC,
@@ -353,11 +356,11 @@ def main():
     res["copy_gbs"] = copy_bandwidth(m["S"] * m["points"])
     res["roofline"]["frac_of_copy"] = achieved / res["copy_gbs"]
     if args.only is None:
-        res["c0"] = c0_timing()
+        res["ground64"] = ground64_timing()
     if args.only is None and not args.no_batch:
-        res["batch"] = batch_c3()
+        res["batch"] = batch_mix64()
     if args.only is None and not args.no_serve:
-        sv = serving_c4(args.serve_requests, args.serve_rate, args.serve_budget_gib)
+        sv = serving_poisson(args.serve_requests, args.serve_rate, args.serve_budget_gib)
         res["serving"] = sv
         res["p50_latency_s"] = sv["p50_s"]
         res["p99_latency_s"] = sv["p99_s"]

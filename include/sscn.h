@@ -59,7 +59,7 @@ extern "C" {
 #define SSCN_E_HIP          -2   /* a HIP runtime call failed */
 #define SSCN_E_NONFINITE    -3   /* norm or chemical potential is NaN/Inf */
 #define SSCN_E_NOSPACE      -4   /* slot busy / buffer too small */
-#define SSCN_E_UNSUPPORTED  -5   /* valid problem outside this build's limits */
+#define SSCN_E_UNSUPPORTED  -5   /* valid problem outside the library's limits */
 
 /* mode and precision */
 #define SSCN_IMAG 0

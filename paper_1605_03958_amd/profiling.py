@@ -16,7 +16,7 @@ step: the x sweep (k_row), then the y and z sweeps (k_col, in that order).
 
 Usage:
   python -m paper_1605_03958_amd.profiling --trace DIR --fetch DIR --write DIR \
-      --workload c1_256cube_c128 --state-bytes 268435456 --name sweeps_c1_256cube_c128 \
+      --workload 256cube_complex128 --state-bytes 268435456 --name sweeps_256cube_complex128 \
       --command "<the rocprofv3 command lines>"
 """
 from __future__ import annotations
@@ -97,7 +97,7 @@ def trace_only(args) -> None:
     whose work per launch varies with the set of running instances)."""
     stats = list(csv.DictReader(open(_find(args.trace, "kernel_stats.csv"))))
     lines = [f"# rocprofv3 summary: {args.name}", "", f"Workload: `{args.workload}`.", "",
-             "Command (run from the repository root on the GPU box):", "", "```", args.command.strip(), "```", "",
+             "Command (run from the repository root on the MI355X machine):", "", "```", args.command.strip(), "```", "",
              "## Kernel statistics (--kernel-trace --stats)", "",
              "| kernel | calls | average us | min us | max us | total ms | share % |",
              "|---|---|---|---|---|---|---|"]
@@ -138,7 +138,7 @@ def main():
     lines = [f"# rocprofv3 summary: {args.name}", "",
              f"Workload: `{args.workload}`; state {S} bytes; algorithmic bytes per sweep launch "
              f"(one read + one write of the state) {alg}.", "",
-             "Commands (run from the repository root on the GPU box):", "", "```",
+             "Commands (run from the repository root on the MI355X machine):", "", "```",
              args.command.strip(), "```", "",
              "## Kernel statistics (--kernel-trace --stats)", "",
              "| kernel | calls | average ns | share % |", "|---|---|---|---|"]

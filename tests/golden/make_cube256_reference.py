@@ -1,4 +1,4 @@
-"""Write tests/golden/c1_oracle_1000.json: the FP64 CPU oracle's result for
+"""Write tests/golden/cube256_oracle_1000.json: the FP64 CPU oracle's result for
 the 256^3 real-time workload after 1000 steps (observables before and after,
 and the state at a seeded sample of grid points).
 
@@ -28,7 +28,7 @@ NSAMPLE = 4096
 SAMPLE_SEED = 12345
 
 
-def main(out=os.path.join(HERE, "c1_oracle_1000.json")):
+def main(out=os.path.join(HERE, "cube256_oracle_1000.json")):
     n = (N, N, N)
     om = (1.0, 1.5, 2.0)
     prob = oracle.Problem(3, n, (DX,) * 3, om, 80.0, 0.02 * DX * DX, oracle.REAL, 0)

@@ -120,7 +120,7 @@ def test_tile_hints_give_the_same_result(chunks):
     assert rel_l2(got, ref) <= 1e-12
 
 
-def test_c0_ground_state_1000_steps():
+def test_ground64_1000_steps():
     """64^3 imaginary time, g = 22, FP64: rel-L2 <= 1e-10 after 500 and 1000
     steps, mu and E to 1e-10."""
     dx = 0.2
@@ -144,15 +144,15 @@ def test_c0_ground_state_1000_steps():
     assert abs(ob.energy - orf.energy) <= 1e-10 * abs(orf.energy)
 
 
-def c1_problem(prec=F64):
+def cube256_problem(prec=F64):
     dx = 0.1
     return Problem(3, (256, 256, 256), (dx,) * 3, (1.0, 1.5, 2.0), 80.0, 0.02 * dx * dx, REAL, prec, 0)
 
 
-def test_c1_full_size_short_run_matches_oracle():
+def test_cube256_short_run_matches_oracle():
     """256^3 complex128 real time in the benchmark's launch configuration:
     10 steps against the oracle."""
-    p = c1_problem()
+    p = cube256_problem()
     psi0 = inputs.thomas_fermi(3, p.n, p.dx, p.omega, 100.0, phase_sigma=0.05, seed=1)
     s = sscn.Solver(p, psi0)
     s.step(10)
@@ -161,11 +161,11 @@ def test_c1_full_size_short_run_matches_oracle():
     assert rel_l2(got, ref) <= 1e-12
 
 
-def test_c1_full_size_norm_and_energy_over_1000_steps():
+def test_cube256_norm_and_energy_over_1000_steps():
     """Properties that hold at any size: the real-time step conserves the
     discrete norm exactly (FP64 round-off), and the energy drift of the
     quenched state stays small."""
-    p = c1_problem()
+    p = cube256_problem()
     psi0 = inputs.thomas_fermi(3, p.n, p.dx, p.omega, 100.0, phase_sigma=0.05, seed=1)
     s = sscn.Solver(p, psi0)
     o0 = s.observe()
@@ -239,16 +239,16 @@ def test_large_sigma_full_depth_scans(mode, sigma):
     assert rel_l2(got, ref) <= max(1e-12, 1e-13 * (1 + 4 * sigma))
 
 
-def _golden_c1():
+def _golden_cube256():
     import json
     import os
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c1_oracle_1000.json")
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "cube256_oracle_1000.json")
     with open(path) as f:
         return json.load(f)
 
 
-def _c1_run(prec, steps=1000):
-    p = c1_problem(prec)
+def _cube256_run(prec, steps=1000):
+    p = cube256_problem(prec)
     psi0 = inputs.thomas_fermi(3, p.n, p.dx, p.omega, 100.0, phase_sigma=0.05, seed=1)
     s = sscn.Solver(p, psi0)
     s.step(steps)
@@ -258,17 +258,17 @@ def _c1_run(prec, steps=1000):
     return ob, flat
 
 
-def test_c1_1000_steps_matches_stored_oracle():
+def test_cube256_1000_steps_matches_stored_oracle():
     """256^3 complex128, 1000 steps, bench launch configuration, against the
-    stored oracle run (tests/golden/make_c1_reference.py): relative L2 over
+    stored oracle run (tests/golden/make_cube256_reference.py): relative L2 over
     4096 seeded sample points <= 1e-10, observables <= 1e-10 relative."""
-    ref = _golden_c1()
-    ob, flat = _c1_run(F64)
+    ref = _golden_cube256()
+    ob, flat = _cube256_run(F64)
     idx = np.asarray(ref["sample_index"])
     exp = np.asarray(ref["sample_re"]) + 1j * np.asarray(ref["sample_im"])
     got = flat[idx].astype(np.complex128)
     err = np.linalg.norm(got - exp) / np.linalg.norm(exp)
-    print(f"C1 FP64 sampled rel-L2 {err:.3e}", flush=True)
+    print(f"256^3 FP64 sampled rel-L2 {err:.3e}", flush=True)
     assert err <= 1e-10
     assert abs(np.sum(np.abs(flat) ** 2) / ref["l2sq"] - 1) <= 1e-12
     for f, g in (("norm", "norm"), ("mu", "mu"), ("energy", "energy"), ("ekin", "K"), ("epot", "P"),
@@ -276,11 +276,11 @@ def test_c1_1000_steps_matches_stored_oracle():
         assert abs(getattr(ob, f) - ref["obs1"][g]) <= 1e-10 * abs(ref["obs1"][g]), f
 
 
-def test_c2_fp32_error_against_stored_oracle():
+def test_cube256_fp32_error_against_stored_oracle():
     """complex64 storage, FP32 sweeps, FP64 tables and reductions, 1000 steps:
     the stated errors against the FP64 oracle; gate |d mu| <= 1e-5."""
-    ref = _golden_c1()
-    ob, flat = _c1_run(F32)
+    ref = _golden_cube256()
+    ob, flat = _cube256_run(F32)
     idx = np.asarray(ref["sample_index"])
     exp = np.asarray(ref["sample_re"]) + 1j * np.asarray(ref["sample_im"])
     got = flat[idx].astype(np.complex128)
@@ -289,7 +289,7 @@ def test_c2_fp32_error_against_stored_oracle():
     dmu = abs(ob.mu - o1["mu"])
     dE = abs(ob.energy - o1["energy"]) / abs(o1["energy"])
     dN = abs(ob.norm - o1["norm"])
-    print(f"C2 FP32: psi sampled rel-L2 {err:.3e}  |d mu| {dmu:.3e}  rel dE {dE:.3e}  |d norm| {dN:.3e}",
+    print(f"256^3 FP32: psi sampled rel-L2 {err:.3e}  |d mu| {dmu:.3e}  rel dE {dE:.3e}  |d norm| {dN:.3e}",
           flush=True)
     assert dmu <= 1e-5
     assert err <= 1e-3

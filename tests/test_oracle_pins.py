@@ -196,7 +196,7 @@ def test_ho_mu_closed_form_second_order():
             res.append(mu - (w / 2 - w * w * dx * dx / 32))
         assert abs(res[0]) < 1e-4
         assert abs(res[0]) > 8 * abs(res[1])
-    # and the uncorrected continuum value (nu + lambda + kappa)/2 at C0's dx
+    # and the uncorrected continuum value (nu + lambda + kappa)/2 at dx = 0.2
     dx = 0.2
     mu3 = 0.0
     for w in (1.0, 1.5, 2.0):
