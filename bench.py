@@ -27,9 +27,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "SSCN grid-point-steps/s at 256^3 FP64 vs FP32; p50/p99 batched solve latency"
 HBM_PEAK_GBS = 8000.0
-# Poisson arrival rate of the serving run (requests/s): about 0.7 of the
-# request throughput the server sustains on the same mix when every request
-# is submitted at once
+# Poisson arrival rate of the serving run (requests/s), kept fixed so that
+# runs stay comparable (0.54 of the 34.9 requests/s the server completes on
+# the same mix when every request is submitted at once)
 SERVE_RATE = 19.0
 
 
@@ -127,6 +127,37 @@ def cpu_baseline(target_s: float = 12.0):
             "kind": "oracle", "cpu": model,
             "sample": f"256^3 complex128 real-time workload, steps 2-{step - 1} ({steps} steps, {el:.1f} s "
                       f"timed after one untimed step), FP64 C oracle with OpenMP over lines"}
+
+
+def imag256_timing(steps: int = 300):
+    """The 64^3 ground-state physics at 256^3 (dx = 0.05, the same box;
+    dt = 0.1 dx^2, g = 22, renormalised every step) with a real FP64 and a
+    real FP32 state: grid-point-steps/s, per-sweep times and the step's
+    fraction of 8 TB/s (2 d S bytes per point-step)."""
+    import torch
+    from paper_1605_03958_amd import inputs, sscn
+    dx = 0.05
+    n = (256, 256, 256)
+    psi0 = inputs.ho_gaussian(3, n, (dx,) * 3, (1.0, 1.5, 2.0), noise=1e-3, seed=0)
+    out = {"workload": "256^3 imaginary time, dx=0.05, dt=0.1*dx^2, g=22, renormalised every step"}
+    for prec, S, name in ((sscn.F64, 8, "f64"), (sscn.F32, 4, "f32")):
+        p = sscn.Problem(3, n, (dx,) * 3, (1.0, 1.5, 2.0), 22.0, 0.1 * dx * dx, sscn.IMAG, prec, 1)
+        s = sscn.Solver(p, psi0)
+        s.step(20)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        k = s.step_timed(steps)
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+        out[name] = {"ptsteps_per_s": p.points * steps / el, "ms_per_step": 1e3 * el / steps,
+                     "hbm_frac": 6 * S * p.points * steps / el / (HBM_PEAK_GBS * 1e9),
+                     "kernel_ms": {kk: round(v, 5) for kk, v in k.items()}}
+    out["speedup_f32"] = out["f32"]["ptsteps_per_s"] / out["f64"]["ptsteps_per_s"]
+    return out
 
 
 def ground64_timing(steps: int = 500):
@@ -357,6 +388,7 @@ def main():
     res["roofline"]["frac_of_copy"] = achieved / res["copy_gbs"]
     if args.only is None:
         res["ground64"] = ground64_timing()
+        res["imag256"] = imag256_timing()
     if args.only is None and not args.no_batch:
         res["batch"] = batch_mix64()
     if args.only is None and not args.no_serve:

@@ -413,7 +413,7 @@ static hipError_t enqueue_step(sscn_solver *s, bool do_renorm, Timer *tm)
             r.nlines = (int32_t)X.nlines;
             r.wpl = X.wpl;
             r.lpb = X.lpb;
-            r.pairs = (X.n % 2 == 0) && (reinterpret_cast<uintptr_t>(s->psi) % 16 == 0);
+            r.v16 = P.S <= 8 && (X.n % (int)(16 / P.S) == 0) && (reinterpret_cast<uintptr_t>(s->psi) % 16 == 0);
             r.sig_re = X.sig_re;
             r.sig_im = X.sig_im;
             r.pp = point_params(s);

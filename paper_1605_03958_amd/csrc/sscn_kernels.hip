@@ -56,8 +56,9 @@ __global__ void __launch_bounds__(MW ? 1024 : 256) k_row(RowArgs a)
     constexpr bool TR = sizeof(V) >= 16 &&
                         (size_t)C * 64 * sizeof(LTab<T, CPLX>) + 4 * ((size_t)C * 64 + 64) * sizeof(V) <= 65536;
     V *buf = reinterpret_cast<V *>(tl + C * G) + lb * (C * 64 + 64);
-    // 8-byte values (complex FP32) move as 16-byte pairs where alignment allows
-    constexpr bool PAIRS = sizeof(V) == 8 && C % 2 == 0;
+    // 4- and 8-byte values move as 16-byte groups where the line length and
+    // the state's alignment allow (a.v16)
+    constexpr bool V16 = sizeof(V) <= 8 && C % (16 / sizeof(V)) == 0;
     for (long long gb = (long long)blockIdx.x * a.lpb; gb < a.nlines;
          gb += (long long)gridDim.x * a.lpb) {
         const long long line = gb + lb;
@@ -65,14 +66,14 @@ __global__ void __launch_bounds__(MW ? 1024 : 256) k_row(RowArgs a)
         if constexpr (MW) {
             nacc += row_line<T, CPLX, C, true>(psi, line, active, a.lt.n, a.lt.tab, G, t, lane, wl, a.wpl, xs,
                                                sig, scale, dt, g, a.pp, a.lt.depth, LAST);
-        } else if constexpr (PAIRS) {
+        } else if constexpr (V16) {
             V u[C];
-            if (a.pairs) row_load_pairs<T, CPLX, C>(psi, line, active, a.lt.n, t, u);
+            if (a.v16) row_load_v16<T, CPLX, C>(psi, line, active, a.lt.n, t, u);
             else row_load<T, CPLX, C>(psi, line, active, a.lt.n, t, u);
             nacc += row_solve<T, CPLX, C, false>(psi, line, active, a.lt.n, static_cast<const LTab<T, CPLX> *>(tl),
                                                  G, t, lane, wl, 1, xs, sig, scale, dt, g, a.pp, a.lt.depth, LAST, u,
                                                  true);
-            if (a.pairs) row_store_pairs<T, CPLX, C>(psi, line, active, a.lt.n, t, u);
+            if (a.v16) row_store_v16<T, CPLX, C>(psi, line, active, a.lt.n, t, u);
             else row_store<T, CPLX, C>(psi, line, active, a.lt.n, t, u);
         } else if constexpr (TR) {
             V u[C];

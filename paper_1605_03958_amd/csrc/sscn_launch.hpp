@@ -31,7 +31,7 @@ struct RowArgs {
     int32_t nlines;        // n_y * n_z
     int32_t wpl;           // waves per line (power of two, <= 16)
     int32_t lpb;           // lines per block
-    int32_t pairs;         // 1: lines of even length, psi 16-byte aligned (paired accesses of 8-byte values)
+    int32_t v16;           // 1: 16-byte groups of 4- or 8-byte values (line length a multiple, psi aligned)
     double sig_re, sig_im; // CN coefficient s
     PointParams pp;
     const double *scale;   // pending renormalisation factor (imaginary time)

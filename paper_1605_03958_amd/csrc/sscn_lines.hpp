@@ -468,47 +468,40 @@ __device__ __forceinline__ void row_load(PV __restrict__ psi, long long line,
     }
 }
 
-// A lane's chunk of 8-byte values moved as 16-byte pairs (C even, the chunk
-// 16-byte aligned: even line length and an aligned state): half the memory
-// instructions of element-wise accesses.
-template <class V>
-__device__ __forceinline__ void pair_split(const float4 &w, V &a, V &b)
-{
-    static_assert(sizeof(V) == 8, "8-byte values");
-    __builtin_memcpy(&a, &w, 8);
-    __builtin_memcpy(&b, reinterpret_cast<const char *>(&w) + 8, 8);
-}
-
+// A lane's chunk moved as 16-byte groups of 16/S values (S = 4 or 8 bytes;
+// C a multiple of the group, the line length too, and an aligned state, so
+// every group lies inside the line or wholly past its end): 16/S times fewer
+// memory instructions than element-wise accesses strided by the chunk.
 template <class T, bool CPLX, int C>
-__device__ __forceinline__ void row_load_pairs(const typename Alg<T, CPLX>::V *__restrict__ psi, long long line,
-                                               bool active, int n, int t, typename Alg<T, CPLX>::V (&u)[C])
+__device__ __forceinline__ void row_load_v16(const typename Alg<T, CPLX>::V *__restrict__ psi, long long line,
+                                             bool active, int n, int t, typename Alg<T, CPLX>::V (&u)[C])
 {
-    using A = Alg<T, CPLX>;
+    using V = typename Alg<T, CPLX>::V;
+    constexpr int PV = 16 / sizeof(V);
+    static_assert(sizeof(V) <= 8 && C % PV == 0, "whole 16-byte groups");
     const int i0 = t * C;
     const float4 *q = reinterpret_cast<const float4 *>(psi + line * (long long)n + i0);
 #pragma unroll
-    for (int j = 0; j < C / 2; ++j) {
-        if (active && i0 + 2 * j < n) {
-            pair_split(q[j], u[2 * j], u[2 * j + 1]);
-        } else {
-            u[2 * j] = A::zero();
-            u[2 * j + 1] = A::zero();
-        }
+    for (int j = 0; j < C / PV; ++j) {
+        float4 w = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (active && i0 + PV * j < n) w = q[j];
+        __builtin_memcpy(&u[PV * j], &w, 16);
     }
 }
 
 template <class T, bool CPLX, int C>
-__device__ __forceinline__ void row_store_pairs(typename Alg<T, CPLX>::V *__restrict__ psi, long long line,
-                                                bool active, int n, int t, const typename Alg<T, CPLX>::V (&v)[C])
+__device__ __forceinline__ void row_store_v16(typename Alg<T, CPLX>::V *__restrict__ psi, long long line,
+                                              bool active, int n, int t, const typename Alg<T, CPLX>::V (&v)[C])
 {
+    using V = typename Alg<T, CPLX>::V;
+    constexpr int PV = 16 / sizeof(V);
     const int i0 = t * C;
     float4 *q = reinterpret_cast<float4 *>(psi + line * (long long)n + i0);
 #pragma unroll
-    for (int j = 0; j < C / 2; ++j) {
-        if (active && i0 + 2 * j < n) {
+    for (int j = 0; j < C / PV; ++j) {
+        if (active && i0 + PV * j < n) {
             float4 w;
-            __builtin_memcpy(&w, &v[2 * j], 8);
-            __builtin_memcpy(reinterpret_cast<char *>(&w) + 8, &v[2 * j + 1], 8);
+            __builtin_memcpy(&w, &v[PV * j], 16);
             q[j] = w;
         }
     }
