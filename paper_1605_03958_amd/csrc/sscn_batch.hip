@@ -348,9 +348,10 @@ __device__ __forceinline__ LTab<T, CPLX> row_tab(const EdgeTab<T, CPLX> *tb, int
 
 // A solo instance's steps with its line in registers for the whole call:
 // the state is read once and written once (and on observation steps), the
-// table head is staged in LDS (the tail is one constant entry), the norm
-// and the finalisation pass through LDS between block barriers, and thread 0
-// keeps the instance state in LDS (sS), writing it back at the end.  Each
+// table is an EdgeTab (LDS entries for the first wave and the line-end wave,
+// one entry for each other wave), the norm and the finalisation pass through
+// LDS between block barriers, and thread 0 keeps the instance state in LDS
+// (sS), writing it back at the end.  Each
 // step is the split items' line solve, observation sums and finalisation,
 // so the results are theirs bit for bit.  Runs `steps` steps, fewer if the
 // instance stops or (target >= 0) once the persistent launches that run
