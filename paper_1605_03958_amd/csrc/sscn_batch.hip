@@ -595,11 +595,16 @@ __global__ void __launch_bounds__(BATCH_BLOCK) k_batch_step(BatchArgs a)
         if (dep >= 0) {
             if (threadIdx.x == 0) {
                 int32_t *cnt = a.done + (size_t)w.slot * 4 + dep;
+                const int32_t need = I.need[w.pass];
                 int spins = 0;
                 // bounded: after spin_limit polls (or once any wait of the
                 // launch has given up) the item proceeds and the error flag
-                // marks the launch's results invalid
-                while (__hip_atomic_load(cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < I.need[w.pass]) {
+                // marks the launch's results invalid.  The polls are relaxed
+                // (an acquire load would invalidate the caches on every
+                // poll, under the feet of the other blocks); one acquire
+                // fence after the count is reached orders the item's reads
+                // after the producers' releases.
+                while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
                     __builtin_amdgcn_s_sleep(2);
                     ++spins;
                     if (spins > a.spin_limit ||
@@ -609,6 +614,7 @@ __global__ void __launch_bounds__(BATCH_BLOCK) k_batch_step(BatchArgs a)
                         break;
                     }
                 }
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             }
             // thread 0's acquire invalidated this CU's caches; the barrier
             // orders the other waves' reads after it
