@@ -28,7 +28,7 @@ sys.path.insert(0, ROOT)
 METRIC = "SSCN grid-point-steps/s at 256^3 FP64 vs FP32; p50/p99 batched solve latency"
 HBM_PEAK_GBS = 8000.0
 # Poisson arrival rate of the serving run (requests/s), kept fixed so that
-# runs stay comparable (0.54 of the 34.9 requests/s the server completes on
+# runs stay comparable (0.53 of the 35.7 requests/s the server completes on
 # the same mix when every request is submitted at once)
 SERVE_RATE = 19.0
 
