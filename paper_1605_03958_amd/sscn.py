@@ -344,7 +344,10 @@ class Solver:
 
     def density_1d(self, keep: int) -> np.ndarray:
         import torch
-        out = torch.zeros(self.prob.n[keep], dtype=torch.float64, device=self.device)
+        # allocated on the solver's stream, which the kernel writes it on
+        # (every element)
+        with torch.cuda.stream(self.stream):
+            out = torch.empty(self.prob.n[keep], dtype=torch.float64, device=self.device)
         _check(lib().sscn_density_1d(self._h, int(keep), ctypes.c_void_p(out.data_ptr())), "sscn_density_1d")
         self.stream.synchronize()
         return out.cpu().numpy()
@@ -352,7 +355,8 @@ class Solver:
     def density_2d(self, drop: int) -> np.ndarray:
         import torch
         keep = [a for a in range(3) if a != drop]
-        out = torch.zeros((self.prob.n[keep[1]], self.prob.n[keep[0]]), dtype=torch.float64, device=self.device)
+        with torch.cuda.stream(self.stream):
+            out = torch.empty((self.prob.n[keep[1]], self.prob.n[keep[0]]), dtype=torch.float64, device=self.device)
         _check(lib().sscn_density_2d(self._h, int(drop), ctypes.c_void_p(out.data_ptr())), "sscn_density_2d")
         self.stream.synchronize()
         return out.cpu().numpy()
@@ -455,7 +459,6 @@ class Batch:
     def admit(self, slot: int, prob: Problem, psi0, mu_tol: float = 0.0, max_steps: int = 1 << 40):
         import torch
         wsb = batch_workspace_bytes(prob)
-        psi = torch.empty(prob.shape, dtype=prob.torch_dtype(), device=self.device)
         if isinstance(psi0, torch.Tensor):
             src = psi0.to(device=self.device, dtype=prob.torch_dtype()).reshape(prob.shape)
         else:
@@ -463,9 +466,13 @@ class Batch:
             if prob.mode == IMAG and np.iscomplexobj(a):
                 a = a.real
             src = torch.from_numpy(a.astype(prob.numpy_dtype())).to(self.device)
+        # src is ready on the caller's stream; the slot's tensors are made
+        # on the batch stream, which the library then works on
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
         with torch.cuda.stream(self.stream):
+            psi = torch.empty(prob.shape, dtype=prob.torch_dtype(), device=self.device)
             psi.copy_(src)
-        ws = torch.zeros(wsb // 8 + 32, dtype=torch.float64, device=self.device)
+            ws = torch.zeros(wsb // 8 + 32, dtype=torch.float64, device=self.device)
         self.stream.synchronize()
         pc = prob.c()
         _check(lib().sscn_batch_admit(self._h, int(slot), ctypes.byref(pc), ctypes.c_void_p(psi.data_ptr()),
