@@ -193,14 +193,17 @@ int make_plan(const sscn_problem &pb, const TileOverride *ov, Plan &P)
             // 4 points per thread (registers for two 1024-thread blocks per
             // CU), more only when 16 waves x Lmax lanes cannot cover the
             // line; Lmax keeps a wave's row segment (64/L lines x S bytes)
-            // at 128 bytes or more
+            // at 128 bytes or more.  A sweep of fewer than 256 blocks (one
+            // per CU) takes more lanes per line, up to Lmax: fewer lines
+            // and waves per block, more blocks (small grids)
             const int lmax = std::max(1, std::min(4, (int)(P.S / 2)));
             int c = 4;
             while (c < 64 && ceil_div(n, c) > 16 * lmax) c *= 2;
             c = std::min<int64_t>(c, pow2ceil(ceil_div(n, 16)));
             if (ov && ov->col_c[a] > 0) c = ov->col_c[a];
             const int64_t K = ceil_div(n, c);           // chunks per line
-            const int L = pow2ceil(ceil_div(K, 16));    // lanes per line
+            int L = pow2ceil(ceil_div(K, 16));          // lanes per line
+            while (L < lmax && L < K && ceil_div(X.nlines, 64 / L) < 256) L *= 2;
             const int64_t W = ceil_div(K, L);
             if (c <= cmax_col(P.S) && L <= 8) {
                 X.kind = K_COL;
