@@ -368,3 +368,26 @@ def test_solo_lines_with_deeper_scans(n, mode, sigma):
     assert alone[1] == st.steps == 30 and alone[2] == st.obs
     assert np.array_equal(alone[3], mix)
     assert rel_l2(mix, oracle.run(oprob(p), psi0, 30).psi) <= 5e-5
+
+
+def test_admit_waits_for_an_input_made_on_the_current_stream():
+    """A device input produced on the caller's stream behind a long kernel is
+    copied into the slot only once it is there (the batch runs on a stream
+    of its own)."""
+    p, psi0 = make(2, (48, 40, 1), IMAG, seed=3)
+    want = np.asarray(psi0).reshape(p.shape).astype(np.float32)
+    b = sscn.Batch(1, stream=torch.cuda.Stream())
+    src = torch.from_numpy(want).cuda()
+    big = torch.randn(4096, 4096, device="cuda")
+    busy = big @ big
+    dev = src + 0.0 * busy[:1, :1]  # ready only after the product
+    b.admit(0, p, dev)
+    got = b.psi[0].cpu().numpy()
+    assert np.array_equal(got, want)
+    b.step(5)
+    b.stream.synchronize()
+    ref = sscn.Batch(1)
+    ref.admit(0, p, psi0)
+    ref.step(5)
+    torch.cuda.synchronize()
+    assert np.array_equal(b.psi[0].cpu().numpy(), ref.psi[0].cpu().numpy())

@@ -201,6 +201,27 @@ def test_quench_set_g():
     assert rel_l2(got, r2) <= 1e-12
 
 
+def test_densities_are_ordered_on_the_solver_stream():
+    """The density outputs are made on the solver's own stream: with torch's
+    current stream still busy, the results are the kernel's (an output
+    cleared on the current stream would land after it)."""
+    import torch
+    p = Problem(3, (40, 36, 30), (0.25, 0.25, 0.3), (1.0, 1.5, 2.0), 10.0, 0.01, IMAG, F64, 1)
+    s = sscn.Solver(p, initial(p, 1))
+    s.step(3)
+    psi = s.state()
+    op = oprob(p)
+    big = torch.randn(4096, 4096, device="cuda")
+    for a in range(3):
+        busy = big @ big  # queued on the current stream, not waited for
+        assert np.allclose(s.density_1d(a), oracle.density_1d(op, psi, a), rtol=1e-12, atol=1e-14)
+        busy = big @ big
+        assert np.allclose(s.density_2d(a), oracle.density_2d(op, psi, a), rtol=1e-12, atol=1e-14)
+    torch.cuda.synchronize()
+    del busy
+    s.close()
+
+
 def test_integrated_densities_match_oracle():
     p = Problem(3, (40, 36, 30), (0.25, 0.25, 0.3), (1.0, 1.5, 2.0), 10.0, 0.01, IMAG, F64, 1)
     psi0 = initial(p, 1)
