@@ -106,6 +106,28 @@ def test_plan_geometries():
     assert sscn.plan_info(p)[1]["kind"] == "stream"
 
 
+@pytest.mark.parametrize("prec", [F64, F32])
+def test_small_grid_column_sweeps_take_more_lanes(prec):
+    # a y/z sweep of fewer than 256 blocks takes more lanes per line (up to
+    # 4 for 8-byte values, 2 for 4-byte ones) so that it launches more blocks
+    lmax = 4 if prec == F64 else 2
+    p = Problem(3, (64, 64, 64), (0.2,) * 3, (1, 1.5, 2), 22.0, 0.004, IMAG, prec, 1)
+    for q in sscn.plan_info(p)[1:]:
+        assert q["kind"] == "col" and q["lanes"] == lmax
+        assert q["grid"] == 64 * 64 // (64 // lmax)
+        assert q["chunk"] * q["waves"] * q["lanes"] >= 64
+    # a sweep that already has 256 blocks keeps the lanes its line length
+    # asks for (128 points: 32 chunks of 4 over 16 waves, 2 lanes)
+    p = Problem(3, (128, 128, 128), (0.2,) * 3, (1, 1.5, 2), 22.0, 0.004, IMAG, prec, 1)
+    for q in sscn.plan_info(p)[1:]:
+        assert (q["chunk"], q["waves"], q["lanes"], q["grid"]) == (4, 16, 2, 512)
+    # never more lanes than chunks: a short line keeps covering itself
+    p = Problem(2, (40, 6, 1), (0.2, 0.2), (1, 1.5), 1.0, 0.004, IMAG, prec, 1)
+    q = sscn.plan_info(p)[1]
+    assert q["kind"] == "col" and q["lanes"] <= max(1, -(-6 // q["chunk"]))
+    assert q["chunk"] * q["waves"] * q["lanes"] >= 6
+
+
 def test_tile_hints_change_the_plan():
     p = Problem(3, (64, 64, 64), (0.2,) * 3, (1, 1.5, 2), 22.0, 0.004, IMAG, F64, 1)
     try:
