@@ -337,3 +337,26 @@ def test_integrated_densities_of_product_gaussian():
     d2 = oracle.density_2d(prob, psi, 2)
     assert d2.shape == (n[1], n[0])
     assert np.allclose(np.sum(d2, axis=0) * dx[1], oracle.density_1d(prob, psi, 0), atol=1e-13)
+
+
+def test_quench_to_a_free_gas_breathes_with_period_pi_over_omega():
+    """Imaginary-time ground state at g = 10 handed to real time with the
+    nonlinearity switched off: a non-interacting gas in a harmonic trap has
+    <x^2>(t) = A + B cos(2 w t) + C sin(2 w t) (closed form), so its second
+    moment repeats after pi / w and does oscillate.  A wrong kinetic factor,
+    a dropped potential or a sign error breaks the period at O(1); the grid
+    and the splitting shift it by far less than the 1 % bound used here."""
+    n, dx = 400, 0.05
+    ip = Problem(1, (n,), (dx,), (1.0,), 10.0, 0.1 * dx * dx, IMAG, 1)
+    psi0 = inputs.ho_gaussian(1, (n, 1, 1), (dx, 1.0, 1.0), (1.0, 0.0, 0.0), noise=0.0)
+    g = oracle.run(ip, psi0, 400000, observe_every=10, mu_tol=1e-11)
+    assert g.converged
+    per = 2000
+    rp = Problem(1, (n,), (dx,), (1.0,), 0.0, math.pi / per, REAL, 0)
+    r = oracle.run(rp, g.psi.astype(np.complex128), 2 * per, observe_every=1)
+    step = r.trace[:, oracle.TRACE_COLS.index("step")].astype(int)
+    msq = r.trace[:, oracle.TRACE_COLS.index("mx2")]
+    assert list(step) == list(range(1, 2 * per + 1))
+    amp = msq.max() - msq.min()
+    assert amp > 0.1 * msq.mean()
+    assert np.max(np.abs(msq[per:] - msq[:per])) < 1e-2 * amp
