@@ -2,9 +2,11 @@
 every function include/sscn.h declares, validates problems before any side
 effect, sizes the state and workspace, and plans kernel geometries."""
 import ctypes
+import math
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_1605_03958_amd import sscn
@@ -291,3 +293,16 @@ def test_bench_refuses_more_than_one_gpu():
     out = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], cwd=root,
                          capture_output=True, text=True, timeout=300)
     assert out.returncode == 2 and "one GPU" in out.stderr and out.stdout == ""
+
+
+def test_dynamics_pipeline_host_checks():
+    # argument checks happen before any device work; rms from the moments
+    from paper_1605_03958_amd import dynamics
+    p = Problem(1, (64,), (0.1,), (1.0,), 1.0, 1e-3, REAL, F64, 0, 1)
+    with pytest.raises(ValueError):
+        dynamics.ground_state_then_dynamics(p, np.zeros(64), 0.5, 10, 1e-3)
+    q = Problem(1, (64,), (0.1,), (1.0,), 1.0, 1e-3, IMAG, F64, 1, 10)
+    with pytest.raises(ValueError):
+        dynamics.ground_state_then_dynamics(q, np.zeros(64), 0.5, -1, 1e-3)
+    o = sscn.Obs(0, 1.0, 0.0, 0.0, 0.0, 0.0, 0.0, (0.0, 0.0, 0.0), (4.0, 9.0, 0.0))
+    assert dynamics.rms_sizes(o, 2) == (2.0, 3.0, math.sqrt(13.0))
