@@ -181,6 +181,64 @@ def ground64_timing(steps: int = 500):
             "ms_per_step": 1e3 * el / steps, "ptsteps_per_s": p.points * steps / el, "mu": mu}
 
 
+def dynamics_timing(real_steps: int = 500):
+    """Ground state then dynamics at 128^3 FP64 (the 64^3 physics at
+    dx = 0.1): imaginary time to |delta mu| < 1e-8 (observed every 10 steps),
+    then real_steps real-time steps (dt = 0.02 dx^2, g x 0.8) with the rms
+    sizes observed every step, against the same real-time steps unobserved."""
+    import numpy as np
+    from paper_1605_03958_amd import dynamics, inputs, sscn
+    dx = 0.1
+    p = sscn.Problem(3, (128,) * 3, (dx,) * 3, (1.0, 1.5, 2.0), 22.0, 0.1 * dx * dx, sscn.IMAG, sscn.F64, 1, 10)
+    psi0 = inputs.ho_gaussian(3, p.n, p.dx, p.omega, noise=1e-3, seed=0)
+    d = dynamics.ground_state_then_dynamics(p, psi0, 0.8, real_steps, 0.02 * dx * dx, mu_tol=1e-8)
+    rp = sscn.Problem(3, p.n, p.dx, p.omega, 22.0 * 0.8, 0.02 * dx * dx, sscn.REAL, sscn.F64, 0, 0)
+    s = sscn.Solver(rp, psi0.astype(np.complex128))
+    s.step(20)
+    s.stream.synchronize()
+    t0 = time.perf_counter()
+    s.step(real_steps)
+    s.stream.synchronize()
+    plain = time.perf_counter() - t0
+    s.close()
+    return {"workload": "128^3 FP64: ground state (dx=0.1, g=22, |dmu|<1e-8) then real time, g x 0.8, "
+                        f"{real_steps} steps with rms sizes every step",
+            "imag_steps": d.ground_steps, "imag_s": d.imag_seconds, "converged": d.converged,
+            "real_ms_per_step_observed": 1e3 * d.real_seconds / max(real_steps, 1),
+            "real_ms_per_step_plain": 1e3 * plain / max(real_steps, 1),
+            "rms_r_first_last": [float(d.table[0, -1]), float(d.table[-1, -1])]}
+
+
+def density_timing(reps: int = 5):
+    """The integrated densities of a 256^3 complex128 state (each reads the
+    state once): kernel time between events on the solver's stream."""
+    import numpy as np
+    import torch
+    from paper_1605_03958_amd import inputs, sscn
+    dx = 0.1
+    p = sscn.Problem(3, (256,) * 3, (dx,) * 3, (1.0, 1.5, 2.0), 80.0, 2e-4, sscn.REAL, sscn.F64, 0, 0)
+    s = sscn.Solver(p, inputs.ho_gaussian(3, p.n, p.dx, p.omega, noise=1e-3, seed=0).astype(np.complex128))
+    nbytes = p.points * 16
+    out = {}
+    for name, fn in (("1d", s.density_1d), ("2d", s.density_2d)):
+        for a in range(3):
+            fn(a)
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            ms = []
+            for _ in range(reps):
+                ev[0].record(s.stream)
+                fn(a)
+                ev[1].record(s.stream)
+                ev[1].synchronize()
+                ms.append(ev[0].elapsed_time(ev[1]))
+            t = float(np.median(ms))
+            out[f"{name}_axis{a}"] = {"ms": t, "gbs": nbytes / (t * 1e-3) / 1e9,
+                                     "hbm_frac": nbytes / (t * 1e-3) / (HBM_PEAK_GBS * 1e9)}
+    s.close()
+    return {"workload": "integrated densities of a 256^3 complex128 state (n_1D keeps axis a, n_2D drops it)",
+            **out}
+
+
 def mix64_problems():
     """The 64-instance uneven batch: 22 1D, 21 2D, 21 3D draws (seeds 100+i),
     imaginary time in FP32 with FP64 reductions, dt = 0.1 dx^2."""
@@ -389,6 +447,8 @@ def main():
     if args.only is None:
         res["ground64"] = ground64_timing()
         res["imag256"] = imag256_timing()
+        res["dynamics128"] = dynamics_timing()
+        res["densities256"] = density_timing()
     if args.only is None and not args.no_batch:
         res["batch"] = batch_mix64()
     if args.only is None and not args.no_serve:

@@ -17,6 +17,7 @@ rms_a = sqrt(<x_a^2>) per present axis and rms_r = sqrt(sum_a <x_a^2>).
 from __future__ import annotations
 
 import math
+import time
 from dataclasses import dataclass, replace
 
 import numpy as np
@@ -37,6 +38,8 @@ class Dynamics:
     converged: bool             # |delta mu| fell below mu_tol
     table: np.ndarray           # rows: t, rms per present axis, rms_r
     trace: list                 # the real-time observations, t = 0 first
+    imag_seconds: float = 0.0   # wall time of the imaginary-time run
+    real_seconds: float = 0.0   # wall time of the real-time run
 
 
 def ground_state_then_dynamics(prob: "sscn.Problem", psi0, g_factor: float, real_steps: int,
@@ -52,8 +55,10 @@ def ground_state_then_dynamics(prob: "sscn.Problem", psi0, g_factor: float, real
         raise ValueError("real_steps >= 0 and observe_every >= 1 are required")
     s = sscn.Solver(prob, psi0)
     try:
+        t0 = time.perf_counter()
         rc, imag_trace = s.run(max_imag_steps, mu_tol, trace_cap=max_imag_steps // max(prob.observe_every, 1) + 2)
         ground = s.observe()
+        t_imag = time.perf_counter() - t0
         psi_g = s.state()
     finally:
         s.close()
@@ -64,10 +69,12 @@ def ground_state_then_dynamics(prob: "sscn.Problem", psi0, g_factor: float, real
     r = sscn.Solver(rp, psi_g.astype(np.complex128))
     try:
         trace = [r.observe()]
+        t0 = time.perf_counter()
         if real_steps:
             _, rows = r.run(real_steps, 0.0, trace_cap=real_steps // observe_every + 2)
             trace += rows
+        t_real = time.perf_counter() - t0
     finally:
         r.close()
     table = np.array([(o.step * dt_real,) + rms_sizes(o, prob.dim) for o in trace])
-    return Dynamics(ground, ground.step, rc == sscn.OK, table, trace)
+    return Dynamics(ground, ground.step, rc == sscn.OK, table, trace, t_imag, t_real)
