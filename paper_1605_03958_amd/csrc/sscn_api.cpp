@@ -245,6 +245,21 @@ int make_plan(const sscn_problem &pb, const TileOverride *ov, Plan &P)
     off = align256(off + (size_t)P.np_norm * sizeof(double));
     P.off_obspart = off;
     off = align256(off + (size_t)P.obs_grid * 12 * sizeof(double));
+    // n_1D keeping x: partial sums over blocks of rows, one per (block, x);
+    // up to 1024 blocks and 256K doubles
+    {
+        const int64_t rows = P.npts / pb.n[0];
+        P.dens_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(rows, 1024),
+                                                                    (int64_t)262144 / pb.n[0]));
+    }
+    // and the x-line sums of n_1D keeping y or z, when there are at most
+    // 256K x lines
+    P.off_dens = off;
+    {
+        const int64_t rows = P.npts / pb.n[0];
+        const int64_t dn = std::max<int64_t>((int64_t)P.dens_blocks * pb.n[0], rows <= 262144 ? rows : 0);
+        off = align256(off + (size_t)dn * sizeof(double));
+    }
     P.ws_bytes = off;
     return SSCN_OK;
 }
@@ -840,7 +855,9 @@ int sscn_density_1d(sscn_solver *s, int keep, void *d_out)
     double w = 1.0;
     for (int a = 0; a < s->pb.dim; ++a)
         if (a != keep) w *= s->pb.dx[a];
-    return launch_density_1d(s->P.elem, s->psi, s->pb.n, keep, w, static_cast<double *>(d_out), s->st) ==
+    double *scratch = reinterpret_cast<double *>(s->ws + s->P.off_dens);
+    return launch_density_1d(s->P.elem, s->psi, s->pb.n, keep, w, static_cast<double *>(d_out), scratch,
+                             s->P.dens_blocks, s->st) ==
                    hipSuccess
                ? SSCN_OK
                : SSCN_E_HIP;

@@ -348,6 +348,79 @@ __global__ void __launch_bounds__(256) k_density_1d(const void *psi_, int nx, in
     if (threadIdx.x == 0) out[c] = w * s;
 }
 
+// n_1D keeping x, pass 1: block b sums |psi|^2 over its contiguous range of
+// rows (x lines) for each x, threads along x (coalesced), into
+// part[b * nx + x]
+template <class T, bool CPLX>
+__global__ void __launch_bounds__(256) k_density_x_rows(const void *psi_, int nx, long long rows, double *part)
+{
+    using A = Alg<T, CPLX>;
+    using V = typename A::V;
+    const V *psi = reinterpret_cast<const V *>(psi_);
+    const long long r0 = rows * blockIdx.x / gridDim.x, r1 = rows * (blockIdx.x + 1) / gridDim.x;
+    for (int x = threadIdx.x; x < nx; x += blockDim.x) {
+        double acc = 0.0;
+#pragma unroll 8
+        for (long long r = r0; r < r1; ++r) acc += A::norm2(psi[r * nx + x]);
+        part[(long long)blockIdx.x * nx + x] = acc;
+    }
+}
+
+// Sums of |psi|^2 along x lines, one wave per line: out[r] = w * sum_x.
+// These are n_2D without x (layout order of (y, z) is the line index) and
+// the first pass of n_1D keeping y or z.
+template <class T, bool CPLX>
+__global__ void __launch_bounds__(256) k_density_rows(const void *psi_, int nx, long long rows, double w, double *out)
+{
+    using A = Alg<T, CPLX>;
+    using V = typename A::V;
+    const long long r = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (r >= rows) return;  // a whole wave
+    const V *row = reinterpret_cast<const V *>(psi_) + r * nx;
+    double acc = 0.0;
+#pragma unroll 4
+    for (int x = lane; x < nx; x += 64) acc += A::norm2(row[x]);
+    acc = wave_sum(acc);
+    if (lane == 0) out[r] = w * acc;
+}
+
+// n_1D keeping y (keep = 1) or z (keep = 2) from the x-line sums rs
+// (index j + ny k): one wave per output, lanes over the other axis.
+__global__ void __launch_bounds__(256) k_density_rows_fin(const double *rs, int ny, int nz, int keep, double w,
+                                                          double *out)
+{
+    const int c = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int nc = keep == 1 ? ny : nz, no = keep == 1 ? nz : ny;
+    if (c >= nc) return;  // a whole wave
+    double acc = 0.0;
+    for (int o = lane; o < no; o += 64) acc += keep == 1 ? rs[c + (long long)ny * o] : rs[o + (long long)ny * c];
+    acc = wave_sum(acc);
+    if (lane == 0) out[c] = w * acc;
+}
+
+// pass 2: out[x] = w * sum_b part[b * nx + x].  A block covers 64 x; its 16
+// waves take consecutive ranges of b and are added in wave order.
+__global__ void __launch_bounds__(1024) k_density_x_fin(const double *part, int nx, int nb, double w, double *out)
+{
+    __shared__ double red[16][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int x = blockIdx.x * 64 + lane;
+    double acc = 0.0;
+    if (x < nx) {
+        const int b0 = (int)((long long)nb * wv / 16), b1 = (int)((long long)nb * (wv + 1) / 16);
+#pragma unroll 8
+        for (int b = b0; b < b1; ++b) acc += part[(long long)b * nx + x];
+    }
+    red[wv][lane] = acc;
+    __syncthreads();
+    if (wv == 0 && x < nx) {
+        double s = 0.0;
+        for (int q = 0; q < 16; ++q) s += red[q][lane];
+        out[x] = w * s;
+    }
+}
+
 template <class T, bool CPLX>
 __global__ void __launch_bounds__(256) k_density_2d(const void *psi_, int nx, int ny, int nz,
                                                     int drop, double w, double *out)
@@ -539,8 +612,36 @@ hipError_t launch_obs_final(const double *partial, int np, double dvol, double g
 }
 
 hipError_t launch_density_1d(int elem, const void *psi, const int32_t *n, int keep, double w, double *out,
-                             hipStream_t st)
+                             double *scratch, int dens_blocks, hipStream_t st)
 {
+    if (keep == 0) {
+        // x is the contiguous axis: partial sums over row blocks, then a
+        // fixed-order sum over the blocks
+        const long long rows = (long long)n[1] * n[2];
+#define DX_CASE(T, CP)                                                                                         \
+    hipLaunchKernelGGL((k_density_x_rows<T, CP>), dim3(dens_blocks), dim3(256), 0, st, psi, n[0], rows, scratch)
+        SSCN_ELEM_DISPATCH(elem, DX_CASE)
+#undef DX_CASE
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_density_x_fin, dim3((n[0] + 63) / 64), dim3(1024), 0, st, scratch, n[0], dens_blocks,
+                           w, out);
+        return hipGetLastError();
+    }
+    const long long rows = (long long)n[1] * n[2];
+    if (rows <= 262144) {
+        // x-line sums into the scratch, then a sum over the other axis
+#define DR_CASE(T, CP)                                                                                        \
+    hipLaunchKernelGGL((k_density_rows<T, CP>), dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st, psi, n[0], \
+                       rows, 1.0, scratch)
+        SSCN_ELEM_DISPATCH(elem, DR_CASE)
+#undef DR_CASE
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_density_rows_fin, dim3((n[keep] + 3) / 4), dim3(256), 0, st, scratch, n[1], n[2], keep,
+                           w, out);
+        return hipGetLastError();
+    }
 #define D1_CASE(T, CP) \
     hipLaunchKernelGGL((k_density_1d<T, CP>), dim3(n[keep]), dim3(256), 0, st, psi, n[0], n[1], n[2], keep, w, out)
     SSCN_ELEM_DISPATCH(elem, D1_CASE)
@@ -553,6 +654,15 @@ hipError_t launch_density_2d(int elem, const void *psi, const int32_t *n, int dr
 {
     const int u = (drop == 0) ? 1 : 0, v = (drop == 2) ? 1 : 2;
     const long long cnt = (long long)n[u] * n[v];
+    if (drop == 0) {
+        // the x-line sums themselves, in (y, z) layout order
+#define DR_CASE(T, CP)                                                                                          \
+    hipLaunchKernelGGL((k_density_rows<T, CP>), dim3((unsigned)((cnt + 3) / 4)), dim3(256), 0, st, psi, n[0], cnt, \
+                       w, out)
+        SSCN_ELEM_DISPATCH(elem, DR_CASE)
+#undef DR_CASE
+        return hipGetLastError();
+    }
     const int grid = (int)((cnt + 255) / 256);
 #define D2_CASE(T, CP) \
     hipLaunchKernelGGL((k_density_2d<T, CP>), dim3(grid), dim3(256), 0, st, psi, n[0], n[1], n[2], drop, w, out)

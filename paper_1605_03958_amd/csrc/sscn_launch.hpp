@@ -92,7 +92,7 @@ hipError_t launch_obs_final(const double *partial, int np, double dvol, double g
                             hipStream_t st);
 
 hipError_t launch_density_1d(int elem, const void *psi, const int32_t *n, int keep, double w,
-                             double *out, hipStream_t st);
+                             double *out, double *scratch, int dens_blocks, hipStream_t st);
 hipError_t launch_density_2d(int elem, const void *psi, const int32_t *n, int drop, double w,
                              double *out, hipStream_t st);
 

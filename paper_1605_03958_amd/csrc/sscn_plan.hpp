@@ -45,7 +45,8 @@ struct Plan {
     AxisPlan ax[3];
     bool sep_pointwise, sep_norm;
     int pw_grid, np_norm, obs_grid;
-    size_t off_scal, off_obs, off_part, off_obspart, ws_bytes;
+    int dens_blocks;       // row blocks of the n_1D-along-x partial sums
+    size_t off_scal, off_obs, off_part, off_obspart, off_dens, ws_bytes;
 };
 
 // Chunk lengths chosen by the tuner for one shape (0 = default choice).

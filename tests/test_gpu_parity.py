@@ -201,6 +201,20 @@ def test_quench_set_g():
     assert rel_l2(got, r2) <= 1e-12
 
 
+@pytest.mark.parametrize("dim,n,dx", [(1, (5000,), (0.01,)), (2, (300, 7), (0.05, 0.3)),
+                                      (3, (70, 9, 5), (0.2, 0.3, 0.4))])
+def test_density_along_x_matches_oracle(dim, n, dx):
+    """n_1D keeping x (partial sums over row blocks) in 1D, 2D and 3D,
+    line lengths above and below one block's threads."""
+    om = (1.0, 1.5, 2.0)[:dim]
+    p = Problem(dim, n, dx, om, 5.0, 0.1 * min(dx) ** 2, IMAG, F64, 1)
+    s = sscn.Solver(p, initial(p, 2))
+    s.step(3)
+    psi = s.state()
+    assert np.allclose(s.density_1d(0), oracle.density_1d(oprob(p), psi, 0), rtol=1e-12, atol=1e-14)
+    s.close()
+
+
 def test_densities_are_ordered_on_the_solver_stream():
     """The density outputs are made on the solver's own stream: with torch's
     current stream still busy, the results are the kernel's (an output
