@@ -186,7 +186,9 @@ int sscn_destroy(sscn_solver *s);
 /* Integrated densities (the paper's n_1D and n_2D outputs, integrating
  * |psi|^2 over the other axes): out is a caller-owned device buffer of
  * n[keep] doubles (1D) or of the two remaining axes' points in layout order
- * (2D, dim == 3 only).  Enqueued on the stream; FP64. */
+ * (2D, dim == 3 only).  Enqueued on the stream; FP64.  n_1D uses the
+ * solver's workspace as scratch (stream-ordered with the steps, so it may
+ * be called between sscn_step calls without a wait). */
 int sscn_density_1d(sscn_solver *s, int keep, void *d_out);
 int sscn_density_2d(sscn_solver *s, int drop, void *d_out);
 
