@@ -143,7 +143,12 @@ int sscn_observe(sscn_solver *s, sscn_obs *out);
  * were taken.  Rows of the observation trace go to trace[0..trace_cap) and
  * their count to *rows (either may be NULL/0).  Returns SSCN_OK on
  * convergence, SSCN_NOT_CONVERGED at the cap, SSCN_E_NONFINITE if the state
- * blew up.  Waits for the stream at every observation. */
+ * blew up (the trace ends at that row).  Waits for the stream at every
+ * observation, except with mu_tol == 0 (no convergence test, a fixed number
+ * of steps): then the observations are queued behind the steps without
+ * waits and read back once per 4096 of them, so after a blow-up the steps
+ * of the rest of that group have also been taken (the step count in the
+ * handle says how many).  Allocates pinned host memory for that mode. */
 int sscn_run(sscn_solver *s, int64_t max_steps, double mu_tol, sscn_obs *trace,
              int64_t trace_cap, int64_t *rows);
 

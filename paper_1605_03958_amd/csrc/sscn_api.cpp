@@ -754,9 +754,9 @@ int sscn_step_timed(sscn_solver *s, int64_t nsteps, double *ms)
     return rc;
 }
 
-int sscn_observe(sscn_solver *s, sscn_obs *out)
+// Enqueue the observation kernels; the 13 results land at *dobs (device).
+static hipError_t obs_enqueue(sscn_solver *s, double **dobs_out)
 {
-    if (!s || !out) return SSCN_E_INVALID;
     const Plan &P = s->P;
     ObsArgs oa;
     std::memset(&oa, 0, sizeof(oa));
@@ -773,13 +773,16 @@ int sscn_observe(sscn_solver *s, sscn_obs *out)
     oa.npts = P.npts;
     oa.partial = reinterpret_cast<double *>(s->ws + P.off_obspart);
     double *dobs = reinterpret_cast<double *>(s->ws + P.off_obs);
-    if (launch_obs_partials(P.elem, oa, P.obs_grid, 256, s->st) != hipSuccess) return SSCN_E_HIP;
-    if (launch_obs_final(oa.partial, P.obs_grid, dv, s->g, dobs, s->st) != hipSuccess) return SSCN_E_HIP;
-    if (hipMemcpyAsync(s->host_obs, dobs, 13 * sizeof(double), hipMemcpyDeviceToHost, s->st) != hipSuccess)
-        return SSCN_E_HIP;
-    if (hipStreamSynchronize(s->st) != hipSuccess) return SSCN_E_HIP;
-    const double *h = s->host_obs;
-    out->step = s->step;
+    hipError_t e = launch_obs_partials(P.elem, oa, P.obs_grid, 256, s->st);
+    if (e == hipSuccess) e = launch_obs_final(oa.partial, P.obs_grid, dv, s->g, dobs, s->st);
+    *dobs_out = dobs;
+    return e;
+}
+
+// An observation row from its 13 results (h) at global step `step`.
+static int obs_from_host(const double *h, int64_t step, sscn_obs *out)
+{
+    out->step = step;
     out->norm = h[0];
     out->mu = h[1];
     out->energy = h[2];
@@ -795,11 +798,76 @@ int sscn_observe(sscn_solver *s, sscn_obs *out)
     return out->status;
 }
 
+int sscn_observe(sscn_solver *s, sscn_obs *out)
+{
+    if (!s || !out) return SSCN_E_INVALID;
+    double *dobs = nullptr;
+    if (obs_enqueue(s, &dobs) != hipSuccess) return SSCN_E_HIP;
+    if (hipMemcpyAsync(s->host_obs, dobs, 13 * sizeof(double), hipMemcpyDeviceToHost, s->st) != hipSuccess)
+        return SSCN_E_HIP;
+    if (hipStreamSynchronize(s->st) != hipSuccess) return SSCN_E_HIP;
+    return obs_from_host(s->host_obs, s->step, out);
+}
+
+// sscn_run without a convergence test: observations are queued behind the
+// steps, their results copied into pinned host rows without waits, and read
+// back once per group of kRunGroup observations.
+constexpr int64_t kRunGroup = 4096;
+
+static int run_queued(sscn_solver *s, int64_t max_steps, sscn_obs *trace, int64_t trace_cap, int64_t *rows)
+{
+    const int64_t every = s->pb.observe_every;
+    double *stage = nullptr;
+    if (hipHostMalloc(reinterpret_cast<void **>(&stage), (size_t)kRunGroup * 13 * sizeof(double),
+                      hipHostMallocDefault) != hipSuccess)
+        return SSCN_E_HIP;
+    std::vector<int64_t> at((size_t)kRunGroup);
+    int64_t nrow = 0, done = 0;
+    int rc = SSCN_NOT_CONVERGED;
+    bool stop = false;
+    while (done < max_steps && !stop) {
+        int64_t nq = 0;
+        while (done < max_steps && nq < kRunGroup) {
+            int64_t k = every - (s->step % every);
+            if (k > max_steps - done) k = max_steps - done;
+            double *dobs = nullptr;
+            if (sscn_step(s, k) != SSCN_OK || obs_enqueue(s, &dobs) != hipSuccess ||
+                hipMemcpyAsync(stage + 13 * nq, dobs, 13 * sizeof(double), hipMemcpyDeviceToHost, s->st) !=
+                    hipSuccess) {
+                (void)hipStreamSynchronize(s->st);
+                (void)hipHostFree(stage);
+                return SSCN_E_HIP;
+            }
+            done += k;
+            at[(size_t)nq++] = s->step;
+        }
+        if (hipStreamSynchronize(s->st) != hipSuccess) {
+            (void)hipHostFree(stage);
+            return SSCN_E_HIP;
+        }
+        for (int64_t q = 0; q < nq; ++q) {
+            sscn_obs o;
+            const int r = obs_from_host(stage + 13 * q, at[(size_t)q], &o);
+            if (trace && nrow < trace_cap) trace[nrow] = o;
+            ++nrow;
+            if (r != SSCN_OK) {
+                rc = r;
+                stop = true;
+                break;
+            }
+        }
+    }
+    (void)hipHostFree(stage);
+    if (rows) *rows = std::min(nrow, trace_cap);
+    return rc;
+}
+
 int sscn_run(sscn_solver *s, int64_t max_steps, double mu_tol, sscn_obs *trace, int64_t trace_cap,
              int64_t *rows)
 {
     if (!s || max_steps < 0 || !(mu_tol >= 0.0) || s->pb.observe_every < 1) return SSCN_E_INVALID;
     if (trace_cap < 0 || (trace_cap > 0 && !trace)) return SSCN_E_INVALID;
+    if (mu_tol == 0.0) return run_queued(s, max_steps, trace, trace_cap, rows);
     const int64_t every = s->pb.observe_every;
     int64_t nrow = 0, done = 0;
     bool have_prev = false;

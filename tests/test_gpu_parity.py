@@ -258,6 +258,44 @@ def test_nonfinite_state_reported():
 
 
 @pytest.mark.parametrize("mode", [IMAG, REAL])
+def test_run_without_convergence_test_equals_observing_by_hand(mode):
+    """mu_tol = 0 queues the observations without waits; the rows are those
+    of stepping to each observation step and observing, bit for bit
+    (observe_every = 7 and a cap between observations)."""
+    p = Problem(3, (40, 36, 30), (0.25, 0.25, 0.3), (1.0, 1.5, 2.0), 10.0,
+                0.01 if mode == IMAG else 0.002, mode, F64, 1 if mode == IMAG else 0, 7)
+    psi0 = initial(p, 5)
+    a = sscn.Solver(p, psi0)
+    rc, rows = a.run(103, 0.0)
+    assert rc == sscn.NOT_CONVERGED
+    b = sscn.Solver(p, psi0)
+    want, done = [], 0
+    while done < 103:
+        k = min(7 - done % 7, 103 - done)
+        b.step(k)
+        done += k
+        want.append(b.observe())
+    assert [r.step for r in rows] == [w.step for w in want] == list(range(7, 103, 7)) + [103]
+    for r, w in zip(rows, want):
+        assert (r.norm, r.mu, r.energy, r.ekin, r.epot, r.eint, r.mean, r.msq, r.status) == \
+               (w.norm, w.mu, w.energy, w.ekin, w.epot, w.eint, w.mean, w.msq, w.status)
+    assert np.array_equal(a.state(), b.state())
+    a.close()
+    b.close()
+
+
+def test_run_without_convergence_test_ends_its_trace_at_a_blow_up():
+    p = Problem(1, (64, 1, 1), (0.2,), (1.0,), 1.0, 0.004, IMAG, F64, 1, 5)
+    psi0 = initial(p, 0)
+    psi0[0, 0, 10] = np.nan
+    s = sscn.Solver(p, psi0)
+    rc, rows = s.run(50, 0.0)
+    assert rc == sscn.E_NONFINITE
+    assert len(rows) == 1 and rows[0].step == 5 and rows[0].status == sscn.E_NONFINITE
+    s.close()
+
+
+@pytest.mark.parametrize("mode", [IMAG, REAL])
 @pytest.mark.parametrize("sigma", [0.3, 10.0, 300.0])
 def test_large_sigma_full_depth_scans(mode, sigma):
     """Large CN coefficients make |alpha| close to 1: the scans must then
