@@ -211,7 +211,10 @@ def dynamics_timing(real_steps: int = 500):
 
 def density_timing(reps: int = 5):
     """The integrated densities of a 256^3 complex128 state (each reads the
-    state once): kernel time between events on the solver's stream."""
+    state once): kernel time between events on the solver's stream around
+    the C-ABI call (output preallocated; no host work in between)."""
+    import ctypes
+
     import numpy as np
     import torch
     from paper_1605_03958_amd import inputs, sscn
@@ -219,15 +222,19 @@ def density_timing(reps: int = 5):
     p = sscn.Problem(3, (256,) * 3, (dx,) * 3, (1.0, 1.5, 2.0), 80.0, 2e-4, sscn.REAL, sscn.F64, 0, 0)
     s = sscn.Solver(p, inputs.ho_gaussian(3, p.n, p.dx, p.omega, noise=1e-3, seed=0).astype(np.complex128))
     nbytes = p.points * 16
+    L = sscn.lib()
+    with torch.cuda.stream(s.stream):
+        buf = torch.empty(p.n[0] * p.n[1], dtype=torch.float64, device="cuda")  # the largest output
     out = {}
-    for name, fn in (("1d", s.density_1d), ("2d", s.density_2d)):
+    for name, fn in (("1d", L.sscn_density_1d), ("2d", L.sscn_density_2d)):
         for a in range(3):
-            fn(a)
+            call = lambda: sscn._check(fn(s._h, a, ctypes.c_void_p(buf.data_ptr())), "density")
+            call()
             ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
             ms = []
             for _ in range(reps):
                 ev[0].record(s.stream)
-                fn(a)
+                call()
                 ev[1].record(s.stream)
                 ev[1].synchronize()
                 ms.append(ev[0].elapsed_time(ev[1]))

@@ -435,8 +435,13 @@ __global__ void __launch_bounds__(256) k_density_2d(const void *psi_, int nx, in
     const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= cnt) return;
     const long long iu = q % n3[u], iv = q / n3[u];
+    // threads along x read coalesced rows; the unrolled loop keeps several
+    // independent loads of the dropped axis in flight (sum order unchanged)
+    const V *p0 = psi + iu * sx[u] + iv * sx[v];
+    const long long sd = sx[drop];
     double acc = 0.0;
-    for (long long k = 0; k < n3[drop]; ++k) acc += A::norm2(psi[iu * sx[u] + iv * sx[v] + k * sx[drop]]);
+#pragma unroll 8
+    for (long long k = 0; k < n3[drop]; ++k) acc += A::norm2(p0[k * sd]);
     out[q] = w * acc;
 }
 
