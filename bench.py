@@ -372,8 +372,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp32", action="store_true")
-    ap.add_argument("--only", choices=["fp64", "fp32", "batch"], default=None,
-                    help="run only one precision, or only the batch (profiling runs)")
+    ap.add_argument("--only", choices=["fp64", "fp32", "batch", "densities", "dynamics"], default=None,
+                    help="run only one precision, the batch, the densities or the dynamics pipeline "
+                         "(profiling runs)")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance batch")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving loop")
     ap.add_argument("--serve-requests", type=int, default=512)
@@ -392,6 +393,12 @@ def main():
     torch.cuda.set_device(0)
     if args.only == "batch":
         print(json.dumps({"batch": batch_mix64()}), flush=True)
+        return
+    if args.only == "densities":
+        print(json.dumps({"densities256": density_timing()}), flush=True)
+        return
+    if args.only == "dynamics":
+        print(json.dumps({"dynamics128": dynamics_timing()}), flush=True)
         return
     out = {}
     precs = [sscn.F64, sscn.F32]
