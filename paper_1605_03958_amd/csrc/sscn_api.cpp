@@ -817,11 +817,16 @@ constexpr int64_t kRunGroup = 4096;
 static int run_queued(sscn_solver *s, int64_t max_steps, sscn_obs *trace, int64_t trace_cap, int64_t *rows)
 {
     const int64_t every = s->pb.observe_every;
+    std::vector<int64_t> at;
+    try {
+        at.resize((size_t)kRunGroup);
+    } catch (...) {
+        return SSCN_E_INVALID;
+    }
     double *stage = nullptr;
     if (hipHostMalloc(reinterpret_cast<void **>(&stage), (size_t)kRunGroup * 13 * sizeof(double),
                       hipHostMallocDefault) != hipSuccess)
         return SSCN_E_HIP;
-    std::vector<int64_t> at((size_t)kRunGroup);
     int64_t nrow = 0, done = 0;
     int rc = SSCN_NOT_CONVERGED;
     bool stop = false;
