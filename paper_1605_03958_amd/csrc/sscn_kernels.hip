@@ -297,12 +297,33 @@ __global__ void __launch_bounds__(256) k_obs_partials(ObsArgs a)
 __global__ void __launch_bounds__(256) k_obs_final(const double *partial, int np, double dvol,
                                                    double g, double *out)
 {
-    __shared__ double red[16];
-    double tot[SSCN_NOBS - 2];
-    for (int q = 0; q < SSCN_NOBS - 2; ++q) {
-        double acc = 0.0;
-        for (int i = threadIdx.x; i < np; i += blockDim.x) acc += partial[(size_t)i * SSCN_NOBS + q];
-        tot[q] = block_sum(acc, red);
+    constexpr int NQ = SSCN_NOBS - 2;
+    __shared__ double red[16][NQ];
+    // every quantity in one pass over the partial rows, then one barrier;
+    // the order of each sum is that of a block_sum per quantity
+    double acc[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+    for (int i = threadIdx.x; i < np; i += blockDim.x) {
+        const double *row = partial + (size_t)i * SSCN_NOBS;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) acc[q] += row[q];
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const double v = wave_sum(acc[q]);
+        if (lane == 0) red[wid][q] = v;
+    }
+    __syncthreads();
+    double tot[NQ];
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int q = 0; q < NQ; ++q) {
+            double s = 0.0;
+            for (int w = 0; w < nw; ++w) s += red[w][q];
+            tot[q] = s;
+        }
     }
     if (threadIdx.x == 0) {
         const double N = dvol * tot[0];
