@@ -215,6 +215,22 @@ def test_density_along_x_matches_oracle(dim, n, dx):
     s.close()
 
 
+@pytest.mark.parametrize("mode", [IMAG, REAL])
+def test_densities_of_fp32_states_match_oracle(mode):
+    """The density kernels over float and complex64 states (FP64 sums): the
+    oracle sums the same stored values in FP64."""
+    p = Problem(3, (70, 36, 30), (0.25, 0.25, 0.3), (1.0, 1.5, 2.0), 10.0,
+                0.01 if mode == IMAG else 0.002, mode, F32, 1 if mode == IMAG else 0)
+    s = sscn.Solver(p, initial(p, 3))
+    s.step(4)
+    psi = s.state().astype(np.complex128 if mode == REAL else np.float64)
+    op = oprob(p)
+    for a in range(3):
+        assert np.allclose(s.density_1d(a), oracle.density_1d(op, psi, a), rtol=1e-12, atol=1e-14)
+        assert np.allclose(s.density_2d(a), oracle.density_2d(op, psi, a), rtol=1e-12, atol=1e-14)
+    s.close()
+
+
 def test_densities_are_ordered_on_the_solver_stream():
     """The density outputs are made on the solver's own stream: with torch's
     current stream still busy, the results are the kernel's (an output
