@@ -255,7 +255,7 @@ class Server:
                 for e in todo:
                     self._admit(e)
                 if not self._running:
-                    # every admission of this round failed (their futures
+                    # every admission of this pass failed (their futures
                     # hold the errors): look at the queue again
                     continue
                 self.ex.step(self.tick)
