@@ -231,6 +231,20 @@ def test_densities_of_fp32_states_match_oracle(mode):
     s.close()
 
 
+def test_densities_with_more_x_lines_than_the_scratch_holds():
+    """More than 256K x lines: n_1D keeping y or z takes the per-output
+    kernel instead of the x-line sums (no scratch for them)."""
+    p = Problem(3, (2, 600, 600), (0.3, 0.05, 0.05), (1.0, 1.5, 2.0), 5.0, 2.5e-4, IMAG, F64, 1)
+    s = sscn.Solver(p, initial(p, 6))
+    s.step(2)
+    psi = s.state()
+    op = oprob(p)
+    for a in range(3):
+        assert np.allclose(s.density_1d(a), oracle.density_1d(op, psi, a), rtol=1e-12, atol=1e-14)
+        assert np.allclose(s.density_2d(a), oracle.density_2d(op, psi, a), rtol=1e-12, atol=1e-14)
+    s.close()
+
+
 def test_densities_are_ordered_on_the_solver_stream():
     """The density outputs are made on the solver's own stream: with torch's
     current stream still busy, the results are the kernel's (an output
