@@ -356,6 +356,23 @@ __device__ __forceinline__ LTab<T, CPLX> row_tab(const EdgeTab<T, CPLX> *tb, int
 // so the results are theirs bit for bit.  Runs `steps` steps, fewer if the
 // instance stops or (target >= 0) once the persistent launches that run
 // beside it have all finished (BCtl::reg_epoch reaches target).
+// block_sum without its leading barrier.  In the solo step loop the last
+// reads of red (thread 0, in the previous step) come before that step's
+// closing barrier, which every wave passes before it writes red again.
+__device__ __forceinline__ double block_sum_after_barrier(double v, double *red)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    v = wave_sum(v);
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int w = 0; w < nw; ++w) s += red[w];
+    }
+    return s;
+}
+
 template <class T, bool CPLX, int C, bool MW>
 __device__ void solo_run(const BInst &I, BState &S, BState &sS, int steps, int target, BCtl *ctl,
                          unsigned char *lds, double *red, double (*redq)[16], int *s_go)
@@ -434,7 +451,7 @@ __device__ void solo_run(const BInst &I, BState &S, BState &sS, int steps, int t
             nacc = row_solve<T, CPLX, C, MW>(psi, 0, active, n, static_cast<const LTab<T, CPLX> *>(etab), G, t, lane,
                                              wl, X.wpl, xs, sig, scale, T(pp.dt), T(pp.g), pp, X.lt.depth, true, u,
                                              true);
-        const double nraw = block_sum(nacc, red);
+        const double nraw = block_sum_after_barrier(nacc, red);
         if (obs_now) {
             // the observation item's own sums over the stored line, so the
             // observables are those of the split items bit for bit
