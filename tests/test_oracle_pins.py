@@ -224,6 +224,36 @@ def test_thomas_fermi_limit_1d():
     assert errs[2] < 1e-3
 
 
+@pytest.mark.parametrize("dim,gs,dx,dt,tol", [
+    (1, (10.0, 100.0, 1000.0), 0.05, 0.0025, 3e-4),
+    (2, (30.0, 300.0, 3000.0), 0.1, 0.005, 3e-3),
+    (3, (30.0, 300.0, 3000.0), 0.2, 0.01, 1.5e-2),
+])
+def test_thomas_fermi_energy_to_mu_ratio(dim, gs, dx, dt, tol):
+    """In the Thomas-Fermi limit (kinetic energy negligible, density
+    (mu - V)/g inside the cloud) the energy per particle and the chemical
+    potential of a d-dimensional harmonic trap stand in the ratio
+    E/mu = (d + 2)/(d + 4).  The converged ground state approaches it as g
+    grows; the error must fall with g and be below tol at the largest g.
+    This fixes the interaction term's weight in E (half of mu's)."""
+    om = (1.0, 1.3, 1.6)[:dim]
+    want = (dim + 2) / (dim + 4)
+    errs = []
+    for g in gs:
+        mu_tf = inputs.mu_thomas_fermi(dim, g, om)
+        n = [int(round(2 * (math.sqrt(2 * mu_tf) / w + 3.0 / math.sqrt(w)) / dx)) for w in om]
+        n = tuple(n + [1] * (3 - dim))
+        dxs = tuple([dx] * dim + [1.0] * (3 - dim))
+        oms = tuple(list(om) + [0.0] * (3 - dim))
+        psi0 = inputs.thomas_fermi(dim, n, dxs, oms, g).real
+        steps = int(round((4.0 if dim == 1 else 3.0) / dt))
+        _, r = _ground_state(dim, n, dxs, oms, g, dt, steps, psi0)
+        mu, E = r.trace[-1, 2], r.trace[-1, 3]
+        errs.append(abs(E / mu - want))
+    assert errs[0] > errs[1] > errs[2], errs
+    assert errs[2] < tol, errs
+
+
 def test_virial_2d():
     """Converged 2D ground state at g > 0: 2K - 2P + d g I / 2 = 0 up to
     O(dx^2), falling ~4x when dx halves."""
@@ -337,6 +367,31 @@ def test_integrated_densities_of_product_gaussian():
     d2 = oracle.density_2d(prob, psi, 2)
     assert d2.shape == (n[1], n[0])
     assert np.allclose(np.sum(d2, axis=0) * dx[1], oracle.density_1d(prob, psi, 0), atol=1e-13)
+
+
+@pytest.mark.parametrize("drop", [0, 1, 2])
+def test_integrated_2d_density_of_shifted_product_gaussian(drop):
+    """n_2D with one axis integrated out of a displaced product Gaussian is
+    the product of the two kept axes' 1D Gaussian densities, laid out with
+    the lower kept axis fastest.  Unequal sizes and displacements per axis
+    make a transposed or mirrored output fail."""
+    om = (1.0, 1.5, 2.0)
+    dx = (0.1, 0.09, 0.08)
+    shift = (0.3, -0.2, 0.25)
+    n = tuple(int(round(16 / math.sqrt(w) / h)) for w, h in zip(om, dx))
+    psi = inputs.ho_gaussian(3, n, dx, om, noise=0.0, shift=shift)
+    prob = Problem(3, n, dx, om, 0.0, 0.01, IMAG, 1)
+    keep = [a for a in range(3) if a != drop]
+    u, v = keep
+    d2 = oracle.density_2d(prob, psi, drop)
+    assert d2.shape == (n[v], n[u])
+
+    def dens(a):
+        x = inputs.coords(n[a], dx[a]) - shift[a]
+        return math.sqrt(om[a] / math.pi) * np.exp(-om[a] * x * x)
+
+    ref = dens(v)[:, None] * dens(u)[None, :]
+    assert np.max(np.abs(d2 - ref)) < 1e-10 * np.max(ref)
 
 
 def test_quench_to_a_free_gas_breathes_with_period_pi_over_omega():
