@@ -74,6 +74,17 @@ class Problem:
 
 
 _lib = None
+_lib_path = LIB_PATH
+
+
+def use_library(path: str) -> str:
+    """Load later calls from the oracle library at `path` (the benchmark's
+    host-tuned copy of the same source); returns the previous path."""
+    global _lib, _lib_path
+    prev = _lib_path
+    _lib_path = path
+    _lib = None
+    return prev
 
 
 def load():
@@ -81,9 +92,9 @@ def load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(LIB_PATH):
-        raise RuntimeError(f"oracle library missing: {LIB_PATH}; run oracle.build.build()")
-    lib = ctypes.CDLL(LIB_PATH)
+    if not os.path.exists(_lib_path):
+        raise RuntimeError(f"oracle library missing: {_lib_path}; run oracle.build.build()")
+    lib = ctypes.CDLL(_lib_path)
     dp = ctypes.POINTER(ctypes.c_double)
     pp = ctypes.POINTER(_Problem)
     lib.orc_thomas.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, dp, dp]
@@ -95,10 +106,11 @@ def load():
                             ctypes.c_double, dp, ctypes.c_long,
                             ctypes.POINTER(ctypes.c_long), ctypes.POINTER(ctypes.c_long)]
     lib.orc_threads.argtypes = []
+    lib.orc_set_threads.argtypes = [ctypes.c_int]
     lib.orc_density_1d.argtypes = [pp, dp, ctypes.c_int, dp]
     lib.orc_density_2d.argtypes = [pp, dp, ctypes.c_int, dp]
     for f in (lib.orc_thomas, lib.orc_cn_line, lib.orc_observe, lib.orc_potential,
-              lib.orc_substep, lib.orc_run, lib.orc_threads, lib.orc_density_1d,
+              lib.orc_substep, lib.orc_run, lib.orc_threads, lib.orc_set_threads, lib.orc_density_1d,
               lib.orc_density_2d):
         f.restype = ctypes.c_int
     _lib = lib
@@ -228,3 +240,8 @@ def density_2d(prob: Problem, psi, drop: int) -> np.ndarray:
 
 def threads() -> int:
     return int(load().orc_threads())
+
+
+def set_threads(n: int) -> None:
+    if load().orc_set_threads(int(n)):
+        raise ValueError(f"orc_set_threads({n})")

@@ -440,6 +440,17 @@ int orc_threads(void)
 #endif
 }
 
+/* Thread count of later parallel regions (the CPU baseline times one core
+ * and all cores); n < 1 is rejected. */
+int orc_set_threads(int n)
+{
+    if (n < 1) return -1;
+#ifdef _OPENMP
+    omp_set_num_threads(n);
+#endif
+    return 0;
+}
+
 /* Integrated densities (the paper's n_1D and n_2D outputs): integrate
  * |psi|^2 dV over every axis except `keep` (out has n[keep] entries), or over
  * the single axis `drop` (out has the points of the remaining two axes in
