@@ -96,13 +96,22 @@ typedef struct {
 
 typedef struct sscn_solver sscn_solver;
 
-/* SSCN_ABI_VERSION of the loaded library. */
+/* Calls that carry no operation of the paper (version, status text, sizes,
+ * timing, tile hints, plan queries, batching and its admission) are marked
+ * "systems call" below: they serve the measurement, the autotuner and the
+ * batched serving loop built around the method.  Every other call cites the
+ * passage of the paper's program summary that defines what it computes. */
+
+/* Systems call: SSCN_ABI_VERSION of the loaded library. */
 int sscn_abi_version(void);
 
-/* Static text for a status code (never NULL). */
+/* Systems call: static text for a status code (never NULL). */
 const char *sscn_status_string(int status);
 
-/* Host-only check of a problem (no GPU access).  SSCN_E_INVALID if dim is
+/* Host-only check of a problem (no GPU access).  The problem is the one of
+ * "Nature of problem": the GP equation in one, two or three dimensions in a
+ * harmonic trap, given by its grid, trap frequencies, nonlinearity, time step
+ * and imaginary/real-time mode.  SSCN_E_INVALID if dim is
  * not 1..3, an n_a < 1, n_a != 1 on an unused axis, dx_a <= 0 or non-finite
  * on a used axis, omega < 0 or non-finite, g non-finite, dt <= 0 or
  * non-finite, mode/prec out of range, renorm_every < 1 in IMAG or != 0 in
@@ -110,13 +119,15 @@ const char *sscn_status_string(int status);
  * build's limits (more than 2^40 points). */
 int sscn_validate(const sscn_problem *pb);
 
-/* Bytes of the caller-owned state (points * element size) and workspace.
+/* Systems call (admission by HBM footprint).
+ * Bytes of the caller-owned state (points * element size) and workspace.
  * The workspace holds the FP64 Thomas tables, reduction partials and device
  * scalars; the two sums are what a solve keeps resident in HBM. */
 int sscn_state_bytes(const sscn_problem *pb, size_t *bytes);
 int sscn_workspace_bytes(const sscn_problem *pb, size_t *bytes);
 
-/* Bind a solver to caller memory: d_psi (state, layout above, at least
+/* "Solution method" (discretisation in space and time): bind a solver to
+ * caller memory: d_psi (state, layout above, at least
  * sscn_state_bytes), d_ws (workspace, at least sscn_workspace_bytes, 256-byte
  * aligned), hip_stream.  Precomputes the FP64 Thomas tables of every axis on
  * the host and uploads them to d_ws on the stream (the call waits for that
@@ -125,20 +136,34 @@ int sscn_workspace_bytes(const sscn_problem *pb, size_t *bytes);
 int sscn_create(const sscn_problem *pb, void *d_psi, void *d_ws, void *hip_stream,
                 sscn_solver **out);
 
-/* Enqueue nsteps >= 0 SSCN steps on the stream and return.  When the stream
- * reaches the end of the call the state is complete: in imaginary time it is
- * renormalised if the last step was a renormalisation step.  On a stream
- * other than the legacy default stream, runs of 32 steps are replayed from
- * hipGraphs captured on first use (one per renormalisation phase; dropped
- * by sscn_set_g and sscn_destroy); the kernels and results are those of
- * direct launches. */
+/* "Solution method" (propagation in imaginary or real time over small time
+ * steps): enqueue nsteps >= 0 SSCN steps on the stream and return.  When the
+ * stream reaches the end of the call the state is complete: in imaginary
+ * time it is renormalised if the last step was a renormalisation step.  On a
+ * stream other than the legacy default stream the call replays hipGraphs of
+ * 32, 16, 8, 4, 2 and 1 steps (the binary decomposition of nsteps), each
+ * captured on first use and kept per (length, renormalisation pattern);
+ * sscn_set_g and sscn_destroy drop them.  The kernels and results are those
+ * of direct launches. */
 int sscn_step(sscn_solver *s, int64_t nsteps);
 
-/* Observables of the current state; waits for the stream.  Returns
- * SSCN_E_NONFINITE (and fills out) if the norm or mu is NaN or Inf. */
+/* Systems call: capture now, without launching anything, the graphs that a
+ * following sscn_step(s, nsteps) from the current step will replay, so that
+ * call does no capture of its own (a timed region, a latency-bound loop).
+ * Never required: sscn_step captures what is missing. */
+int sscn_prepare(sscn_solver *s, int64_t nsteps);
+
+/* "Summary of revisions" (the general output file holds the energy and the
+ * chemical potential; the dynamics files hold rms sizes): observables of the
+ * current state, with the moments <x_a>, <x_a^2> from which the rms sizes
+ * follow; waits for the stream.  Returns SSCN_E_NONFINITE (and fills out) if
+ * the norm or mu is NaN or Inf. */
 int sscn_observe(sscn_solver *s, sscn_obs *out);
 
-/* Propagate until |mu(t) - mu(t - observe_every)| < mu_tol at an observation
+/* "Solution method" and "Summary of revisions" (imaginary-time iterations
+ * that yield the stationary state, with its energy and chemical potential
+ * written out; real-time iterations with the rms sizes written per time):
+ * propagate until |mu(t) - mu(t - observe_every)| < mu_tol at an observation
  * step (observe_every from the problem, >= 1), or until max_steps more steps
  * were taken.  Rows of the observation trace go to trace[0..trace_cap) and
  * their count to *rows (either may be NULL/0).  Returns SSCN_OK on
@@ -152,11 +177,14 @@ int sscn_observe(sscn_solver *s, sscn_obs *out);
 int sscn_run(sscn_solver *s, int64_t max_steps, double mu_tol, sscn_obs *trace,
              int64_t trace_cap, int64_t *rows);
 
-/* Change the nonlinearity for later steps and observables (a quench).
- * SSCN_E_INVALID if g is not finite. */
+/* "Summary of revisions" (the dynamics is generated by multiplying the
+ * nonlinearity by a given factor during the real-time iterations, starting
+ * from the imaginary-time state): change the nonlinearity for later steps
+ * and observables (a quench).  SSCN_E_INVALID if g is not finite. */
 int sscn_set_g(sscn_solver *s, double g);
 
-/* Enqueue nsteps steps exactly as sscn_step does, with HIP events recorded
+/* Systems call (measurement).
+ * Enqueue nsteps steps exactly as sscn_step does, with HIP events recorded
  * around every kernel, wait, and report the mean duration in milliseconds of
  * each kernel class over the steps in ms[0..SSCN_NKERNELS).  Classes: 0 the
  * pointwise + x sweep, 1 the y sweep, 2 the z sweep (+ norm partials),
@@ -166,7 +194,8 @@ int sscn_set_g(sscn_solver *s, double g);
 #define SSCN_NKERNELS 5
 int sscn_step_timed(sscn_solver *s, int64_t nsteps, double *ms);
 
-/* Tile hints (used by the tuner): for problems of pb's shape (dim, n, mode,
+/* Systems call (autotuner).
+ * Tile hints (used by the tuner): for problems of pb's shape (dim, n, mode,
  * prec), use chunk[0] points per thread on x lines and chunk[1], chunk[2] on
  * y and z lines (powers of two <= 64; 0 keeps the default).  Applies to later
  * sscn_workspace_bytes / sscn_create calls of that shape, process-wide.
@@ -175,7 +204,8 @@ int sscn_step_timed(sscn_solver *s, int64_t nsteps, double *ms);
 int sscn_set_tile_hint(const sscn_problem *pb, const int32_t chunk[3]);
 int sscn_clear_tile_hints(void);
 
-/* Kernel plan of a problem, 8 ints per axis (x, y, z): kind (0 ROW: lanes
+/* Systems call (autotuner, tests).
+ * Kernel plan of a problem, 8 ints per axis (x, y, z): kind (0 ROW: lanes
  * along the line, 1 COL: lanes across lines, 2 one-thread-per-line
  * fallback, -1 unused axis), points per thread, waves per line group (ROW)
  * or per block (COL), lanes per line (COL; 1 otherwise), grid size, block
@@ -184,7 +214,8 @@ int sscn_clear_tile_hints(void);
  * cap >= 24 entries. */
 int sscn_plan_info(const sscn_problem *pb, int32_t *info, int32_t cap);
 
-/* Free the handle's host state (the caller's device memory is untouched).
+/* Systems call: free the handle's host state (the caller's device memory is
+ * untouched).
  * Waits for the stream. */
 int sscn_destroy(sscn_solver *s);
 
@@ -199,6 +230,11 @@ int sscn_density_2d(sscn_solver *s, int drop, void *d_out);
 
 /* ------------------------------------------------------------------------
  * Batched persistent stepping (many uneven instances, FP32 forms).
+ *
+ * Systems calls (batching): each instance is the problem of "Nature of
+ * problem" propagated by the method of "Solution method" in imaginary or
+ * real time, exactly as sscn_step would; what these calls add is many
+ * instances per launch.
  *
  * A batch advances every running instance by one SSCN step per launch of a
  * persistent kernel whose blocks take tiles of all instances from a work

@@ -322,8 +322,8 @@ struct sscn_solver {
     int64_t step;
     double g;
     double host_obs[16];
-    // captured runs of kGraphSteps steps, keyed by the renormalisation phase
-    // (step mod renorm_every) they start at; their kernel arguments hold g
+    // captured runs of 2^lg steps (lg <= kGraphLog), keyed by lg and by
+    // which of their steps renormalise; their kernel arguments hold g
     std::map<int64_t, hipGraphExec_t> graphs;
     bool graphs_off;          // capture failed once on this stream: launch directly
 };
@@ -477,20 +477,42 @@ static hipError_t enqueue_step(sscn_solver *s, bool do_renorm, Timer *tm)
     return hipSuccess;
 }
 
-// Steps per captured graph.  Small problems are bound by launch overhead
-// (four kernels of a few microseconds per step); a graph replay issues a
-// run of steps with one call.  The replayed kernels and arguments are those
-// the direct path would launch, so results are the same.
-constexpr int64_t kGraphSteps = 32;
+// Captured graphs.  Small problems are bound by launch overhead (four
+// kernels of a few microseconds per step); a graph replay issues a run of
+// steps with one call.  A call of n steps replays the graphs of its binary
+// decomposition into runs of 32, 16, ..., 1 steps, so every length is
+// replayed, not only multiples of 32.  The replayed kernels and arguments are
+// those the direct path would launch, so results are the same.
+constexpr int kGraphLog = 5;                 // longest run: 32 steps
+constexpr size_t kMaxGraphs = 192;           // renormalisation patterns x lengths
 
-static hipError_t capture_run(sscn_solver *s, hipGraphExec_t *out)
+// A run's graph is fixed by its length and by which of its steps
+// renormalise: bit k-1 of the mask is set when step after+k does.
+static int64_t graph_key(const sscn_solver *s, int64_t after_step, int lg)
+{
+    int64_t mask = 0;
+    if (s->pb.mode == SSCN_IMAG)
+        for (int64_t k = 1; k <= (int64_t(1) << lg); ++k)
+            if ((after_step + k) % s->pb.renorm_every == 0) mask |= int64_t(1) << (k - 1);
+    return mask * 8 + lg;
+}
+
+// Length exponent of the next graph run for `left` steps.
+static int run_log(int64_t left)
+{
+    int lg = 0;
+    while (lg < kGraphLog && (int64_t(2) << lg) <= left) ++lg;
+    return lg;
+}
+
+static hipError_t capture_run(sscn_solver *s, int64_t after_step, int lg, hipGraphExec_t *out)
 {
     const bool imag = s->pb.mode == SSCN_IMAG;
     hipError_t e = hipStreamBeginCapture(s->st, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return e;
     hipError_t le = hipSuccess;
-    for (int64_t k = 1; k <= kGraphSteps && le == hipSuccess; ++k) {
-        const int64_t step = s->step + k;
+    for (int64_t k = 1; k <= (int64_t(1) << lg) && le == hipSuccess; ++k) {
+        const int64_t step = after_step + k;
         le = enqueue_step(s, imag && (step % s->pb.renorm_every == 0), nullptr);
     }
     hipGraph_t g = nullptr;
@@ -504,29 +526,58 @@ static hipError_t capture_run(sscn_solver *s, hipGraphExec_t *out)
     return e;
 }
 
+// The graph for a run of 2^lg steps after step `after_step`, captured on
+// first use; nullptr when graphs are off for this solver.
+static hipGraphExec_t graph_for(sscn_solver *s, int64_t after_step, int lg)
+{
+    if (s->st == nullptr || s->graphs_off) return nullptr;   // the legacy default stream cannot be captured
+    const int64_t key = graph_key(s, after_step, lg);
+    auto it = s->graphs.find(key);
+    if (it != s->graphs.end()) return it->second;
+    if (s->graphs.size() >= kMaxGraphs) drop_graphs(s);
+    hipGraphExec_t ex = nullptr;
+    if (capture_run(s, after_step, lg, &ex) != hipSuccess) {
+        (void)hipGetLastError();
+        s->graphs_off = true;
+        return nullptr;
+    }
+    try {
+        s->graphs.emplace(key, ex);
+    } catch (...) {
+        (void)hipGraphExecDestroy(ex);
+        return nullptr;
+    }
+    return ex;
+}
+
+// Capture, without launching anything, every graph a later call of nsteps
+// steps from the current step will replay.
+static void prepare_graphs(sscn_solver *s, int64_t nsteps)
+{
+    int64_t step = s->step;
+    while (nsteps > 0) {
+        const int lg = run_log(nsteps);
+        if (!graph_for(s, step, lg)) return;
+        step += int64_t(1) << lg;
+        nsteps -= int64_t(1) << lg;
+    }
+}
+
 static hipError_t enqueue_steps(sscn_solver *s, int64_t nsteps, Timer *tm)
 {
     if (nsteps <= 0) return hipSuccess;
     const bool imag = s->pb.mode == SSCN_IMAG;
     bool last_renorm = false;
-    // whole runs of kGraphSteps from captured graphs (not on the legacy
-    // default stream, which cannot be captured, and not when timing)
-    while (!tm && s->st != nullptr && !s->graphs_off && nsteps >= kGraphSteps) {
-        const int64_t phase = imag ? s->step % s->pb.renorm_every : 0;
-        auto it = s->graphs.find(phase);
-        if (it == s->graphs.end()) {
-            hipGraphExec_t ex = nullptr;
-            if (capture_run(s, &ex) != hipSuccess) {
-                (void)hipGetLastError();
-                s->graphs_off = true;
-                break;
-            }
-            it = s->graphs.emplace(phase, ex).first;
-        }
-        hipError_t e = hipGraphLaunch(it->second, s->st);
+    // graph runs (not when timing: the timed path launches each kernel with
+    // its own events)
+    while (!tm && nsteps > 0) {
+        const int lg = run_log(nsteps);
+        hipGraphExec_t ex = graph_for(s, s->step, lg);
+        if (!ex) break;
+        hipError_t e = hipGraphLaunch(ex, s->st);
         if (e != hipSuccess) return e;
-        s->step += kGraphSteps;
-        nsteps -= kGraphSteps;
+        s->step += int64_t(1) << lg;
+        nsteps -= int64_t(1) << lg;
         last_renorm = imag && (s->step % s->pb.renorm_every == 0);
     }
     for (int64_t t = 0; t < nsteps; ++t) {
@@ -714,6 +765,13 @@ int sscn_step(sscn_solver *s, int64_t nsteps)
 {
     if (!s || nsteps < 0) return SSCN_E_INVALID;
     return enqueue_steps(s, nsteps, nullptr) == hipSuccess ? SSCN_OK : SSCN_E_HIP;
+}
+
+int sscn_prepare(sscn_solver *s, int64_t nsteps)
+{
+    if (!s || nsteps < 0) return SSCN_E_INVALID;
+    prepare_graphs(s, nsteps);
+    return SSCN_OK;
 }
 
 int sscn_step_timed(sscn_solver *s, int64_t nsteps, double *ms)

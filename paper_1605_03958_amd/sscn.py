@@ -83,6 +83,7 @@ EXPORTS = {
     "sscn_create": ([ctypes.POINTER(CProblem), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                      ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
     "sscn_step": ([ctypes.c_void_p, ctypes.c_int64], ctypes.c_int),
+    "sscn_prepare": ([ctypes.c_void_p, ctypes.c_int64], ctypes.c_int),
     "sscn_observe": ([ctypes.c_void_p, ctypes.POINTER(CObs)], ctypes.c_int),
     "sscn_run": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.POINTER(CObs),
                   ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
@@ -319,6 +320,10 @@ class Solver:
     # -- propagation ---------------------------------------------------------
     def step(self, nsteps: int) -> None:
         _check(lib().sscn_step(self._h, int(nsteps)), "sscn_step")
+
+    def prepare(self, nsteps: int) -> None:
+        """Capture the graphs a following step(nsteps) replays (no launch)."""
+        _check(lib().sscn_prepare(self._h, int(nsteps)), "sscn_prepare")
 
     def step_timed(self, nsteps: int):
         ms = (ctypes.c_double * NKERNELS)()
