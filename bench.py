@@ -69,8 +69,12 @@ def load_traffic(kernel_class: str, workload: str):
 
 
 def time_steps(solver, steps, warmup):
+    """Wall time of `steps` steps after `warmup` untimed ones.  The graphs the
+    timed call replays are captured before the timed region (sscn_prepare),
+    so the region holds only their replays."""
     import torch
     solver.step(warmup)
+    solver.prepare(steps)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     solver.step(steps)
@@ -97,18 +101,20 @@ def copy_bandwidth(nbytes: int, reps: int = 20):
     return 2 * nbytes / dt / 1e9
 
 
-def cpu_baseline(target_s: float = 12.0):
-    """The FP64 oracle on a bounded sample of the same workload: the full
-    256^3 grid, one untimed step (thread start-up, first touch), then runs of
-    steps until about target_s seconds have been timed."""
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            return next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        return ""
+
+
+def _oracle_rate(op, psi, target_s: float, first_step: int = 2):
+    """Oracle grid-point-steps/s over runs of steps until about target_s
+    seconds have been timed (after the caller's untimed first step)."""
     import oracle
-    from paper_1605_03958_amd import inputs
-    p = cube256_problem(0)
-    op = oracle.Problem(p.dim, p.n, p.dx, p.omega, p.g, p.dt, p.mode, p.renorm_every)
-    psi = inputs.thomas_fermi(3, p.n, p.dx, p.omega, 100.0, phase_sigma=0.05, seed=1)
-    psi = oracle.run(op, psi, 1).psi
-    step, steps, el = 2, 0, 0.0
-    chunk = 2
+    step, steps, el = first_step, 0, 0.0
+    chunk = 1
     while el < target_s:
         t0 = time.perf_counter()
         psi = oracle.run(op, psi, chunk, first_step=step).psi
@@ -117,16 +123,54 @@ def cpu_baseline(target_s: float = 12.0):
         steps += chunk
         step += chunk
         chunk = max(1, min(50, int(0.25 * target_s * chunk / max(dt, 1e-3))))
-    model = ""
-    try:
-        with open("/proc/cpuinfo") as f:
-            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
-    except OSError:
-        pass
-    return {"value": p.points * steps / el, "unit": "grid-point-steps/s", "cores": oracle.threads(),
-            "kind": "oracle", "cpu": model,
-            "sample": f"256^3 complex128 real-time workload, steps 2-{step - 1} ({steps} steps, {el:.1f} s "
-                      f"timed after one untimed step), FP64 C oracle with OpenMP over lines"}
+    pts = op.n[0] * op.n[1] * op.n[2]
+    return pts * steps / el, steps, el, step - 1
+
+
+def cpu_baseline(target_s: float = 8.0):
+    """The FP64 oracle, built for this host (-O3 -march=native) and timed on
+    bounded samples: the 256^3 real-time workload on every core the process
+    may use and on one core, and the 64^3 ground-state workload on every
+    core.  Each sample runs one untimed step (thread start-up, first touch),
+    then runs of steps until about target_s seconds have been timed."""
+    import tempfile
+
+    import oracle
+    from oracle.build import build as build_oracle
+    from paper_1605_03958_amd import inputs
+    affinity = len(os.sched_getaffinity(0))
+    env_threads = os.environ.get("OMP_NUM_THREADS", "")
+    threads = min(affinity, int(env_threads)) if env_threads.isdigit() and int(env_threads) > 0 else affinity
+    with tempfile.TemporaryDirectory() as tmp:
+        lib_path = build_oracle(native=True, out=os.path.join(tmp, "liboracle_native.so"))
+        prev = oracle.use_library(lib_path)
+        try:
+            p = cube256_problem(0)
+            op = oracle.Problem(p.dim, p.n, p.dx, p.omega, p.g, p.dt, p.mode, p.renorm_every)
+            psi0 = inputs.thomas_fermi(3, p.n, p.dx, p.omega, 100.0, phase_sigma=0.05, seed=1)
+            oracle.set_threads(threads)
+            used = oracle.threads()
+            psi = oracle.run(op, psi0, 1).psi
+            rate_all, n_all, el_all, last_all = _oracle_rate(op, psi, target_s)
+            oracle.set_threads(1)
+            psi = oracle.run(op, psi0, 1).psi
+            rate_one, n_one, el_one, last_one = _oracle_rate(op, psi, target_s)
+            oracle.set_threads(threads)
+            dx = 0.2
+            c0 = oracle.Problem(3, (64, 64, 64), (dx,) * 3, (1.0, 1.5, 2.0), 22.0, 0.1 * dx * dx, oracle.IMAG, 1)
+            g0 = oracle.run(c0, inputs.ho_gaussian(3, c0.n, c0.dx, c0.omega, noise=1e-3, seed=0), 1).psi
+            rate_c0, n_c0, el_c0, _ = _oracle_rate(c0, g0, 0.5 * target_s)
+        finally:
+            oracle.use_library(prev)
+    return {"value": rate_all, "unit": "grid-point-steps/s", "cores": used, "kind": "oracle",
+            "cpu": _cpu_model(), "affinity_cpus": affinity,
+            "one_core": {"value": rate_one, "cores": 1,
+                         "sample": f"steps 2-{last_one} ({n_one} steps, {el_one:.1f} s timed)"},
+            "ground64": {"value": rate_c0, "cores": used, "workload": "64^3 FP64 imaginary time, dx=0.2, g=22",
+                         "sample": f"{n_c0} steps, {el_c0:.1f} s timed after one untimed step"},
+            "build": "gcc -O3 -march=native -fopenmp (ISO C floating point)",
+            "sample": f"256^3 complex128 real-time workload, steps 2-{last_all} ({n_all} steps, {el_all:.1f} s "
+                      f"timed after one untimed step), FP64 C oracle with OpenMP over lines on {used} threads"}
 
 
 def imag256_timing(steps: int = 300):
@@ -260,13 +304,54 @@ def mix64_problems():
     return out
 
 
-def batch_mix64(tick: int = 100, cap: int = 300000, time_limit: float = 60.0):
-    """All 64 instances admitted at once and run to |delta mu| < 1e-6; each
-    is evicted when it stops.  Also times the first steps, while all 64 run,
-    against the HBM roofline (2 d S bytes per point-step)."""
+def batch_all_active(launches: int = 20):
+    """The 64-instance mix with no stop rule (mu_tol = 0), so that every
+    instance runs through the window: warm-up launches for 0.3 s (the graph
+    is captured and the clocks come up after the host-side admissions), then
+    `launches` timed ones.  Solo 1D instances take several steps per launch,
+    so the work is counted from the step counters."""
     import numpy as np
     import torch
     from paper_1605_03958_amd import inputs, sscn
+    probs = mix64_problems()
+    for _, p in probs:
+        apply_tiles(p, "batch")
+    st = torch.cuda.Stream()
+    b = sscn.Batch(64, stream=st)
+    for i, (d, p) in enumerate(probs):
+        b.admit(i, p, inputs.ho_gaussian(d.dim, d.n, d.dx, d.omega, noise=1e-3, seed=d.seed), mu_tol=0.0,
+                max_steps=1 << 40)
+    pts = np.array([p.points for _, p in probs], dtype=np.float64)
+    dims = np.array([p.dim for _, p in probs])
+    t0 = time.perf_counter()
+    while True:
+        b.step(launches)
+        s0 = b.poll(wait=True)
+        if time.perf_counter() - t0 > 0.3:
+            break
+    ta = time.perf_counter()
+    b.step(launches)
+    s = b.poll(wait=True)
+    t_all = time.perf_counter() - ta
+    err = b.error()
+    b.close()
+    d_steps = np.array([x.steps - y.steps for x, y in zip(s, s0)], dtype=np.float64)
+    big = dims > 1
+    return {"launches": launches, "ms_per_launch": 1e3 * t_all / launches,
+            "ptsteps_per_s": float((d_steps * pts).sum()) / t_all,
+            "hbm_frac": float((d_steps * pts * 2 * dims * 4).sum()) / t_all / (HBM_PEAK_GBS * 1e9),
+            "hbm_frac_2d3d": float((d_steps * pts * 2 * dims * 4)[big].sum()) / t_all / (HBM_PEAK_GBS * 1e9),
+            "all_running": all(x.state == sscn.SLOT_RUNNING for x in s), "error_flag": bool(err)}
+
+
+def batch_mix64(tick: int = 100, cap: int = 300000, time_limit: float = 60.0):
+    """All 64 instances admitted at once and run to |delta mu| < 1e-6; each
+    is evicted when it stops.  Beside it, the same mix with every instance
+    running is timed against the HBM roofline (2 d S bytes per point-step)."""
+    import numpy as np
+    import torch
+    from paper_1605_03958_amd import inputs, sscn
+    allact = batch_all_active()
     probs = mix64_problems()
     for _, p in probs:
         apply_tiles(p, "batch")
@@ -279,24 +364,8 @@ def batch_mix64(tick: int = 100, cap: int = 300000, time_limit: float = 60.0):
     dims = np.array([p.dim for _, p in probs])
     done = {}
     t0 = time.perf_counter()
-    # while all 64 run: warm-up launches for 0.3 s (the graph is captured and
-    # the clocks come up after the host-side admissions), then 20 timed ones;
-    # solo 1D instances take several steps per launch, so the work is
-    # counted from the step counters
-    while True:
-        b.step(20)
-        s0 = b.poll(wait=True)
-        if time.perf_counter() - t0 > 0.3:
-            break
-    ta = time.perf_counter()
-    b.step(20)
+    b.step(tick)
     s = b.poll(wait=True)
-    t_all = time.perf_counter() - ta
-    d_steps = np.array([x.steps - y.steps for x, y in zip(s, s0)], dtype=np.float64)
-    allact = {"launches": 20, "ms_per_launch": 1e3 * t_all / 20,
-              "ptsteps_per_s": float((d_steps * pts).sum()) / t_all,
-              "hbm_frac": float((d_steps * pts * 2 * dims * 4).sum()) / t_all / (HBM_PEAK_GBS * 1e9),
-              "all_running": all(x.state == sscn.SLOT_RUNNING for x in s)}
     while len(done) < 64 and time.perf_counter() - t0 < time_limit:
         now = time.perf_counter()
         for i, x in enumerate(s):
@@ -421,11 +490,17 @@ def main():
 
     main_prec = precs[0]
     m = out[main_prec]
-    # dominant kernel: the sweep class with the largest mean duration
-    sweeps = {k: v for k, v in m["kernels"].items() if k in ("x_sweep_pointwise", "y_sweep", "z_sweep_norm")}
-    dom = max(sweeps, key=sweeps.get)
-    alg_bytes = 2 * m["S"] * m["points"]            # one read + one write of psi per sweep
-    achieved = alg_bytes / (sweeps[dom] * 1e-3) / 1e9
+    # dominant kernel: the kernel with the largest total time per step.  In
+    # real time the y and z sweeps are launches of one kernel (k_col), the x
+    # sweep another (k_row); per launch each moves one read and one write of
+    # the state
+    km = m["kernels"]
+    per_kernel = {"x_sweep_pointwise": (km["x_sweep_pointwise"], 1),
+                  "yz_sweep": ((km["y_sweep"] + km["z_sweep_norm"]) / 2, 2)}
+    dom = max(per_kernel, key=lambda k: per_kernel[k][0] * per_kernel[k][1])
+    mean_ms, launches = per_kernel[dom]
+    alg_bytes = 2 * m["S"] * m["points"]
+    achieved = alg_bytes / (mean_ms * 1e-3) / 1e9
     workload = "256cube_complex128" if main_prec == sscn.F64 else "256cube_complex64"
     traffic = load_traffic(dom, workload)
     res = {
@@ -447,7 +522,9 @@ def main():
                    "mode": "real-time"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "alg_bytes_per_launch": alg_bytes, "mean_launch_ms": sweeps[dom]},
+                     "alg_bytes_per_launch": alg_bytes, "mean_launch_ms": mean_ms,
+                     "launches_per_step": launches,
+                     "share_of_kernel_time": mean_ms * launches / sum(v[0] * v[1] for v in per_kernel.values())},
         "kernel_ms": {k: round(v, 5) for k, v in m["kernels"].items()},
         "step_hbm_frac": (6 * m["S"] * m["points"] * args.steps / m["elapsed"]) / (HBM_PEAK_GBS * 1e9),
     }

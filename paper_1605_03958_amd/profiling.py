@@ -12,7 +12,8 @@ HBM traffic per launch = FETCH_SIZE * f_fetch + WRITE_SIZE * f_write, where
 f_* = (bytes a plain device copy of known size must move) / (what the same
 counter reads for that copy kernel) -- the copy is bench.py's torch copy of
 one state's worth of bytes.  Kernel classes follow the launch order of a
-step: the x sweep (k_row), then the y and z sweeps (k_col, in that order).
+step: the x sweep (k_row), then the y and z sweeps (k_col, in that order);
+"yz_sweep" is the mean over both k_col launches of a step.
 
 Usage:
   python -m paper_1605_03958_amd.profiling --trace DIR --fetch DIR --write DIR \
@@ -149,7 +150,13 @@ def main():
               "| class | mean duration us | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM bytes / launch "
               "(calibrated) | / algorithmic | achieved GB/s (algorithmic) |", "|---|---|---|---|---|---|---|"]
     rec = {}
-    for cls in ("x_sweep_pointwise", "y_sweep", "z_sweep_norm", "copy"):
+    # the y and z sweeps of a real-time step launch one kernel (k_col): its
+    # mean over both launches is the class "yz_sweep"
+    if "y_sweep" in fetch and "z_sweep_norm" in fetch:
+        for d in (fetch, write, dur):
+            if "y_sweep" in d and "z_sweep_norm" in d:
+                d["yz_sweep"] = 0.5 * (d["y_sweep"] + d["z_sweep_norm"])
+    for cls in ("x_sweep_pointwise", "y_sweep", "z_sweep_norm", "yz_sweep", "copy"):
         if cls not in fetch:
             continue
         tb = fetch[cls] * kib * f_fetch + write[cls] * kib * f_write

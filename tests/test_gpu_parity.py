@@ -350,6 +350,30 @@ def _golden_cube256():
         return json.load(f)
 
 
+def _golden_lines():
+    """The stored oracle's line sums (every grid point enters three of them)
+    and the function that defines them."""
+    import importlib.util
+    import os
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    spec = importlib.util.spec_from_file_location("make_cube256_reference",
+                                                  os.path.join(here, "make_cube256_reference.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    ref = np.load(os.path.join(here, "cube256_oracle_1000_lines.npz"))
+    return {k: ref[k] for k in ref.files}, mod.line_sums
+
+
+def _line_errors(flat, shape):
+    ref, line_sums = _golden_lines()
+    got = line_sums(flat.astype(np.complex128).reshape(shape))
+    out = {}
+    for k, r in ref.items():
+        d = got[k] - r
+        out[k] = (float(np.linalg.norm(d) / np.linalg.norm(r)), float(np.max(np.abs(d)) / np.max(np.abs(r))))
+    return out
+
+
 def _cube256_run(prec, steps=1000):
     p = cube256_problem(prec)
     psi0 = inputs.thomas_fermi(3, p.n, p.dx, p.omega, 100.0, phase_sigma=0.05, seed=1)
@@ -364,15 +388,23 @@ def _cube256_run(prec, steps=1000):
 def test_cube256_1000_steps_matches_stored_oracle():
     """256^3 complex128, 1000 steps, bench launch configuration, against the
     stored oracle run (tests/golden/make_cube256_reference.py): relative L2 over
-    4096 seeded sample points <= 1e-10, observables <= 1e-10 relative."""
+    4096 seeded sample points <= 1e-10 and each sample within 1e-10 of the
+    largest; every grid point through the x-, y- and z-line sums (relative
+    L2 and largest deviation <= 1e-10 of each vector); observables <= 1e-10
+    relative."""
     ref = _golden_cube256()
     ob, flat = _cube256_run(F64)
     idx = np.asarray(ref["sample_index"])
     exp = np.asarray(ref["sample_re"]) + 1j * np.asarray(ref["sample_im"])
     got = flat[idx].astype(np.complex128)
     err = np.linalg.norm(got - exp) / np.linalg.norm(exp)
-    print(f"256^3 FP64 sampled rel-L2 {err:.3e}", flush=True)
-    assert err <= 1e-10
+    emax = np.max(np.abs(got - exp)) / np.max(np.abs(exp))
+    lines = _line_errors(flat, (256, 256, 256))
+    print(f"256^3 FP64 sampled rel-L2 {err:.3e} max {emax:.3e}; line sums (rel-L2, max) "
+          + " ".join(f"{k} {v[0]:.2e} {v[1]:.2e}" for k, v in lines.items()), flush=True)
+    assert err <= 1e-10 and emax <= 1e-10
+    for k, (l2, mx) in lines.items():
+        assert l2 <= 1e-10 and mx <= 1e-10, k
     assert abs(np.sum(np.abs(flat) ** 2) / ref["l2sq"] - 1) <= 1e-12
     for f, g in (("norm", "norm"), ("mu", "mu"), ("energy", "energy"), ("ekin", "K"), ("epot", "P"),
                  ("eint", "I")):
@@ -388,16 +420,45 @@ def test_cube256_fp32_error_against_stored_oracle():
     exp = np.asarray(ref["sample_re"]) + 1j * np.asarray(ref["sample_im"])
     got = flat[idx].astype(np.complex128)
     err = np.linalg.norm(got - exp) / np.linalg.norm(exp)
+    emax = np.max(np.abs(got - exp)) / np.max(np.abs(exp))
+    lines = _line_errors(flat, (256, 256, 256))
     o1 = ref["obs1"]
     dmu = abs(ob.mu - o1["mu"])
     dE = abs(ob.energy - o1["energy"]) / abs(o1["energy"])
     dN = abs(ob.norm - o1["norm"])
-    print(f"256^3 FP32: psi sampled rel-L2 {err:.3e}  |d mu| {dmu:.3e}  rel dE {dE:.3e}  |d norm| {dN:.3e}",
-          flush=True)
+    print(f"256^3 FP32: psi sampled rel-L2 {err:.3e} max {emax:.3e}  |d mu| {dmu:.3e}  rel dE {dE:.3e}  "
+          f"|d norm| {dN:.3e}; line sums (rel-L2, max) "
+          + " ".join(f"{k} {v[0]:.2e} {v[1]:.2e}" for k, v in lines.items()), flush=True)
     assert dmu <= 1e-5
-    assert err <= 1e-3
+    assert err <= 1e-3 and emax <= 1e-4
+    for k, (l2, mx) in lines.items():
+        assert l2 <= 1e-3 and mx <= 1e-3, k
     assert dE <= 1e-5
     assert dN <= 1e-5
+
+
+@pytest.mark.parametrize("mode,prec", [(IMAG, F64), (REAL, F64), (IMAG, F32), (REAL, F32)])
+def test_checkpoint_and_resume_is_bitwise(mode, prec):
+    """1000 steps in one solver equal, bit for bit, 500 steps, the state
+    saved to host memory, a fresh solver created from it, and 500 more
+    (imaginary time renormalises every step, so the phase of the
+    renormalisation does not depend on where the run was cut)."""
+    p = Problem(3, (40, 36, 30), (0.25, 0.25, 0.3), (1.0, 1.5, 2.0), 18.0,
+                0.006 if mode == IMAG else 0.0012, mode, prec, 1 if mode == IMAG else 0)
+    psi0 = initial(p, seed=9)
+    s = sscn.Solver(p, psi0)
+    s.step(1000)
+    whole = s.state()
+    s.close()
+    a = sscn.Solver(p, psi0)
+    a.step(500)
+    saved = a.state().copy()
+    a.close()
+    b = sscn.Solver(p, saved)
+    b.step(500)
+    resumed = b.state()
+    b.close()
+    assert np.array_equal(whole, resumed)
 
 
 def test_graph_replay_equals_direct_launches():
@@ -413,18 +474,25 @@ def test_graph_replay_equals_direct_launches():
             psi0 = inputs.ho_gaussian(3, p.n, p.dx, p.omega, noise=1e-3, seed=5)
         else:
             psi0 = inputs.thomas_fermi(3, p.n, p.dx, p.omega, 10.0, phase_sigma=0.05, seed=5)
-        plan = [(70, None), (101, 6.0), (33, None)]      # 70 = 2 runs + 6; quench; ...
+        # 70 = 32 + 32 + 4 + 2; quench; 101 = 3 x 32 + 4 + 1; 20 = 16 + 4
+        # after sscn_prepare; 1 step
+        plan = [(70, None), (101, 6.0), (20, None), (1, None)]
         outs = []
-        for how in ("graph", "direct", "default"):
+        for how in ("graph", "step1", "direct", "default"):
             s = sscn.Solver(p, psi0, stream=torch.cuda.default_stream() if how == "default" else None)
             for n, g in plan:
                 if g is not None:
                     s.set_g(g)
-                if how == "direct":
+                if how == "step1":                  # one-step graphs
                     for _ in range(n):
                         s.step(1)
+                elif how == "direct":               # the timed path launches every kernel directly
+                    s.step_timed(n)
                 else:
+                    if n == 20:
+                        s.prepare(n)
                     s.step(n)
             outs.append(s.state())
             s.close()
-        assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2]), mode
+        for k in range(1, len(outs)):
+            assert np.array_equal(outs[0], outs[k]), (mode, k)
