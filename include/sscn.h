@@ -147,10 +147,12 @@ int sscn_create(const sscn_problem *pb, void *d_psi, void *d_ws, void *hip_strea
  * of direct launches. */
 int sscn_step(sscn_solver *s, int64_t nsteps);
 
-/* Systems call: capture now, without launching anything, the graphs that a
- * following sscn_step(s, nsteps) from the current step will replay, so that
- * call does no capture of its own (a timed region, a latency-bound loop).
- * Never required: sscn_step captures what is missing. */
+/* Systems call: capture now, without launching any kernel, the graphs that
+ * a following sscn_step(s, nsteps) from the current step will replay, and
+ * upload them to the device on the stream, so that call does no capture or
+ * upload of its own (a timed region, a latency-bound loop).  Never
+ * required: sscn_step captures what is missing.  SSCN_E_HIP if an upload
+ * fails. */
 int sscn_prepare(sscn_solver *s, int64_t nsteps);
 
 /* "Summary of revisions" (the general output file holds the energy and the

@@ -551,16 +551,21 @@ static hipGraphExec_t graph_for(sscn_solver *s, int64_t after_step, int lg)
 }
 
 // Capture, without launching anything, every graph a later call of nsteps
-// steps from the current step will replay.
-static void prepare_graphs(sscn_solver *s, int64_t nsteps)
+// steps from the current step will replay, and upload each to the device
+// (a graph's first launch otherwise pays for the upload).
+static hipError_t prepare_graphs(sscn_solver *s, int64_t nsteps)
 {
     int64_t step = s->step;
     while (nsteps > 0) {
         const int lg = run_log(nsteps);
-        if (!graph_for(s, step, lg)) return;
+        hipGraphExec_t ex = graph_for(s, step, lg);
+        if (!ex) return hipSuccess;             // graphs off: sscn_step launches directly
+        hipError_t e = hipGraphUpload(ex, s->st);
+        if (e != hipSuccess) return e;
         step += int64_t(1) << lg;
         nsteps -= int64_t(1) << lg;
     }
+    return hipSuccess;
 }
 
 static hipError_t enqueue_steps(sscn_solver *s, int64_t nsteps, Timer *tm)
@@ -770,8 +775,7 @@ int sscn_step(sscn_solver *s, int64_t nsteps)
 int sscn_prepare(sscn_solver *s, int64_t nsteps)
 {
     if (!s || nsteps < 0) return SSCN_E_INVALID;
-    prepare_graphs(s, nsteps);
-    return SSCN_OK;
+    return prepare_graphs(s, nsteps) == hipSuccess ? SSCN_OK : SSCN_E_HIP;
 }
 
 int sscn_step_timed(sscn_solver *s, int64_t nsteps, double *ms)
