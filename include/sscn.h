@@ -136,6 +136,27 @@ int sscn_workspace_bytes(const sscn_problem *pb, size_t *bytes);
 int sscn_create(const sscn_problem *pb, void *d_psi, void *d_ws, void *hip_stream,
                 sscn_solver **out);
 
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation.  Same as
+ * sscn_create, but the workspace is the library's own static device array
+ * of SSCN_STATIC_WS_BYTES bytes on the current device (the device the
+ * stream belongs to), which each GPU the library runs on holds until the
+ * process ends.  The call allocates no device or pinned host memory (no
+ * hipMalloc, hipHostMalloc or hipFree; the handle and the host image of the
+ * tables are ordinary host memory).  It rewrites the whole array (tables,
+ * then zeros), so nothing of an earlier solver's contents survives; it
+ * waits for that copy.  One live solver per device may hold the array:
+ * while one does, another call on that device returns SSCN_E_NOSPACE;
+ * sscn_destroy releases it after waiting for the solver's stream.  Every
+ * later call on the solver is the same as on one from sscn_create; calls
+ * on it from several threads at once race, as for any handle.  Errors as
+ * sscn_create, plus SSCN_E_UNSUPPORTED when the problem's workspace
+ * (sscn_workspace_bytes) exceeds SSCN_STATIC_WS_BYTES or the device index
+ * is 64 or more, SSCN_E_NOSPACE as above, SSCN_E_HIP if the array's device
+ * address cannot be taken. */
+#define SSCN_STATIC_WS_BYTES ((size_t)4 << 20)
+int sscn_create_noalloc(const sscn_problem *pb, void *d_psi, void *hip_stream, sscn_solver **out);
+
 /* "Solution method" (propagation in imaginary or real time over small time
  * steps): enqueue nsteps >= 0 SSCN steps on the stream and return.  When the
  * stream reaches the end of the call the state is complete: in imaginary

@@ -326,6 +326,7 @@ struct sscn_solver {
     // which of their steps renormalise; their kernel arguments hold g
     std::map<int64_t, hipGraphExec_t> graphs;
     bool graphs_off;          // capture failed once on this stream: launch directly
+    int static_dev;           // sscn_create_noalloc: the device whose static workspace it holds, else -1
 };
 
 static void drop_graphs(sscn_solver *s)
@@ -722,13 +723,14 @@ int sscn_workspace_bytes(const sscn_problem *pb, size_t *bytes)
     return SSCN_OK;
 }
 
-int sscn_create(const sscn_problem *pb, void *d_psi, void *d_ws, void *hip_stream, sscn_solver **out)
+}  // extern "C"
+
+// A solver over caller memory.  whole_ws: upload an image of the whole
+// workspace (zeros past the tables) instead of its head only, for a
+// workspace whose earlier contents are unknown.
+static int create_solver(const sscn_problem *pb, void *d_psi, void *d_ws, void *hip_stream, bool whole_ws,
+                         int static_dev, sscn_solver **out)
 {
-    int v = validate(pb);
-    if (v != SSCN_OK) return v;
-    if (!d_psi || !d_ws || !out) return SSCN_E_INVALID;
-    if (reinterpret_cast<uintptr_t>(d_ws) % 256 != 0) return SSCN_E_INVALID;
-    if (reinterpret_cast<uintptr_t>(d_psi) % 16 != 0) return SSCN_E_INVALID;
     sscn_solver *s = new (std::nothrow) sscn_solver();   // value-initialised: members zero, map empty
     if (!s) return SSCN_E_INVALID;
     s->pb = *pb;
@@ -736,15 +738,16 @@ int sscn_create(const sscn_problem *pb, void *d_psi, void *d_ws, void *hip_strea
     s->ws = static_cast<char *>(d_ws);
     s->st = static_cast<hipStream_t>(hip_stream);
     s->g = pb->g;
+    s->static_dev = static_dev;
     TileOverride ov;
-    v = make_plan(*pb, tile_hint_copy(*pb, ov) ? &ov : nullptr, s->P);
+    int v = make_plan(*pb, tile_hint_copy(*pb, ov) ? &ov : nullptr, s->P);
     if (v != SSCN_OK) {
         delete s;
         return v;
     }
     // host image of the workspace head and tables, uploaded in one pass
     try {
-        std::vector<char> img(s->P.off_part, 0);
+        std::vector<char> img(whole_ws ? s->P.ws_bytes : s->P.off_part, 0);
         double *scal = reinterpret_cast<double *>(img.data() + s->P.off_scal);
         scal[0] = 1.0;
         scal[1] = 1.0;
@@ -762,6 +765,65 @@ int sscn_create(const sscn_problem *pb, void *d_psi, void *d_ws, void *hip_strea
         delete s;
         return SSCN_E_INVALID;
     }
+    *out = s;
+    return SSCN_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Static workspace of sscn_create_noalloc: one array per device, which every
+// GPU the library runs on holds until the process ends.  In host code the
+// array's name is only a stand-in: its device address comes from
+// hipGetSymbolAddress, taken once per device with that device current, and
+// only that address is used.
+// ---------------------------------------------------------------------------
+constexpr size_t kStaticWsBytes = SSCN_STATIC_WS_BYTES;
+static __device__ __align__(256) char scratch[kStaticWsBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_static_mu;
+static void *g_static_ptr[kMaxDevices];                  // device address of `scratch`, per device
+static const sscn_solver *g_static_owner[kMaxDevices];   // the live solver holding it, per device
+
+extern "C" {
+
+int sscn_create(const sscn_problem *pb, void *d_psi, void *d_ws, void *hip_stream, sscn_solver **out)
+{
+    int v = validate(pb);
+    if (v != SSCN_OK) return v;
+    if (!d_psi || !d_ws || !out) return SSCN_E_INVALID;
+    if (reinterpret_cast<uintptr_t>(d_ws) % 256 != 0) return SSCN_E_INVALID;
+    if (reinterpret_cast<uintptr_t>(d_psi) % 16 != 0) return SSCN_E_INVALID;
+    return create_solver(pb, d_psi, d_ws, hip_stream, false, -1, out);
+}
+
+int sscn_create_noalloc(const sscn_problem *pb, void *d_psi, void *hip_stream, sscn_solver **out)
+{
+    int v = validate(pb);
+    if (v != SSCN_OK) return v;
+    if (!d_psi || !out) return SSCN_E_INVALID;
+    if (reinterpret_cast<uintptr_t>(d_psi) % 16 != 0) return SSCN_E_INVALID;
+    Plan P;
+    TileOverride ov;
+    v = make_plan(*pb, tile_hint_copy(*pb, ov) ? &ov : nullptr, P);
+    if (v != SSCN_OK) return v;
+    if (P.ws_bytes > kStaticWsBytes) return SSCN_E_UNSUPPORTED;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return SSCN_E_HIP;
+    if (dev < 0 || dev >= kMaxDevices) return SSCN_E_UNSUPPORTED;
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (!g_static_ptr[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return SSCN_E_HIP;
+        }
+        g_static_ptr[dev] = ptr;
+    }
+    if (g_static_owner[dev]) return SSCN_E_NOSPACE;
+    sscn_solver *s = nullptr;
+    v = create_solver(pb, d_psi, g_static_ptr[dev], hip_stream, true, dev, &s);
+    if (v != SSCN_OK) return v;
+    g_static_owner[dev] = s;
     *out = s;
     return SSCN_OK;
 }
@@ -981,6 +1043,10 @@ int sscn_destroy(sscn_solver *s)
     if (!s) return SSCN_E_INVALID;
     (void)hipStreamSynchronize(s->st);
     drop_graphs(s);
+    if (s->static_dev >= 0) {
+        std::lock_guard<std::mutex> lk(g_static_mu);
+        if (g_static_owner[s->static_dev] == s) g_static_owner[s->static_dev] = nullptr;
+    }
     delete s;
     return SSCN_OK;
 }
@@ -991,8 +1057,8 @@ int sscn_density_1d(sscn_solver *s, int keep, void *d_out)
     double w = 1.0;
     for (int a = 0; a < s->pb.dim; ++a)
         if (a != keep) w *= s->pb.dx[a];
-    double *scratch = reinterpret_cast<double *>(s->ws + s->P.off_dens);
-    return launch_density_1d(s->P.elem, s->psi, s->pb.n, keep, w, static_cast<double *>(d_out), scratch,
+    double *dens_scratch = reinterpret_cast<double *>(s->ws + s->P.off_dens);
+    return launch_density_1d(s->P.elem, s->psi, s->pb.n, keep, w, static_cast<double *>(d_out), dens_scratch,
                              s->P.dens_blocks, s->st) ==
                    hipSuccess
                ? SSCN_OK

@@ -82,6 +82,8 @@ EXPORTS = {
     "sscn_workspace_bytes": ([ctypes.POINTER(CProblem), ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "sscn_create": ([ctypes.POINTER(CProblem), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                      ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
+    "sscn_create_noalloc": ([ctypes.POINTER(CProblem), ctypes.c_void_p, ctypes.c_void_p,
+                             ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
     "sscn_step": ([ctypes.c_void_p, ctypes.c_int64], ctypes.c_int),
     "sscn_prepare": ([ctypes.c_void_p, ctypes.c_int64], ctypes.c_int),
     "sscn_observe": ([ctypes.c_void_p, ctypes.POINTER(CObs)], ctypes.c_int),
@@ -277,7 +279,9 @@ class Solver:
     legacy default stream, so the library can replay its steps from captured
     graphs); state(), observe() and the densities wait for it."""
 
-    def __init__(self, prob: Problem, psi0=None, device: str = "cuda", stream=None):
+    def __init__(self, prob: Problem, psi0=None, device: str = "cuda", stream=None, noalloc: bool = False):
+        """noalloc: create through sscn_create_noalloc (the library's static
+        workspace on the device; no workspace tensor)."""
         import torch
         L = lib()
         if not torch.cuda.is_available():
@@ -288,18 +292,25 @@ class Solver:
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
         self.psi = torch.zeros(prob.shape, dtype=prob.torch_dtype(), device=self.device)
-        wsb = workspace_bytes(prob)
-        self.ws = torch.zeros(wsb // 8 + 32, dtype=torch.float64, device=self.device)
-        ws_ptr = self.ws.data_ptr()
-        if ws_ptr % 256:
-            raise RuntimeError("workspace tensor is not 256-byte aligned")
+        self.ws = None
+        if not noalloc:
+            wsb = workspace_bytes(prob)
+            self.ws = torch.zeros(wsb // 8 + 32, dtype=torch.float64, device=self.device)
+            if self.ws.data_ptr() % 256:
+                raise RuntimeError("workspace tensor is not 256-byte aligned")
         if psi0 is not None:
             self.set_state(psi0)
         h = ctypes.c_void_p(0)
         torch.cuda.synchronize(self.device)
-        _check(L.sscn_create(ctypes.byref(self._pc), ctypes.c_void_p(self.psi.data_ptr()),
-                             ctypes.c_void_p(ws_ptr), ctypes.c_void_p(self.stream.cuda_stream),
-                             ctypes.byref(h)), "sscn_create")
+        if noalloc:
+            with torch.cuda.device(self.device):
+                _check(L.sscn_create_noalloc(ctypes.byref(self._pc), ctypes.c_void_p(self.psi.data_ptr()),
+                                             ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
+                       "sscn_create_noalloc")
+        else:
+            _check(L.sscn_create(ctypes.byref(self._pc), ctypes.c_void_p(self.psi.data_ptr()),
+                                 ctypes.c_void_p(self.ws.data_ptr()), ctypes.c_void_p(self.stream.cuda_stream),
+                                 ctypes.byref(h)), "sscn_create")
         self._h = h
 
     # -- state ---------------------------------------------------------------
