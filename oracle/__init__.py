@@ -1,4 +1,6 @@
-"""ctypes binding of the plain FP64 CPU oracle (``sscn_oracle.c``).
+"""ctypes binding of the plain FP64 CPU oracle (``sscn_oracle.c`` for the
+anisotropic Cartesian grids, ``sscn_sym_oracle.c`` for the circular,
+spherical and axial traps).
 
 TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's
 CPU-baseline leg are the only callers.  The product path never imports this
@@ -73,6 +75,60 @@ class Problem:
         return (n[2], n[1], n[0])
 
 
+CIR, SPH, AXI = 1, 2, 3
+SYM_TRACE_COLS = ("step", "norm", "mu", "energy", "K", "P", "I", "mr", "mz", "unused", "mr2", "mz2",
+                  "unused2")
+
+
+class _SymProblem(ctypes.Structure):
+    _fields_ = [
+        ("geom", ctypes.c_int),
+        ("n", ctypes.c_int * 2),
+        ("dx", ctypes.c_double * 2),
+        ("omega", ctypes.c_double * 2),
+        ("g", ctypes.c_double),
+        ("dt", ctypes.c_double),
+        ("mode", ctypes.c_int),
+        ("renorm_every", ctypes.c_int),
+    ]
+
+
+@dataclass
+class SymProblem:
+    """Symmetric trap: geom CIR (2D circular, psi(r)), SPH (3D spherical,
+    psi(r)) or AXI (3D axial, psi(rho, z)); n = (n_r, n_z), dx = (dr, dz),
+    omega = (omega_r, omega_z); n_z = 1 unless axial."""
+    geom: int
+    n: tuple
+    dx: tuple
+    omega: tuple
+    g: float
+    dt: float
+    mode: int = IMAG
+    renorm_every: int = 1
+
+    def c(self) -> _SymProblem:
+        p = _SymProblem()
+        p.geom = int(self.geom)
+        n = list(self.n) + [1] * (2 - len(self.n))
+        dx = list(self.dx) + [1.0] * (2 - len(self.dx))
+        om = list(self.omega) + [0.0] * (2 - len(self.omega))
+        for a in range(2):
+            p.n[a] = int(n[a])
+            p.dx[a] = float(dx[a])
+            p.omega[a] = float(om[a])
+        p.g = float(self.g)
+        p.dt = float(self.dt)
+        p.mode = int(self.mode)
+        p.renorm_every = int(self.renorm_every)
+        return p
+
+    @property
+    def shape(self):
+        n = list(self.n) + [1] * (2 - len(self.n))
+        return (n[1], n[0])
+
+
 _lib = None
 _lib_path = LIB_PATH
 
@@ -109,9 +165,16 @@ def load():
     lib.orc_set_threads.argtypes = [ctypes.c_int]
     lib.orc_density_1d.argtypes = [pp, dp, ctypes.c_int, dp]
     lib.orc_density_2d.argtypes = [pp, dp, ctypes.c_int, dp]
+    sp = ctypes.POINTER(_SymProblem)
+    lib.ors_coefs.argtypes = [sp, dp, dp, dp, dp]
+    lib.ors_observe.argtypes = [sp, dp, dp]
+    lib.ors_substep.argtypes = [sp, dp, ctypes.c_int]
+    lib.ors_run.argtypes = [sp, dp, ctypes.c_long, ctypes.c_long, ctypes.c_int,
+                            ctypes.c_double, dp, ctypes.c_long,
+                            ctypes.POINTER(ctypes.c_long), ctypes.POINTER(ctypes.c_long)]
     for f in (lib.orc_thomas, lib.orc_cn_line, lib.orc_observe, lib.orc_potential,
               lib.orc_substep, lib.orc_run, lib.orc_threads, lib.orc_set_threads, lib.orc_density_1d,
-              lib.orc_density_2d):
+              lib.orc_density_2d, lib.ors_coefs, lib.ors_observe, lib.ors_substep, lib.ors_run):
         f.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -245,3 +308,59 @@ def threads() -> int:
 def set_threads(n: int) -> None:
     if load().orc_set_threads(int(n)):
         raise ValueError(f"orc_set_threads({n})")
+
+
+# ---------------------------------------------------------------------------
+# symmetric traps (sscn_sym_oracle.c)
+# ---------------------------------------------------------------------------
+
+def _as_sym_state(prob: SymProblem, psi) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(psi, dtype=np.complex128).reshape(prob.shape)).copy()
+
+
+def sym_coefs(prob: SymProblem):
+    """(l, d, u, W): H_r = -Lap_r/2 on radial cell i is
+    d_i psi_i - l_i psi_{i-1} - u_i psi_{i+1}; W_i the cell weights."""
+    n = prob.n[0]
+    l, d, u, w = (np.zeros(n) for _ in range(4))
+    pc = prob.c()
+    rc = load().ors_coefs(ctypes.byref(pc), _ptr(l), _ptr(d), _ptr(u), _ptr(w))
+    if rc:
+        raise ValueError(f"ors_coefs rc={rc}")
+    return l, d, u, w
+
+
+def sym_observe(prob: SymProblem, psi) -> Observables:
+    a = _as_sym_state(prob, psi)
+    out = np.zeros(12)
+    pc = prob.c()
+    rc = load().ors_observe(ctypes.byref(pc), _ptr(a.view(np.float64)), _ptr(out))
+    if rc:
+        raise ValueError(f"ors_observe rc={rc}")
+    return Observables(*out[:6], tuple(out[6:9]), tuple(out[9:12]))
+
+
+def sym_substep(prob: SymProblem, psi, which: int) -> np.ndarray:
+    """which = -1: pointwise substep; 0: the r substep; 1: the z substep."""
+    a = _as_sym_state(prob, psi)
+    pc = prob.c()
+    rc = load().ors_substep(ctypes.byref(pc), _ptr(a.view(np.float64)), int(which))
+    if rc:
+        raise ValueError(f"ors_substep rc={rc}")
+    return a
+
+
+def sym_run(prob: SymProblem, psi, nsteps: int, observe_every: int = 0,
+            mu_tol: float = 0.0, first_step: int = 1) -> RunResult:
+    a = _as_sym_state(prob, psi)
+    cap = (nsteps // observe_every + 2) if observe_every > 0 else 2
+    trace = np.zeros((cap, len(SYM_TRACE_COLS)))
+    rows = ctypes.c_long(0)
+    done = ctypes.c_long(0)
+    pc = prob.c()
+    rc = load().ors_run(ctypes.byref(pc), _ptr(a.view(np.float64)), int(nsteps), int(first_step),
+                        int(observe_every), float(mu_tol), _ptr(trace), cap, ctypes.byref(rows),
+                        ctypes.byref(done))
+    if rc < 0:
+        raise ValueError(f"ors_run rc={rc}")
+    return RunResult(a, trace[: rows.value].copy(), int(done.value), rc == 0)

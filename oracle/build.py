@@ -13,7 +13,7 @@ import os
 import subprocess
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(_HERE, "sscn_oracle.c")
+SRCS = [os.path.join(_HERE, "sscn_oracle.c"), os.path.join(_HERE, "sscn_sym_oracle.c")]
 LIB = os.path.join(_HERE, "liboracle.so")
 
 
@@ -27,7 +27,7 @@ def build(verbose: bool = False, native: bool = False, sanitize: bool = False,
     if sanitize:
         cmd += ["-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
                 "-fno-sanitize-recover=undefined"]
-    cmd += ["-o", tmp, SRC, "-lm"]
+    cmd += ["-o", tmp] + SRCS + ["-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)

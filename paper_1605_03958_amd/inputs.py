@@ -105,6 +105,80 @@ def thomas_fermi(dim, n, dx, omega, g_init: float, phase_sigma: float = 0.0,
 
 
 # ---------------------------------------------------------------------------
+# Symmetric traps: circular (2D, psi(r)), spherical (3D, psi(r)), axial
+# (3D, psi(rho, z)).  Radial grid convention (shared by both implementations
+# by definition, not by code): n cells of width dr with values at the
+# centres r_i = (i + 1/2) dr; z as a Cartesian axis.  Arrays are shaped
+# (n_z, n_r), r fastest (n_z = 1 unless axial).
+# ---------------------------------------------------------------------------
+
+SYM_CIR, SYM_SPH, SYM_AXI = 1, 2, 3
+
+
+def radial_coords(n: int, dr: float) -> np.ndarray:
+    return (np.arange(n, dtype=np.float64) + 0.5) * dr
+
+
+def sym_gaussian(geom: int, n, dx, omega, noise: float = 1e-3, seed: int = 0,
+                 z_shift: float = 0.0) -> np.ndarray:
+    """The harmonic-oscillator ground state of the trap (continuum
+    normalisation: (w/pi)^(d/4) exp(-w r^2/2) with d = 2 (circular) or 3
+    (spherical); axial: (w_rho/pi)^(1/2) (w_z/pi)^(1/4) exp(-w_rho rho^2/2
+    - w_z (z - z_shift)^2/2)), plus U[-noise, noise) per point.  Real FP64,
+    shape (n_z, n_r).  Not renormalised on the grid."""
+    nr = int(n[0])
+    nz = int(n[1]) if geom == SYM_AXI else 1
+    r = radial_coords(nr, dx[0])
+    w = omega[0]
+    if geom == SYM_CIR:
+        psi = (w / math.pi) ** 0.5 * np.exp(-0.5 * w * r * r)[None, :]
+    elif geom == SYM_SPH:
+        psi = (w / math.pi) ** 0.75 * np.exp(-0.5 * w * r * r)[None, :]
+    else:
+        wz = omega[1]
+        z = coords(nz, dx[1]) - z_shift
+        psi = ((w / math.pi) ** 0.5 * np.exp(-0.5 * w * r * r)[None, :]
+               * ((wz / math.pi) ** 0.25 * np.exp(-0.5 * wz * z * z))[:, None])
+    psi = np.broadcast_to(psi, (nz, nr))
+    if noise > 0:
+        rng = np.random.default_rng(seed)
+        psi = psi + rng.uniform(-noise, noise, size=psi.shape)
+    return np.array(psi)
+
+
+def sym_mu_thomas_fermi(geom: int, g: float, omega) -> float:
+    """Thomas-Fermi chemical potential of a unit-norm condensate in the
+    symmetric trap (2D isotropic for circular, 3D otherwise)."""
+    w = omega[0]
+    if geom == SYM_CIR:
+        return math.sqrt(g * w * w / math.pi)
+    wz = w if geom == SYM_SPH else omega[1]
+    return 0.5 * (15.0 * g * w * w * wz / (4.0 * math.pi)) ** 0.4
+
+
+def sym_thomas_fermi(geom: int, n, dx, omega, g_init: float, phase_sigma: float = 0.0,
+                     seed: int = 1) -> np.ndarray:
+    """sqrt(max(mu_TF - V, 0) / g_init) (continuum-normalised by the choice of
+    mu_TF) times exp(i theta), theta ~ N(0, phase_sigma^2) iid per point.
+    Complex128, shape (n_z, n_r)."""
+    nr = int(n[0])
+    nz = int(n[1]) if geom == SYM_AXI else 1
+    r = radial_coords(nr, dx[0])
+    v = 0.5 * omega[0] ** 2 * r * r
+    if geom == SYM_AXI:
+        z = coords(nz, dx[1])
+        v = v[None, :] + (0.5 * omega[1] ** 2 * z * z)[:, None]
+    else:
+        v = v[None, :]
+    mu = sym_mu_thomas_fermi(geom, g_init, omega)
+    amp = np.sqrt(np.maximum(mu - v, 0.0) / g_init)
+    if phase_sigma > 0:
+        rng = np.random.default_rng(seed)
+        return amp * np.exp(1j * rng.normal(0.0, phase_sigma, size=amp.shape))
+    return amp.astype(np.complex128)
+
+
+# ---------------------------------------------------------------------------
 # Batch and serving draws
 # ---------------------------------------------------------------------------
 
