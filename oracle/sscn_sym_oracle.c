@@ -46,6 +46,11 @@
  *
  * Observables (the energy functional of the discrete Hamiltonian):
  *   N = <psi, psi>,  K = Re <psi, H_kin psi>,  P = <psi, V psi>,
+ *   where K is evaluated in its gradient form (summation by parts, an exact
+ *   identity): K = c dr (dz) [ 1/2 sum_j sum_faces F_f |psi_f - psi_{f-1}|^2 / dr^2
+ *   + 1/2 sum_i W_i sum_z-edges |psi_{j+1} - psi_j|^2 / dz^2 ], ghosts zero
+ *   (the operator form loses about eps * d_i / |H psi| to cancellation on
+ *   fine grids),
  *   I = c dr (dz) sum W |psi|^4,
  *   E = (K + P + g I / 2) / N,  mu = (K + P + g I) / N,
  *   moments <r>, <r^2> (radial), <z>, <z^2> (axial), divided by N.
@@ -264,27 +269,29 @@ static int ors_step(const ors_problem *pb, double complex *psi, long step_index)
 static void ors_observe_c(const ors_problem *pb, const double complex *psi, double *out)
 {
     const int nr = pb->n[0], nz = pb->n[1];
+    const double dr2 = pb->dx[0] * pb->dx[0];
+    const double dz2 = (pb->geom == ORS_AXI) ? pb->dx[1] * pb->dx[1] : 1.0;
     double s2 = 0, sk = 0, sp = 0, s4 = 0, mr = 0, mz = 0, mr2 = 0, mz2 = 0;
-    const double kz = (pb->geom == ORS_AXI) ? 1.0 / (2.0 * pb->dx[1] * pb->dx[1]) : 0.0;
     for (int j = 0; j < nz; ++j)
         for (int i = 0; i < nr; ++i) {
             long p = i + (long)nr * j;
             double complex v = psi[p];
             double w = ors_cell(pb, i);
             double q = creal(v) * creal(v) + cimag(v) * cimag(v);
-            double l, d, u;
-            ors_radial_coefs(pb, i, &l, &d, &u);
-            double complex left = (i > 0) ? psi[p - 1] : 0.0;
-            double complex right = (i + 1 < nr) ? psi[p + 1] : 0.0;
-            double complex hv = d * v - l * left - u * right;
+            /* the radial face above cell i (the ghost cell past the edge is 0) */
+            double complex up = (i + 1 < nr) ? psi[p + 1] : 0.0;
+            double complex dd = up - v;
+            sk += 0.5 * ors_face(pb, i + 1) * (creal(dd) * creal(dd) + cimag(dd) * cimag(dd)) / dr2;
             if (pb->geom == ORS_AXI) {
-                double complex lo = (j > 0) ? psi[p - nr] : 0.0;
+                /* the z edge above point j, and below the first point */
                 double complex hi = (j + 1 < nz) ? psi[p + nr] : 0.0;
-                hv += kz * (2.0 * v - lo - hi);
+                double complex dz = hi - v;
+                double e = creal(dz) * creal(dz) + cimag(dz) * cimag(dz);
+                if (j == 0) e += q;
+                sk += 0.5 * w * e / dz2;
             }
             double r = ors_r(pb, i), z = ors_z(pb, j);
             s2 += w * q;
-            sk += w * creal(conj(v) * hv);
             sp += w * ors_potential(pb, i, j) * q;
             s4 += w * q * q;
             mr += w * r * q;

@@ -59,6 +59,40 @@ def test_radial_operator_is_symmetric_in_its_inner_product(geom):
     np.testing.assert_allclose(d[:-1], l[:-1] + u[:-1], rtol=1e-15)
 
 
+@pytest.mark.parametrize("geom", [CIR, SPH])
+def test_kinetic_energy_is_the_operator_expectation(geom):
+    """K (evaluated in its gradient form) equals Re <psi, H_r psi> with H_r
+    the dense operator of the oracle's coefficients and the weighted inner
+    product c dr sum W conj(a) b (summation by parts)."""
+    n = 80
+    h = 0.1
+    prob = SymProblem(geom, (n, 1), (h, 1.0), (1.0, 0.0), 0.0, 0.01)
+    l, d, u, w = oracle.sym_coefs(prob)
+    H = np.diag(d) - np.diag(u[:-1], 1) - np.diag(l[1:], -1)
+    rng = np.random.default_rng(geom)
+    psi = (rng.normal(size=n) + 1j * rng.normal(size=n)) * np.exp(-0.02 * np.arange(n))
+    c = 4 * math.pi if geom == SPH else 2 * math.pi
+    want = c * h * np.real(np.sum(w * np.conj(psi) * (H @ psi)))
+    assert abs(oracle.sym_observe(prob, psi).K - want) <= 1e-12 * abs(want)
+
+
+@pytest.mark.parametrize("k", [1, 3, 7])
+def test_axial_kinetic_energy_of_a_z_sine_mode(k):
+    """psi = a(rho) sin(pi k (j+1)/(n_z+1)): the z factor is an exact
+    eigenvector of the Dirichlet 3-point Laplacian with eigenvalue
+    tau_k = 2 - 2 cos(pi k/(n_z+1)), so the axial trap's kinetic energy per
+    norm is the circular trap's for a(rho) plus tau_k/(2 dz^2) exactly."""
+    nr, nz, h, hz = 30, 25, 0.15, 0.2
+    rng = np.random.default_rng(k)
+    a = np.exp(-0.5 * inputs.radial_coords(nr, h) ** 2) * (1 + 0.2 * rng.uniform(size=nr))
+    j = np.arange(nz)
+    b = np.sin(math.pi * k * (j + 1) / (nz + 1))
+    ax = oracle.sym_observe(SymProblem(AXI, (nr, nz), (h, hz), (1.0, 1.0), 0.0, 0.01), b[:, None] * a[None, :])
+    ci = oracle.sym_observe(SymProblem(CIR, (nr, 1), (h, 1.0), (1.0, 0.0), 0.0, 0.01), a)
+    tau = 2 - 2 * math.cos(math.pi * k / (nz + 1))
+    assert abs(ax.K / ax.norm - (ci.K / ci.norm + tau / (2 * hz * hz))) <= 1e-12 * (ax.K / ax.norm)
+
+
 @pytest.mark.parametrize("geom", [CIR, SPH, AXI])
 def test_real_time_conserves_the_weighted_norm(geom):
     n = (60, 1) if geom != AXI else (30, 40)
