@@ -23,6 +23,26 @@
  *
  * Grid: axis a has n_a points at x_a(i) = (i - (n_a - 1)/2) dx_a; unused axes
  * (a >= dim) have n_a = 1.  Layout: x fastest, p = i + n_x (j + n_y k).
+ *
+ * Symmetric traps ("Nature of problem": circular symmetry in 2D, radial and
+ * axial symmetry in 3D; geom below).  Circular (2D) and spherical (3D):
+ * psi(r), one stored axis (dim = 1); axial (3D): psi(rho, z), two stored
+ * axes (dim = 2, axis 0 rho, axis 1 z).  The radial axis has n_0 cells
+ * [i dr, (i+1) dr] with values at r_i = (i + 1/2) dr; its Laplacian
+ * (1/r^k) d/dr (r^k d/dr), k = 1 (circular, axial) or 2 (spherical), is the
+ * finite-volume form
+ *     (Lap psi)_i = [F_{i+1} (psi_{i+1} - psi_i) - F_i (psi_i - psi_{i-1})] / (W_i dr^2)
+ * with face weights F_i = (i dr)^k (F_0 = 0: no flux through the origin)
+ * and cell weights W_i = r_i (k = 1) or r_i^2 + dr^2/12 (k = 2); psi = 0
+ * past the outer edge.  z is a Cartesian axis as above.  Inner product and
+ * norm: c dr (dz) sum W_i conj(a) b, c = 2 pi (circular, axial) or 4 pi
+ * (spherical).  A step is the pointwise substep with V = omega_0^2 r^2/2
+ * (+ omega_1^2 z^2/2, axial), then the Crank-Nicolson substep
+ * (1 + tau H_r) v = (1 - tau H_r) u along r, H_r = -Lap_r/2, tau = dt/2 or
+ * i dt/2 (a general tridiagonal system per radial line), then (axial) along
+ * z as on a Cartesian axis; in imaginary time the renormalisation in this
+ * norm.  Observables are those of this Hamiltonian in this inner product;
+ * mean/msq hold <r>, <r^2> (axis 0) and <z>, <z^2> (axis 1, axial).
  * State dtype by (mode, prec):
  *     IMAG + F64 -> double        IMAG + F32 -> float
  *     REAL + F64 -> double2 (re, im interleaved, like complex128)
@@ -49,7 +69,7 @@
 extern "C" {
 #endif
 
-#define SSCN_ABI_VERSION 1
+#define SSCN_ABI_VERSION 2
 
 /* status codes */
 #define SSCN_OK              0
@@ -67,6 +87,13 @@ extern "C" {
 #define SSCN_F64  0
 #define SSCN_F32  1
 
+/* trap geometry (sscn_problem.geom) */
+#define SSCN_GEOM_CART 0   /* anisotropic trap on a Cartesian grid of dim axes */
+#define SSCN_GEOM_CIR  1   /* 2D circular symmetry: psi(r), dim = 1 */
+#define SSCN_GEOM_SPH  2   /* 3D spherical symmetry: psi(r), dim = 1 */
+#define SSCN_GEOM_AXI  3   /* 3D axial symmetry: psi(rho, z), dim = 2 */
+#define SSCN_RADIAL_MAX 16384   /* longest radial axis (cells) */
+
 typedef struct {
     int32_t dim;            /* 1, 2 or 3 */
     int32_t n[3];           /* points per axis; axes >= dim must be 1 */
@@ -78,6 +105,8 @@ typedef struct {
     int32_t prec;           /* SSCN_F64 or SSCN_F32 */
     int32_t renorm_every;   /* IMAG: >= 1 (renormalise every k steps); REAL: 0 */
     int32_t observe_every;  /* >= 0; observation interval of sscn_run / batch */
+    int32_t geom;           /* SSCN_GEOM_*; 0 (Cartesian) for a zero-filled struct */
+    int32_t pad_;           /* 0 */
 } sscn_problem;
 
 typedef struct {
@@ -115,8 +144,10 @@ const char *sscn_status_string(int status);
  * not 1..3, an n_a < 1, n_a != 1 on an unused axis, dx_a <= 0 or non-finite
  * on a used axis, omega < 0 or non-finite, g non-finite, dt <= 0 or
  * non-finite, mode/prec out of range, renorm_every < 1 in IMAG or != 0 in
- * REAL, observe_every < 0.  SSCN_E_UNSUPPORTED if the grid exceeds this
- * build's limits (more than 2^40 points). */
+ * REAL, observe_every < 0, geom out of range, dim != 1 for the circular
+ * and spherical traps or != 2 for the axial trap.  SSCN_E_UNSUPPORTED if
+ * the grid exceeds this build's limits (more than 2^40 points, or a radial
+ * axis of more than SSCN_RADIAL_MAX cells). */
 int sscn_validate(const sscn_problem *pb);
 
 /* Systems call (admission by HBM footprint).
@@ -218,7 +249,8 @@ int sscn_set_g(sscn_solver *s, double g);
 int sscn_step_timed(sscn_solver *s, int64_t nsteps, double *ms);
 
 /* Systems call (autotuner).
- * Tile hints (used by the tuner): for problems of pb's shape (dim, n, mode,
+ * Tile hints (used by the tuner; Cartesian traps only, SSCN_E_UNSUPPORTED
+ * otherwise): for problems of pb's shape (dim, n, mode,
  * prec), use chunk[0] points per thread on x lines and chunk[1], chunk[2] on
  * y and z lines (powers of two <= 64; 0 keeps the default).  Applies to later
  * sscn_workspace_bytes / sscn_create calls of that shape, process-wide.
@@ -230,8 +262,9 @@ int sscn_clear_tile_hints(void);
 /* Systems call (autotuner, tests).
  * Kernel plan of a problem, 8 ints per axis (x, y, z): kind (0 ROW: lanes
  * along the line, 1 COL: lanes across lines, 2 one-thread-per-line
- * fallback, -1 unused axis), points per thread, waves per line group (ROW)
- * or per block (COL), lanes per line (COL; 1 otherwise), grid size, block
+ * fallback, 3 radial line per block, -1 unused axis), points per thread,
+ * waves per line group (ROW), per block (COL) or per line (radial), lanes
+ * per line (COL; 1 otherwise), grid size, block
  * size, first index of the constant tail of the Thomas table, and the scan
  * depth (ROW: shuffle steps; COL: preceding chunks folded).  info needs
  * cap >= 24 entries. */
@@ -247,7 +280,8 @@ int sscn_destroy(sscn_solver *s);
  * n[keep] doubles (1D) or of the two remaining axes' points in layout order
  * (2D, dim == 3 only).  Enqueued on the stream; FP64.  n_1D uses the
  * solver's workspace as scratch (stream-ordered with the steps, so it may
- * be called between sscn_step calls without a wait). */
+ * be called between sscn_step calls without a wait).  Cartesian traps
+ * only: SSCN_E_UNSUPPORTED for the symmetric ones. */
 int sscn_density_1d(sscn_solver *s, int keep, void *d_out);
 int sscn_density_2d(sscn_solver *s, int drop, void *d_out);
 
@@ -301,9 +335,10 @@ typedef struct {
 int sscn_batch_ctl_bytes(int32_t max_slots, int64_t max_items, size_t *bytes);
 
 /* Bytes of one instance's workspace in a batch (FP64 tables and partials).
- * SSCN_E_UNSUPPORTED unless prec == SSCN_F32 and the lines fit the
- * persistent kernel's tiles (x lines up to 16384 points in float and complex;
- * y and z lines up to 1024 (complex) / 2048 (float) points). */
+ * SSCN_E_UNSUPPORTED unless prec == SSCN_F32, geom == SSCN_GEOM_CART and
+ * the lines fit the persistent kernel's tiles (x lines up to 16384 points in
+ * float and complex; y and z lines up to 1024 (complex) / 2048 (float)
+ * points). */
 int sscn_batch_workspace_bytes(const sscn_problem *pb, size_t *bytes);
 
 /* Batch tile hints (used by the tuner): for instances of pb's shape (dim, n,

@@ -18,7 +18,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libsscn.so")
 ARCH = os.environ.get("SSCN_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["sscn_kernels.hip", "sscn_batch.hip", "sscn_api.cpp", "sscn_batch_api.cpp"]
+SOURCES = ["sscn_kernels.hip", "sscn_sym.hip", "sscn_batch.hip", "sscn_api.cpp", "sscn_batch_api.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

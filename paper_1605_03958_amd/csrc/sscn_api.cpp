@@ -18,6 +18,7 @@
 #include "sscn.h"
 #include "sscn_launch.hpp"
 #include "sscn_plan.hpp"
+#include "sscn_sym.hpp"
 
 using namespace sscn;
 
@@ -64,8 +65,78 @@ int validate(const sscn_problem *pb)
     if (pb->mode == SSCN_IMAG && pb->renorm_every < 1) return SSCN_E_INVALID;
     if (pb->mode == SSCN_REAL && pb->renorm_every != 0) return SSCN_E_INVALID;
     if (pb->observe_every < 0) return SSCN_E_INVALID;
+    if (pb->geom < SSCN_GEOM_CART || pb->geom > SSCN_GEOM_AXI || pb->pad_ != 0) return SSCN_E_INVALID;
+    if ((pb->geom == SSCN_GEOM_CIR || pb->geom == SSCN_GEOM_SPH) && pb->dim != 1) return SSCN_E_INVALID;
+    if (pb->geom == SSCN_GEOM_AXI && pb->dim != 2) return SSCN_E_INVALID;
     if (pts > 1099511627776.0) return SSCN_E_UNSUPPORTED;
+    if (pb->geom != SSCN_GEOM_CART && pb->n[0] > SSCN_RADIAL_MAX) return SSCN_E_UNSUPPORTED;
     return SSCN_OK;
+}
+
+double inner_dvol(const sscn_problem &pb)
+{
+    double dv = 1.0;
+    for (int a = 0; a < pb.dim; ++a) dv *= pb.dx[a];
+    constexpr double kPi = 3.14159265358979323846;
+    if (pb.geom == SSCN_GEOM_SPH) dv *= 4.0 * kPi;
+    else if (pb.geom != SSCN_GEOM_CART) dv *= 2.0 * kPi;
+    return dv;
+}
+
+// Radial cell weights W_i = (1/dr) * integral of r^k over cell i.
+void rad_weights(const sscn_problem &pb, std::vector<double> &w)
+{
+    const int n = pb.n[0];
+    const double h = pb.dx[0];
+    w.resize(n);
+    for (int i = 0; i < n; ++i) {
+        const double r = (i + 0.5) * h;
+        w[i] = (pb.geom == SSCN_GEOM_SPH) ? r * r + h * h / 12.0 : r;
+    }
+}
+
+// Radial table (layout in sscn_sym.hpp): the finite-volume operator
+// H_r psi_i = d_i psi_i - l_i psi_{i-1} - u_i psi_{i+1} with
+// l_i = F_i / (2 dr^2 W_i), u_i = F_{i+1} / (2 dr^2 W_i), d_i = l_i + u_i,
+// F_i = (i dr)^k, and the Thomas elimination of (1 + tau H_r) v = rhs in FP64:
+// m_i = 1 / (1 + tau d_i - tau l_i * tau u_{i-1} m_{i-1}), alpha_i = tau l_i m_i,
+// beta_i = tau u_i m_i.
+void build_rad_table(const sscn_problem &pb, const Plan &P, std::vector<double> &out)
+{
+    const AxisPlan &X = P.ax[0];
+    const int n = X.n, G = X.block, C = X.C, Q = G * C;
+    const double h = pb.dx[0], theta = 0.5 * pb.dt;
+    const std::complex<double> tau = (pb.mode == SSCN_REAL) ? std::complex<double>(0.0, theta)
+                                                             : std::complex<double>(theta, 0.0);
+    const int k = (pb.geom == SSCN_GEOM_SPH) ? 2 : 1;
+    auto face = [&](int i) { const double f = i * h; return k == 1 ? f : f * f; };
+    std::vector<double> w;
+    rad_weights(pb, w);
+    out.assign((size_t)RQ_N * Q, 0.0);
+    std::complex<double> m_prev = 0.0, tu_prev = 0.0;
+    for (int i = 0; i < n; ++i) {
+        const double l = face(i) / (2.0 * h * h * w[i]);
+        const double u = face(i + 1) / (2.0 * h * h * w[i]);
+        const double d = l + u;
+        const std::complex<double> tl = tau * l, tu = tau * u;
+        const std::complex<double> den = 1.0 + tau * d - (i > 0 ? tl * tu_prev * m_prev : 0.0);
+        const std::complex<double> m = 1.0 / den;
+        const std::complex<double> al = tl * m, be = tu * m;
+        const int t = i / C, kk = i - t * C;
+        const size_t s = (size_t)kk * G + t;
+        out[RQ_MR * (size_t)Q + s] = m.real();
+        out[RQ_MI * (size_t)Q + s] = m.imag();
+        out[RQ_AR * (size_t)Q + s] = al.real();
+        out[RQ_AI * (size_t)Q + s] = al.imag();
+        out[RQ_BR * (size_t)Q + s] = be.real();
+        out[RQ_BI * (size_t)Q + s] = be.imag();
+        out[RQ_L * (size_t)Q + s] = theta * l;
+        out[RQ_D * (size_t)Q + s] = theta * d;
+        out[RQ_U * (size_t)Q + s] = theta * u;
+        out[RQ_W * (size_t)Q + s] = w[i];
+        m_prev = m;
+        tu_prev = tu;
+    }
 }
 
 void thomas_coefs(double s_re, double s_im, int n, std::vector<double> &m_re, std::vector<double> &m_im,
@@ -152,6 +223,25 @@ int make_plan(const sscn_problem &pb, const TileOverride *ov, Plan &P)
         X.sig_re = imag ? s : 0.0;
         X.sig_im = imag ? 0.0 : s;
         X.kind = K_STREAM;
+        if (a == 0 && pb.geom != SSCN_GEOM_CART) {
+            // radial axis: one line per block, C cells per thread, up to 16
+            // waves (k_rad); the table is RQ_N doubles per padded cell
+            X.kind = K_RAD;
+            X.C = n <= 4096 ? 4 : (n <= 8192 ? 8 : 16);
+            X.wpl = (int)ceil_div(n, 64 * (int64_t)X.C);
+            X.block = 64 * X.wpl;
+            X.grid = (int)X.nlines;
+            X.lds = 0;
+            X.m1 = (int)ny;
+            X.s1 = nx;
+            X.s2 = nx * ny;
+            X.stride = 1;
+            X.tab_entries = ceil_div((int64_t)RQ_N * X.block * X.C * (int64_t)sizeof(double),
+                                     (int64_t)sizeof(TabEntry));
+            X.i_conv = X.n;
+            X.depth = 0;
+            continue;
+        }
         if (a == 0) {
             X.m1 = (int)ny;
             X.s1 = nx;
@@ -226,6 +316,9 @@ int make_plan(const sscn_problem &pb, const TileOverride *ov, Plan &P)
         if (X.grid > 2147483647 / 2) return SSCN_E_UNSUPPORTED;
     }
     const AxisPlan &L = P.ax[pb.dim - 1];
+    // the axial trap's z sweep weighs its norm terms in the last sweep's
+    // kernel, which only the COL kernel does
+    if (pb.geom == SSCN_GEOM_AXI && L.kind != K_COL) return SSCN_E_UNSUPPORTED;
     P.sep_pointwise = P.ax[0].kind == K_STREAM;
     P.sep_norm = imag && L.kind == K_STREAM;
     P.pw_grid = (int)std::min<int64_t>(ceil_div(P.npts, 256), 4096);
@@ -240,6 +333,11 @@ int make_plan(const sscn_problem &pb, const TileOverride *ov, Plan &P)
     for (int a = 0; a < pb.dim; ++a) {
         P.ax[a].tab_off = off;
         off = align256(off + P.ax[a].tab_entries * sizeof(TabEntry));
+    }
+    P.off_wline = 0;
+    if (pb.geom == SSCN_GEOM_AXI) {
+        P.off_wline = off;
+        off = align256(off + (size_t)pb.n[0] * sizeof(double));
     }
     P.off_part = off;
     off = align256(off + (size_t)P.np_norm * sizeof(double));
@@ -296,7 +394,7 @@ static std::vector<HintEntry> g_hints;
 
 static bool hint_match(const HintEntry &h, const sscn_problem &pb)
 {
-    return h.dim == pb.dim && h.n[0] == pb.n[0] && h.n[1] == pb.n[1] && h.n[2] == pb.n[2] &&
+    return pb.geom == SSCN_GEOM_CART && h.dim == pb.dim && h.n[0] == pb.n[0] && h.n[1] == pb.n[1] && h.n[2] == pb.n[2] &&
            h.mode == pb.mode && h.prec == pb.prec;
 }
 
@@ -383,6 +481,7 @@ static ColArgs col_args(sscn_solver *s, int a, bool last)
     c.sig_re = X.sig_re;
     c.sig_im = X.sig_im;
     c.partial = last ? reinterpret_cast<double *>(s->ws + s->P.off_part) : nullptr;
+    c.wline = (last && s->P.off_wline) ? reinterpret_cast<const double *>(s->ws + s->P.off_wline) : nullptr;
     return c;
 }
 
@@ -440,6 +539,23 @@ static hipError_t enqueue_step(sscn_solver *s, bool do_renorm, Timer *tm)
             r.scale = scal;
             r.partial = last ? part : nullptr;
             CHK(launch_row(P.elem, X.C, last, r, X.grid, X.block, X.lds, s->st, e0, e1));
+        } else if (X.kind == K_RAD) {
+            const bool rlast = imag && do_renorm && dim == 1;
+            RadArgs r;
+            r.psi = s->psi;
+            r.tab = reinterpret_cast<const double *>(s->ws + X.tab_off);
+            r.n = X.n;
+            r.dt = pb.dt;
+            r.g = s->g;
+            r.dr = pb.dx[0];
+            r.w2h_r = 0.5 * pb.omega[0] * pb.omega[0];
+            const bool axial = pb.geom == SSCN_GEOM_AXI;
+            r.dz = axial ? pb.dx[1] : 0.0;
+            r.cen_z = axial ? 0.5 * (pb.n[1] - 1) : 0.0;
+            r.w2h_z = axial ? 0.5 * pb.omega[1] * pb.omega[1] : 0.0;
+            r.scale = scal;
+            r.partial = rlast ? part : nullptr;
+            CHK(launch_rad(P.elem, X.C, rlast, r, X.grid, X.block, s->st, e0, e1));
         } else {
             PointArgs pa;
             pa.psi = s->psi;
@@ -469,9 +585,7 @@ static hipError_t enqueue_step(sscn_solver *s, bool do_renorm, Timer *tm)
         if (e0) CHK(hipEventRecord(e0, s->st));
         if (do_renorm && P.sep_norm)
             CHK(launch_norm_partials(P.elem, s->psi, P.npts, part, P.pw_grid, 256, s->st));
-        double dv = 1.0;
-        for (int a = 0; a < dim; ++a) dv *= pb.dx[a];
-        CHK(launch_norm_final(part, P.np_norm, dv, do_renorm ? 1 : 0, scal, s->st));
+        CHK(launch_norm_final(part, P.np_norm, inner_dvol(pb), do_renorm ? 1 : 0, scal, s->st));
         if (e1) CHK(hipEventRecord(e1, s->st));
     }
 #undef CHK
@@ -635,6 +749,7 @@ int sscn_set_tile_hint(const sscn_problem *pb, const int32_t chunk[3])
 {
     int v = validate(pb);
     if (v != SSCN_OK) return v;
+    if (pb->geom != SSCN_GEOM_CART) return SSCN_E_UNSUPPORTED;
     if (!chunk) return SSCN_E_INVALID;
     for (int a = 0; a < 3; ++a) {
         const int c = chunk[a];
@@ -691,7 +806,7 @@ int sscn_plan_info(const sscn_problem *pb, int32_t *info, int32_t cap)
         int32_t *o = info + 8 * a;
         o[0] = used ? X.kind : -1;
         o[1] = used ? X.C : 0;
-        o[2] = used ? (X.kind == K_ROW ? X.wpl : X.W) : 0;
+        o[2] = used ? ((X.kind == K_ROW || X.kind == K_RAD) ? X.wpl : X.W) : 0;
         o[3] = used ? (X.kind == K_COL ? X.L : 1) : 0;
         o[4] = used ? X.grid : 0;
         o[5] = used ? X.block : 0;
@@ -753,8 +868,19 @@ static int create_solver(const sscn_problem *pb, void *d_psi, void *d_ws, void *
         scal[1] = 1.0;
         std::vector<TabEntry> tab;
         for (int a = 0; a < pb->dim; ++a) {
+            if (s->P.ax[a].kind == K_RAD) {
+                std::vector<double> rt;
+                build_rad_table(*pb, s->P, rt);
+                std::memcpy(img.data() + s->P.ax[a].tab_off, rt.data(), rt.size() * sizeof(double));
+                continue;
+            }
             build_table(*pb, s->P, a, tab);
             std::memcpy(img.data() + s->P.ax[a].tab_off, tab.data(), tab.size() * sizeof(TabEntry));
+        }
+        if (s->P.off_wline) {
+            std::vector<double> w;
+            rad_weights(*pb, w);
+            std::memcpy(img.data() + s->P.off_wline, w.data(), w.size() * sizeof(double));
         }
         if (hipMemcpyAsync(s->ws, img.data(), img.size(), hipMemcpyHostToDevice, s->st) != hipSuccess ||
             hipStreamSynchronize(s->st) != hipSuccess) {
@@ -883,6 +1009,29 @@ int sscn_step_timed(sscn_solver *s, int64_t nsteps, double *ms)
 static hipError_t obs_enqueue(sscn_solver *s, double **dobs_out)
 {
     const Plan &P = s->P;
+    double *dobs = reinterpret_cast<double *>(s->ws + P.off_obs);
+    *dobs_out = dobs;
+    if (s->pb.geom != SSCN_GEOM_CART) {
+        const sscn_problem &pb = s->pb;
+        const bool axial = pb.geom == SSCN_GEOM_AXI;
+        SymObsArgs so;
+        std::memset(&so, 0, sizeof(so));
+        so.psi = s->psi;
+        so.nr = pb.n[0];
+        so.nz = axial ? pb.n[1] : 1;
+        so.k = (pb.geom == SSCN_GEOM_SPH) ? 2 : 1;
+        so.axial = axial ? 1 : 0;
+        so.dr = pb.dx[0];
+        so.dz = axial ? pb.dx[1] : 0.0;
+        so.cen_z = axial ? 0.5 * (pb.n[1] - 1) : 0.0;
+        so.w2h_r = 0.5 * pb.omega[0] * pb.omega[0];
+        so.w2h_z = axial ? 0.5 * pb.omega[1] * pb.omega[1] : 0.0;
+        so.npts = P.npts;
+        so.partial = reinterpret_cast<double *>(s->ws + P.off_obspart);
+        hipError_t e = launch_sym_obs_partials(P.elem, so, P.obs_grid, 256, s->st);
+        if (e == hipSuccess) e = launch_obs_final(so.partial, P.obs_grid, inner_dvol(pb), s->g, dobs, s->st);
+        return e;
+    }
     ObsArgs oa;
     std::memset(&oa, 0, sizeof(oa));
     oa.psi = s->psi;
@@ -897,10 +1046,8 @@ static hipError_t obs_enqueue(sscn_solver *s, double **dobs_out)
     }
     oa.npts = P.npts;
     oa.partial = reinterpret_cast<double *>(s->ws + P.off_obspart);
-    double *dobs = reinterpret_cast<double *>(s->ws + P.off_obs);
     hipError_t e = launch_obs_partials(P.elem, oa, P.obs_grid, 256, s->st);
     if (e == hipSuccess) e = launch_obs_final(oa.partial, P.obs_grid, dv, s->g, dobs, s->st);
-    *dobs_out = dobs;
     return e;
 }
 
@@ -1054,6 +1201,7 @@ int sscn_destroy(sscn_solver *s)
 int sscn_density_1d(sscn_solver *s, int keep, void *d_out)
 {
     if (!s || !d_out || keep < 0 || keep >= s->pb.dim) return SSCN_E_INVALID;
+    if (s->pb.geom != SSCN_GEOM_CART) return SSCN_E_UNSUPPORTED;
     double w = 1.0;
     for (int a = 0; a < s->pb.dim; ++a)
         if (a != keep) w *= s->pb.dx[a];
@@ -1068,6 +1216,7 @@ int sscn_density_1d(sscn_solver *s, int keep, void *d_out)
 int sscn_density_2d(sscn_solver *s, int drop, void *d_out)
 {
     if (!s || !d_out || s->pb.dim != 3 || drop < 0 || drop > 2) return SSCN_E_INVALID;
+    if (s->pb.geom != SSCN_GEOM_CART) return SSCN_E_UNSUPPORTED;
     return launch_density_2d(s->P.elem, s->psi, s->pb.n, drop, s->pb.dx[drop], static_cast<double *>(d_out),
                              s->st) == hipSuccess
                ? SSCN_OK

@@ -295,6 +295,7 @@ int batch_validate(const sscn_problem *pb)
     int v = validate(pb);
     if (v != SSCN_OK) return v;
     if (pb->prec != SSCN_F32) return SSCN_E_UNSUPPORTED;  // the batch runs the FP32 forms
+    if (pb->geom != SSCN_GEOM_CART) return SSCN_E_UNSUPPORTED;  // and the Cartesian traps
     if (pb->mode == SSCN_IMAG && pb->renorm_every != 1) return SSCN_E_INVALID;
     if (pb->observe_every < 1) return SSCN_E_INVALID;
     return SSCN_OK;

@@ -121,10 +121,11 @@ __global__ void __launch_bounds__(1024) k_col(ColArgs a)
     long long base = 0;
     if (active) base = (line % a.m1) * a.s1 + (line / a.m1) * a.s2;
     stage_table<T, CPLX>(a.lt, tb, nch * C, 0, C);
-    const double nacc = col_tile<T, CPLX, C>(reinterpret_cast<V *>(a.psi), active, base, a.lt.n, a.stride, nch, ch,
-                                             LPB, li, tb, xs0, xs1, A::coef(a.sig_re, a.sig_im), a.lt.depth,
-                                             LAST);
+    double nacc = col_tile<T, CPLX, C>(reinterpret_cast<V *>(a.psi), active, base, a.lt.n, a.stride, nch, ch,
+                                       LPB, li, tb, xs0, xs1, A::coef(a.sig_re, a.sig_im), a.lt.depth, LAST);
     if constexpr (LAST) {
+        // the axial trap weighs each z line by its radial cell weight
+        if (a.wline && active) nacc *= a.wline[line % a.m1];
         const double s = block_sum(nacc, red);
         if (threadIdx.x == 0) a.partial[blockIdx.x] = s;
     }

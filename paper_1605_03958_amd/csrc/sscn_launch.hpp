@@ -52,6 +52,7 @@ struct ColArgs {
     int32_t L;             // COL: lanes per line (chunks per line = W * L)
     double sig_re, sig_im;
     double *partial;
+    const double *wline;   // last sweep: weight of line l's norm terms at [l % m1] (axial trap), or null
 };
 
 struct PointArgs {

@@ -14,7 +14,7 @@
 
 namespace sscn {
 
-enum { K_ROW = 0, K_COL = 1, K_STREAM = 2 };
+enum { K_ROW = 0, K_COL = 1, K_STREAM = 2, K_RAD = 3 };
 
 struct AxisPlan {
     int kind;
@@ -47,6 +47,7 @@ struct Plan {
     int pw_grid, np_norm, obs_grid;
     int dens_blocks;       // row blocks of the n_1D-along-x partial sums
     size_t off_scal, off_obs, off_part, off_obspart, off_dens, ws_bytes;
+    size_t off_wline;      // axial trap: radial cell weights of the z lines (n_0 doubles)
 };
 
 // Chunk lengths chosen by the tuner for one shape (0 = default choice).
@@ -60,6 +61,13 @@ size_t elem_bytes(int elem);
 int validate(const sscn_problem *pb);
 int make_plan(const sscn_problem &pb, const TileOverride *ov, Plan &P);
 void build_table(const sscn_problem &pb, const Plan &P, int a, std::vector<TabEntry> &out);
+// Radial axis of a symmetric trap: its table in the layout k_rad reads
+// (sscn_sym.hpp) and the cell weights W_i.
+void build_rad_table(const sscn_problem &pb, const Plan &P, std::vector<double> &out);
+void rad_weights(const sscn_problem &pb, std::vector<double> &w);
+// The inner product's volume factor: prod dx (Cartesian), times 2 pi
+// (circular, axial) or 4 pi (spherical).
+double inner_dvol(const sscn_problem &pb);
 // Constant-tail index, constant entry and scan depth of an axis whose kind,
 // n, C, W, L and sigma are set.
 void table_meta(AxisPlan &X, bool fp32);

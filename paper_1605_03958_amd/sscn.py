@@ -21,6 +21,7 @@ OK, NOT_CONVERGED, BUSY = 0, 1, 2
 E_INVALID, E_HIP, E_NONFINITE, E_NOSPACE, E_UNSUPPORTED = -1, -2, -3, -4, -5
 IMAG, REAL = 0, 1
 F64, F32 = 0, 1
+GEOM_CART, GEOM_CIR, GEOM_SPH, GEOM_AXI = 0, 1, 2, 3
 NKERNELS = 5
 KERNEL_CLASSES = ("x_sweep_pointwise", "y_sweep", "z_sweep_norm", "norm_final", "scale_pass")
 
@@ -43,6 +44,8 @@ class CProblem(ctypes.Structure):
         ("prec", ctypes.c_int32),
         ("renorm_every", ctypes.c_int32),
         ("observe_every", ctypes.c_int32),
+        ("geom", ctypes.c_int32),
+        ("pad_", ctypes.c_int32),
     ]
 
 
@@ -166,6 +169,7 @@ class Problem:
     prec: int = F64
     renorm_every: int = 1
     observe_every: int = 0
+    geom: int = GEOM_CART
 
     def __post_init__(self):
         self.n = tuple(int(v) for v in (list(self.n) + [1, 1, 1])[:3])
@@ -185,6 +189,8 @@ class Problem:
         p.prec = int(self.prec)
         p.renorm_every = int(self.renorm_every)
         p.observe_every = int(self.observe_every)
+        p.geom = int(self.geom)
+        p.pad_ = 0
         return p
 
     @property
@@ -234,7 +240,7 @@ def plan_info(prob: Problem):
     pc = prob.c()
     info = (ctypes.c_int32 * 24)()
     _check(lib().sscn_plan_info(ctypes.byref(pc), info, 24), "sscn_plan_info")
-    kinds = {0: "row", 1: "col", 2: "stream", -1: None}
+    kinds = {0: "row", 1: "col", 2: "stream", 3: "rad", -1: None}
     out = []
     for a in range(3):
         o = info[8 * a: 8 * a + 8]

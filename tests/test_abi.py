@@ -34,7 +34,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_abi_version_and_status_strings():
     L = sscn.lib()
-    assert L.sscn_abi_version() == 1
+    assert L.sscn_abi_version() == 2
     for code in (0, 1, -1, -2, -3, -4, -5, 99):
         assert isinstance(sscn.status_string(code), str) and sscn.status_string(code)
 
@@ -306,3 +306,31 @@ def test_dynamics_pipeline_host_checks():
         dynamics.ground_state_then_dynamics(q, np.zeros(64), 0.5, -1, 1e-3)
     o = sscn.Obs(0, 1.0, 0.0, 0.0, 0.0, 0.0, 0.0, (0.0, 0.0, 0.0), (4.0, 9.0, 0.0))
     assert dynamics.rms_sizes(o, 2) == (2.0, 3.0, math.sqrt(13.0))
+
+
+def test_symmetric_trap_validation_and_plan():
+    """Circular and spherical traps store one radial axis, the axial trap
+    two (rho, z); radial axes are limited to SSCN_RADIAL_MAX cells; the
+    batch, the densities' shapes and the tile hints are Cartesian only; the
+    plan puts the radial axis on the line-per-block kernel."""
+    G = sscn
+    ok = Problem(1, (500, 1, 1), (0.02,), (1.0,), 5.0, 1e-4, IMAG, F64, 1, geom=G.GEOM_CIR)
+    assert sscn.validate(ok) == sscn.OK
+    for bad in (Problem(2, (50, 40, 1), (0.1, 0.1), (1.0, 1.0), 5.0, 1e-4, IMAG, F64, 1, geom=G.GEOM_SPH),
+                Problem(1, (50, 1, 1), (0.1,), (1.0,), 5.0, 1e-4, IMAG, F64, 1, geom=G.GEOM_AXI),
+                Problem(1, (50, 1, 1), (0.1,), (1.0,), 5.0, 1e-4, IMAG, F64, 1, geom=7)):
+        assert sscn.validate(bad) == sscn.E_INVALID
+    big = Problem(1, (16385, 1, 1), (0.01,), (1.0,), 5.0, 1e-4, IMAG, F64, 1, geom=G.GEOM_SPH)
+    assert sscn.validate(big) == sscn.E_UNSUPPORTED
+    ax = Problem(2, (100, 70, 1), (0.1, 0.2), (1.0, 2.0), 5.0, 1e-4, REAL, F64, 0, geom=G.GEOM_AXI)
+    info = sscn.plan_info(ax)
+    assert info[0]["kind"] == "rad" and info[0]["grid"] == 70 and info[0]["block"] * info[0]["chunk"] >= 100
+    assert info[1]["kind"] == "col"
+    assert sscn.workspace_bytes(ax) > 0
+    batch = Problem(1, (500, 1, 1), (0.02,), (1.0,), 5.0, 1e-4, IMAG, F32, 1, 10, geom=G.GEOM_CIR)
+    with pytest.raises(sscn.SSCNError) as e:
+        sscn.batch_workspace_bytes(batch)
+    assert e.value.code == sscn.E_UNSUPPORTED
+    with pytest.raises(sscn.SSCNError) as e:
+        sscn.set_tile_hint(ok, (4, 0, 0))
+    assert e.value.code == sscn.E_UNSUPPORTED
