@@ -290,6 +290,56 @@ def density_timing(reps: int = 5):
             **out}
 
 
+def sym_timing(steps: int = 2000):
+    """The symmetric traps: circular and spherical lines of 4096 cells
+    (dr = 8/4096) in imaginary time (FP64, dt = 0.1 dr^2, g = 50,
+    renormalised every step) -- one radial line, so latency-bound: us per
+    step -- and an axial grid of 512 x 1024 (rho x z) in real time
+    (complex128, dt = 0.02 dr^2, g = 50): grid-point-steps/s and the step's
+    fraction of 8 TB/s at 2 x 2 x 16 bytes per point-step."""
+    import torch
+    from paper_1605_03958_amd import inputs, sscn
+    out = {}
+    for name, geom in (("cir4096_imag_f64", sscn.GEOM_CIR), ("sph4096_imag_f64", sscn.GEOM_SPH)):
+        n = 4096
+        dr = 8.0 / n
+        p = sscn.Problem(1, (n, 1, 1), (dr,), (1.0,), 50.0, 0.1 * dr * dr, sscn.IMAG, sscn.F64, 1, geom=geom)
+        psi0 = inputs.sym_gaussian(geom, (n, 1), (dr, 1.0), (1.0, 0.0), noise=1e-3, seed=0)
+        s = sscn.Solver(p, psi0.reshape(p.shape))
+        s.step(64)
+        s.prepare(steps)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        k = s.step_timed(200)
+        s.close()
+        out[name] = {"us_per_step": 1e6 * el / steps, "kernel_us": {kk: round(1e3 * v, 2) for kk, v in k.items() if v}}
+    nr, nz = 512, 1024
+    dr, dz = 8.0 / nr, 16.0 / nz
+    p = sscn.Problem(2, (nr, nz, 1), (dr, dz), (1.0, 1.6), 50.0, 0.02 * dr * dr, sscn.REAL, sscn.F64, 0,
+                     geom=sscn.GEOM_AXI)
+    psi0 = inputs.sym_thomas_fermi(sscn.GEOM_AXI, (nr, nz), (dr, dz), (1.0, 1.6), 60.0, phase_sigma=0.05, seed=1)
+    s = sscn.Solver(p, psi0.reshape(p.shape))
+    s.step(64)
+    s.prepare(steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    k = s.step_timed(200)
+    s.close()
+    pts = nr * nz
+    out["axi512x1024_real_c128"] = {"us_per_step": 1e6 * el / steps, "ptsteps_per_s": pts * steps / el,
+                                    "hbm_frac": 2 * 2 * 16 * pts * steps / el / (HBM_PEAK_GBS * 1e9),
+                                    "kernel_us": {kk: round(1e3 * v, 2) for kk, v in k.items() if v}}
+    out["workload"] = ("symmetric traps: circular/spherical 4096-cell radial lines, imaginary time FP64; "
+                       "axial 512x1024 real time complex128")
+    return out
+
+
 def mix64_problems():
     """The 64-instance uneven batch: 22 1D, 21 2D, 21 3D draws (seeds 100+i),
     imaginary time in FP32 with FP64 reductions, dt = 0.1 dx^2."""
@@ -441,7 +491,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp32", action="store_true")
-    ap.add_argument("--only", choices=["fp64", "fp32", "batch", "densities", "dynamics"], default=None,
+    ap.add_argument("--only", choices=["fp64", "fp32", "batch", "densities", "dynamics", "sym"], default=None,
                     help="run only one precision, the batch, the densities or the dynamics pipeline "
                          "(profiling runs)")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance batch")
@@ -468,6 +518,9 @@ def main():
         return
     if args.only == "dynamics":
         print(json.dumps({"dynamics128": dynamics_timing()}), flush=True)
+        return
+    if args.only == "sym":
+        print(json.dumps({"symmetric": sym_timing()}), flush=True)
         return
     out = {}
     precs = [sscn.F64, sscn.F32]
@@ -540,6 +593,7 @@ def main():
         res["imag256"] = imag256_timing()
         res["dynamics128"] = dynamics_timing()
         res["densities256"] = density_timing()
+        res["symmetric"] = sym_timing()
     if args.only is None and not args.no_batch:
         res["batch"] = batch_mix64()
     if args.only is None and not args.no_serve:

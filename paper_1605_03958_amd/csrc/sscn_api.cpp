@@ -320,6 +320,9 @@ int make_plan(const sscn_problem &pb, const TileOverride *ov, Plan &P)
     // kernel, which only the COL kernel does
     if (pb.geom == SSCN_GEOM_AXI && L.kind != K_COL) return SSCN_E_UNSUPPORTED;
     P.sep_pointwise = P.ax[0].kind == K_STREAM;
+    // a one-line radial sweep that renormalises every step finalises the
+    // norm in its own (single) block
+    P.fused_norm = imag && pb.renorm_every == 1 && pb.dim == 1 && P.ax[0].kind == K_RAD && P.ax[0].grid == 1;
     P.sep_norm = imag && L.kind == K_STREAM;
     P.pw_grid = (int)std::min<int64_t>(ceil_div(P.npts, 256), 4096);
     P.np_norm = P.sep_norm ? P.pw_grid : L.grid;
@@ -555,6 +558,8 @@ static hipError_t enqueue_step(sscn_solver *s, bool do_renorm, Timer *tm)
             r.w2h_z = axial ? 0.5 * pb.omega[1] * pb.omega[1] : 0.0;
             r.scale = scal;
             r.partial = rlast ? part : nullptr;
+            r.scalars = (rlast && P.fused_norm) ? scal : nullptr;
+            r.dvol = inner_dvol(pb);
             CHK(launch_rad(P.elem, X.C, rlast, r, X.grid, X.block, s->st, e0, e1));
         } else {
             PointArgs pa;
@@ -580,7 +585,7 @@ static hipError_t enqueue_step(sscn_solver *s, bool do_renorm, Timer *tm)
             if (e1) CHK(hipEventRecord(e1, s->st));
         }
     }
-    if (imag) {
+    if (imag && !P.fused_norm) {
         if (tm) tm->pair(3, e0, e1);
         if (e0) CHK(hipEventRecord(e0, s->st));
         if (do_renorm && P.sep_norm)

@@ -44,6 +44,7 @@ struct Plan {
     int64_t npts;
     AxisPlan ax[3];
     bool sep_pointwise, sep_norm;
+    bool fused_norm;       // the last sweep's single block also finalises the norm
     int pw_grid, np_norm, obs_grid;
     int dens_blocks;       // row blocks of the n_1D-along-x partial sums
     size_t off_scal, off_obs, off_part, off_obspart, off_dens, ws_bytes;

@@ -98,10 +98,39 @@ __device__ __forceinline__ typename Alg<T, CPLX>::V chunk_incoming(typename Alg<
     return A::fma(ea, x, eb);
 }
 
-template <class T, bool CPLX>
-__device__ __forceinline__ typename Alg<T, CPLX>::V rad_coef(const double *tab, int qre, int qim, int Q, int s)
+// The table entries of a thread's C cells: with PRE (short chunks) all of
+// them are loaded into registers at the start of the kernel, so their
+// latency overlaps the state's load instead of adding a round trip to each
+// phase; otherwise each phase loads what it needs.
+template <int C, bool PRE>
+struct RadTab {
+    const double *tab;
+    int Q, G, t;
+    double v[PRE ? RQ_N : 1][PRE ? C : 1];
+    __device__ __forceinline__ void init(const double *tb, int q, int g, int th)
+    {
+        tab = tb;
+        Q = q;
+        G = g;
+        t = th;
+        if constexpr (PRE) {
+#pragma unroll
+            for (int qq = 0; qq < RQ_N; ++qq)
+#pragma unroll
+                for (int k = 0; k < C; ++k) v[qq][k] = tab[qq * Q + k * G + t];
+        }
+    }
+    __device__ __forceinline__ double at(int q, int k) const
+    {
+        if constexpr (PRE) return v[q][k];
+        else return tab[q * Q + k * G + t];
+    }
+};
+
+template <class T, bool CPLX, class TB>
+__device__ __forceinline__ typename Alg<T, CPLX>::V rad_coef(const TB &tb, int qre, int qim, int k)
 {
-    return Alg<T, CPLX>::coef(tab[qre * Q + s], CPLX ? tab[qim * Q + s] : 0.0);
+    return Alg<T, CPLX>::coef(tb.at(qre, k), CPLX ? tb.at(qim, k) : 0.0);
 }
 
 template <class T, bool CPLX, int C, bool LAST>
@@ -116,7 +145,8 @@ __global__ void __launch_bounds__(1024) k_rad(RadArgs a)
     const int t = threadIdx.x, lane = t & 63, w = t >> 6, nw = G >> 6;
     const int Q = G * C;
     const int n = a.n;
-    const double *tab = a.tab;
+    RadTab<C, (C <= 4)> rt;
+    rt.init(a.tab, Q, G, t);
     V *psi = reinterpret_cast<V *>(a.psi) + (long long)blockIdx.x * n;
     const T scale = CPLX ? T(1) : T(*a.scale);
     const T dt = T(a.dt), g = T(a.g);
@@ -146,8 +176,7 @@ __global__ void __launch_bounds__(1024) k_rad(RadArgs a)
         V prev = left;
 #pragma unroll
         for (int k = 0; k < C; ++k) {
-            const int s = k * G + t;
-            const T L = T(tab[RQ_L * Q + s]), D = T(tab[RQ_D * Q + s]), U = T(tab[RQ_U * Q + s]);
+            const T L = T(rt.at(RQ_L, k)), D = T(rt.at(RQ_D, k)), U = T(rt.at(RQ_U, k));
             const V next = (k + 1 < C) ? u[k + 1] : right;
             const V x = A::sub(A::scal(D, u[k]), A::add(A::scal(L, prev), A::scal(U, next)));
             prev = u[k];
@@ -160,18 +189,16 @@ __global__ void __launch_bounds__(1024) k_rad(RadArgs a)
         V fa = A::one(), fb = A::zero();
 #pragma unroll
         for (int k = 0; k < C; ++k) {
-            const int s = k * G + t;
-            const V m = rad_coef<T, CPLX>(tab, RQ_MR, RQ_MI, Q, s);
-            const V al = rad_coef<T, CPLX>(tab, RQ_AR, RQ_AI, Q, s);
+            const V m = rad_coef<T, CPLX>(rt, RQ_MR, RQ_MI, k);
+            const V al = rad_coef<T, CPLX>(rt, RQ_AR, RQ_AI, k);
             fb = A::fma(al, fb, A::mul(m, u[k]));
             fa = A::mul(al, fa);
         }
         V d = chunk_incoming<T, CPLX, true>(fa, fb, ta, tb);
 #pragma unroll
         for (int k = 0; k < C; ++k) {
-            const int s = k * G + t;
-            const V m = rad_coef<T, CPLX>(tab, RQ_MR, RQ_MI, Q, s);
-            const V al = rad_coef<T, CPLX>(tab, RQ_AR, RQ_AI, Q, s);
+            const V m = rad_coef<T, CPLX>(rt, RQ_MR, RQ_MI, k);
+            const V al = rad_coef<T, CPLX>(rt, RQ_AR, RQ_AI, k);
             d = A::fma(al, d, A::mul(m, u[k]));
             u[k] = d;
         }
@@ -181,14 +208,14 @@ __global__ void __launch_bounds__(1024) k_rad(RadArgs a)
         V ba = A::one(), bb = A::zero();
 #pragma unroll
         for (int k = C - 1; k >= 0; --k) {
-            const V be = rad_coef<T, CPLX>(tab, RQ_BR, RQ_BI, Q, k * G + t);
+            const V be = rad_coef<T, CPLX>(rt, RQ_BR, RQ_BI, k);
             bb = A::fma(be, bb, u[k]);
             ba = A::mul(be, ba);
         }
         V v = chunk_incoming<T, CPLX, false>(ba, bb, ta, tb);
 #pragma unroll
         for (int k = C - 1; k >= 0; --k) {
-            const V be = rad_coef<T, CPLX>(tab, RQ_BR, RQ_BI, Q, k * G + t);
+            const V be = rad_coef<T, CPLX>(rt, RQ_BR, RQ_BI, k);
             v = A::fma(be, v, u[k]);
             u[k] = v;
         }
@@ -200,12 +227,20 @@ __global__ void __launch_bounds__(1024) k_rad(RadArgs a)
         const int i = t * C + k;
         if (i < n) {
             psi[i] = u[k];
-            if constexpr (LAST) nacc = fmaT(tab[RQ_W * Q + k * G + t], A::norm2(u[k]), nacc);
+            if constexpr (LAST) nacc = fmaT(rt.at(RQ_W, k), A::norm2(u[k]), nacc);
         }
     }
     if constexpr (LAST) {
         const double s = block_sum(nacc, red);
-        if (threadIdx.x == 0) a.partial[blockIdx.x] = s;
+        if (threadIdx.x == 0) {
+            a.partial[blockIdx.x] = s;
+            if (a.scalars) {
+                // every thread read the old factor before block_sum's barriers
+                const double N = a.dvol * s;
+                a.scalars[1] = N;
+                a.scalars[0] = 1.0 / sqrt(N);
+            }
+        }
     }
 }
 

@@ -27,6 +27,11 @@ struct RadArgs {
     double dz, cen_z, w2h_z;   // axial: line l at z = (l - cen_z) dz; 0 otherwise
     const double *scale;   // pending renormalisation factor (imaginary time)
     double *partial;       // last sweep: sum W |psi|^2 per block
+    // one-block sweeps that renormalise every step: also finalise here,
+    // as the norm's final sum would (scalars[1] = dvol * sum, scalars[0] =
+    // its inverse square root); null otherwise
+    double *scalars;
+    double dvol;
 };
 
 struct SymObsArgs {
