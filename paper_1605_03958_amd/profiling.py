@@ -113,6 +113,61 @@ def trace_only(args) -> None:
     print("\n".join(lines))
 
 
+def kernel_means(path: str, counter: str, match: str):
+    """Mean counter value over the dispatches whose kernel name contains
+    `match`, and their count."""
+    vals = [float(r["Counter_Value"]) for r in csv.DictReader(open(path))
+            if r["Counter_Name"] == counter and match in r["Kernel_Name"]]
+    return (sum(vals) / len(vals) if vals else float("nan")), len(vals)
+
+
+def largest_mean(path: str, counter: str, match: str) -> float:
+    """Mean counter value over the dispatches of `match` within 10 % of the
+    largest one."""
+    vals = [float(r["Counter_Value"]) for r in csv.DictReader(open(path))
+            if r["Counter_Name"] == counter and match in r["Kernel_Name"]]
+    top = max(vals)
+    big = [v for v in vals if v >= 0.9 * top]
+    return sum(big) / len(big)
+
+
+def batch_summary(args) -> None:
+    """HBM traffic of the persistent batch kernel (k_batch_step) against its
+    algorithmic bytes per launch (one step of every 2D and 3D instance of the
+    all-active mix), calibrated on the torch copy of --state-bytes."""
+    kib = 1024.0
+    S = args.state_bytes
+    # the calibration copy is the largest copy dispatch (admissions add small ones)
+    cf = largest_mean(_find(args.fetch, "counter_collection.csv"), "FETCH_SIZE", COPY_KERNEL)
+    cw = largest_mean(_find(args.write, "counter_collection.csv"), "WRITE_SIZE", COPY_KERNEL)
+    f_fetch, f_write = S / (cf * kib), S / (cw * kib)
+    stats = list(csv.DictReader(open(_find(args.trace, "kernel_stats.csv"))))
+    lines = [f"# rocprofv3 summary: {args.name}", "", f"Workload: `{args.workload}`.", "",
+             "Commands (run from the repository root on the MI355X machine):", "", "```", args.command.strip(), "```",
+             "", "## Kernel statistics (--kernel-trace --stats)", "",
+             "| kernel | calls | average us | min us | max us | share % |", "|---|---|---|---|---|---|"]
+    for r in stats[:8]:
+        lines.append(f"| `{r['Name'][:90]}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |")
+    lines += ["", "## HBM traffic per dispatch (FETCH_SIZE, WRITE_SIZE, calibrated)", "",
+              "| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM bytes / launch | algorithmic bytes / launch "
+              "| ratio |", "|---|---|---|---|---|---|---|"]
+    for match, alg in (("k_batch_step", args.alg_bytes), ("k_batch_solo", None)):
+        f, nf = kernel_means(_find(args.fetch, "counter_collection.csv"), "FETCH_SIZE", match)
+        w, _ = kernel_means(_find(args.write, "counter_collection.csv"), "WRITE_SIZE", match)
+        if nf == 0:
+            continue
+        tb = f * kib * f_fetch + w * kib * f_write
+        lines.append(f"| {match} | {nf} | {f:.0f} | {w:.0f} | {tb:.4g} | "
+                     f"{alg:.4g} | {tb / alg:.3f} |" if alg else
+                     f"| {match} | {nf} | {f:.0f} | {w:.0f} | {tb:.4g} | (steps vary per launch) | - |")
+    lines += ["", f"Calibration: the copy kernel `{COPY_KERNEL}` moves {S} bytes each way; factors "
+              f"{f_fetch:.4f} (FETCH_SIZE) and {f_write:.4f} (WRITE_SIZE).", ""]
+    with open(os.path.join(ROOT, "profiles", f"{args.name}.md"), "w") as fh:
+        fh.write("\n".join(lines))
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--trace", required=True)
@@ -122,7 +177,12 @@ def main():
     ap.add_argument("--state-bytes", type=int)
     ap.add_argument("--name", required=True)
     ap.add_argument("--command", default="")
+    ap.add_argument("--batch", action="store_true", help="summarise the persistent batch kernel")
+    ap.add_argument("--alg-bytes", type=float, default=0.0, help="algorithmic bytes per persistent launch")
     args = ap.parse_args()
+    if args.batch:
+        batch_summary(args)
+        return
     if not args.fetch or not args.write:
         trace_only(args)
         return
