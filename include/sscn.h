@@ -125,11 +125,42 @@ typedef struct {
 
 typedef struct sscn_solver sscn_solver;
 
+/* Physical inputs of a condensate ("Reasons for the new version" and
+ * "Summary of revisions": the programs take the number of atoms, the
+ * scattering length and the oscillator length of the trap, and compute the
+ * dimensionless nonlinearity they propagate with). */
+typedef struct {
+    int32_t dim;            /* 1, 2 or 3: dimensions of the propagated problem */
+    int32_t pad_;           /* 0 */
+    double  atoms;          /* N > 0 */
+    double  scattering_length;  /* a, in Bohr radii (any sign) */
+    double  mass;           /* atomic mass, in unified atomic mass units (> 0) */
+    double  omega;          /* reference angular trap frequency (rad/s, > 0): time unit 1/omega,
+                               length unit l = sqrt(hbar / (m omega)) */
+    double  tight[2];       /* frozen directions' trap frequencies over omega (> 0):
+                               dim 2: tight[0] (z); dim 1: tight[0], tight[1] (y, z); dim 3: unused */
+} sscn_units;
+
 /* Calls that carry no operation of the paper (version, status text, sizes,
  * timing, tile hints, plan queries, batching and its admission) are marked
  * "systems call" below: they serve the measurement, the autotuner and the
  * batched serving loop built around the method.  Every other call cites the
  * passage of the paper's program summary that defines what it computes. */
+
+/* "Reasons for the new version", "Summary of revisions" (physical inputs ->
+ * the dimensionless nonlinearity).  Host only.  In units of l and 1/omega
+ * the 3D equation has g = 4 pi N a / l; a problem of lower dimension is the
+ * 3D one with the frozen directions in their oscillator ground states
+ * (widths d = 1/sqrt(tight)), integrated out:
+ *     dim 3: g = 4 pi N a / l
+ *     dim 2: g = 4 pi N a / l * sqrt(tight[0] / (2 pi))
+ *     dim 1: g = 4 pi N a / l * sqrt(tight[0] tight[1]) / (2 pi)
+ * (the factors are the integrals of the frozen Gaussians' fourth power).
+ * The paper prints no formula; these are the standard reductions.  Writes g
+ * and, when non-NULL, l in metres and 1/omega in seconds.  SSCN_E_INVALID
+ * for a NULL pointer, dim out of range or a non-positive / non-finite
+ * input. */
+int sscn_units_to_g(const sscn_units *u, double *g, double *length_m, double *time_s);
 
 /* Systems call: SSCN_ABI_VERSION of the loaded library. */
 int sscn_abi_version(void);

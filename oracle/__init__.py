@@ -13,6 +13,7 @@ come back real-valued in complex storage.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 from dataclasses import dataclass, field
 
@@ -364,3 +365,32 @@ def sym_run(prob: SymProblem, psi, nsteps: int, observe_every: int = 0,
     if rc < 0:
         raise ValueError(f"ors_run rc={rc}")
     return RunResult(a, trace[: rows.value].copy(), int(done.value), rc == 0)
+
+
+# ---------------------------------------------------------------------------
+# physical units -> dimensionless nonlinearity
+# ---------------------------------------------------------------------------
+
+def units_to_g(dim: int, atoms: float, scattering_length_bohr: float, mass_amu: float, omega: float,
+               tight=(1.0, 1.0)):
+    """The nonlinearity of the dimensionless GP equation from physical inputs
+    (the paper's programs take the number of atoms, the scattering length
+    and the trap's oscillator length; "Reasons for the new version").  In
+    units of l = sqrt(hbar/(m omega)) the 3D coefficient is 4 pi N a / l; a
+    problem of lower dimension keeps the frozen directions in their
+    oscillator ground states and integrates |phi|^4 over them, here by
+    numerical quadrature of the normalised Gaussians (no closed form).
+    Parity unpinned against the paper's programs: it prints no formula.
+    Returns (g, l in m, 1/omega in s)."""
+    hbar, amu, bohr = 1.054571817e-34, 1.66053906660e-27, 5.29177210903e-11
+    length = math.sqrt(hbar / (mass_amu * amu * omega))
+    g = 4.0 * math.pi * atoms * scattering_length_bohr * bohr / length
+    frozen = {3: (), 2: (tight[0],), 1: (tight[0], tight[1])}[int(dim)]
+    for nu in frozen:
+        # phi(z) = (nu/pi)^(1/4) exp(-nu z^2/2): integrate phi^4 on a grid
+        # reaching 12 widths, trapezoid rule (spectrally accurate here)
+        w = 1.0 / math.sqrt(nu)
+        z = np.linspace(-12.0 * w, 12.0 * w, 20001)
+        phi = (nu / math.pi) ** 0.25 * np.exp(-0.5 * nu * z * z)
+        g *= float(np.trapezoid(phi ** 4, z))
+    return g, length, 1.0 / omega

@@ -750,6 +750,27 @@ const char *sscn_status_string(int status)
 
 int sscn_validate(const sscn_problem *pb) { return validate(pb); }
 
+int sscn_units_to_g(const sscn_units *u, double *g, double *length_m, double *time_s)
+{
+    if (!u || !g || u->dim < 1 || u->dim > 3 || u->pad_ != 0) return SSCN_E_INVALID;
+    auto pos = [](double v) { return std::isfinite(v) && v > 0.0; };
+    if (!pos(u->atoms) || !pos(u->mass) || !pos(u->omega) || !std::isfinite(u->scattering_length))
+        return SSCN_E_INVALID;
+    if (u->dim <= 2 && !pos(u->tight[0])) return SSCN_E_INVALID;
+    if (u->dim == 1 && !pos(u->tight[1])) return SSCN_E_INVALID;
+    // CODATA 2018: reduced Planck constant, unified atomic mass unit, Bohr radius
+    constexpr double kHbar = 1.054571817e-34, kAmu = 1.66053906660e-27, kBohr = 5.29177210903e-11;
+    constexpr double kPi = 3.14159265358979323846;
+    const double l = std::sqrt(kHbar / (u->mass * kAmu * u->omega));
+    double gv = 4.0 * kPi * u->atoms * u->scattering_length * kBohr / l;
+    if (u->dim == 2) gv *= std::sqrt(u->tight[0] / (2.0 * kPi));
+    if (u->dim == 1) gv *= std::sqrt(u->tight[0] * u->tight[1]) / (2.0 * kPi);
+    *g = gv;
+    if (length_m) *length_m = l;
+    if (time_s) *time_s = 1.0 / u->omega;
+    return SSCN_OK;
+}
+
 int sscn_set_tile_hint(const sscn_problem *pb, const int32_t chunk[3])
 {
     int v = validate(pb);

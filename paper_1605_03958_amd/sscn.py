@@ -77,10 +77,24 @@ class CBatchSlot(ctypes.Structure):
 
 SLOT_EMPTY, SLOT_RUNNING, SLOT_CONVERGED, SLOT_DONE, SLOT_NONFINITE = 0, 1, 2, 3, 4
 
+
+class CUnits(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int32),
+        ("pad_", ctypes.c_int32),
+        ("atoms", ctypes.c_double),
+        ("scattering_length", ctypes.c_double),
+        ("mass", ctypes.c_double),
+        ("omega", ctypes.c_double),
+        ("tight", ctypes.c_double * 2),
+    ]
+
 EXPORTS = {
     "sscn_abi_version": ([], ctypes.c_int),
     "sscn_status_string": ([ctypes.c_int], ctypes.c_char_p),
     "sscn_validate": ([ctypes.POINTER(CProblem)], ctypes.c_int),
+    "sscn_units_to_g": ([ctypes.POINTER(CUnits), ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                         ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "sscn_state_bytes": ([ctypes.POINTER(CProblem), ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "sscn_workspace_bytes": ([ctypes.POINTER(CProblem), ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "sscn_create": ([ctypes.POINTER(CProblem), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
@@ -217,6 +231,28 @@ class Problem:
         return np.complex128 if self.prec == F64 else np.complex64
 
 
+def units_to_g(dim: int, atoms: float, scattering_length_bohr: float, mass_amu: float, omega: float,
+               tight=(1.0, 1.0)):
+    """The dimensionless nonlinearity of a condensate of `atoms` atoms of
+    mass `mass_amu` (u) and scattering length `scattering_length_bohr`
+    (Bohr radii) in a trap of reference angular frequency `omega` (rad/s);
+    `tight`: the frozen directions' frequencies over omega (dim < 3).
+    Returns (g, length unit in m, time unit in s)."""
+    u = CUnits()
+    u.dim = int(dim)
+    u.pad_ = 0
+    u.atoms = float(atoms)
+    u.scattering_length = float(scattering_length_bohr)
+    u.mass = float(mass_amu)
+    u.omega = float(omega)
+    u.tight[0] = float(tight[0])
+    u.tight[1] = float(tight[1])
+    g, l, t = ctypes.c_double(0), ctypes.c_double(0), ctypes.c_double(0)
+    _check(lib().sscn_units_to_g(ctypes.byref(u), ctypes.byref(g), ctypes.byref(l), ctypes.byref(t)),
+           "sscn_units_to_g")
+    return g.value, l.value, t.value
+
+
 def validate(prob: Problem) -> int:
     pc = prob.c()
     return lib().sscn_validate(ctypes.byref(pc))
@@ -321,7 +357,16 @@ class Solver:
 
     # -- state ---------------------------------------------------------------
     def set_state(self, psi0) -> None:
+        """psi0: a host array, or a device tensor ready on torch's current
+        stream (converted to the state's dtype by the copy)."""
         import torch
+        if isinstance(psi0, torch.Tensor):
+            src = psi0.reshape(self.prob.shape)
+            self.stream.wait_stream(torch.cuda.current_stream(self.device))
+            with torch.cuda.stream(self.stream):
+                self.psi.copy_(src)
+            self.stream.synchronize()
+            return
         a = np.ascontiguousarray(np.asarray(psi0).reshape(self.prob.shape))
         if self.prob.mode == IMAG and np.iscomplexobj(a):
             a = a.real
@@ -354,8 +399,9 @@ class Solver:
         return Obs.from_c(o)
 
     def run(self, max_steps: int, mu_tol: float, trace_cap: int = 100000):
+        """sscn_run; trace_cap = 0 keeps no trace (the rows are not copied)."""
         cap = int(trace_cap)
-        buf = (CObs * max(cap, 1))()
+        buf = (CObs * cap)() if cap > 0 else None
         rows = ctypes.c_int64(0)
         rc = lib().sscn_run(self._h, int(max_steps), float(mu_tol), buf, cap, ctypes.byref(rows))
         _check(rc, "sscn_run", allow=(OK, NOT_CONVERGED, E_NONFINITE))
