@@ -7,9 +7,10 @@ rms sizes of the condensate over time (its dynamics output files, with time
 in the first column and the rms sizes per axis and of r after it).
 
 This module only orchestrates library calls (sscn_run, sscn_observe) on two
-solvers; every step runs in the HIP kernels.  The hand-off goes through host
-memory: the converged real state becomes the real-time solver's complex
-initial state.
+solvers; every step runs in the HIP kernels.  The hand-off stays on the
+device: the converged real state is cast to the real-time dtype on the
+imaginary-time solver's stream and copied into the real-time solver's
+state.
 
 rms sizes are taken about the trap centre (the origin of the coordinates):
 rms_a = sqrt(<x_a^2>) per present axis and rms_r = sqrt(sum_a <x_a^2>).
@@ -53,20 +54,26 @@ def ground_state_then_dynamics(prob: "sscn.Problem", psi0, g_factor: float, real
         raise ValueError("the pipeline starts from an imaginary-time problem")
     if real_steps < 0 or observe_every < 1:
         raise ValueError("real_steps >= 0 and observe_every >= 1 are required")
+    import torch
+    rp = replace(prob, g=prob.g * g_factor, dt=dt_real, mode=sscn.REAL, renorm_every=0,
+                 observe_every=observe_every)
     s = sscn.Solver(prob, psi0)
     try:
         t0 = time.perf_counter()
-        rc, imag_trace = s.run(max_imag_steps, mu_tol, trace_cap=max_imag_steps // max(prob.observe_every, 1) + 2)
+        # no trace: the convergence test runs inside sscn_run, and the
+        # last observation is read afterwards
+        rc, _ = s.run(max_imag_steps, mu_tol, trace_cap=0)
         ground = s.observe()
         t_imag = time.perf_counter() - t0
-        psi_g = s.state()
+        if ground.status != sscn.OK:
+            raise sscn.SSCNError(ground.status, "imaginary-time run")
+        with torch.cuda.stream(s.stream):
+            psi_g = s.psi.to(rp.torch_dtype())
+        s.stream.synchronize()
     finally:
         s.close()
-    if ground.status != sscn.OK:
-        raise sscn.SSCNError(ground.status, "imaginary-time run")
-    rp = replace(prob, g=prob.g * g_factor, dt=dt_real, mode=sscn.REAL, renorm_every=0,
-                 observe_every=observe_every)
-    r = sscn.Solver(rp, psi_g.astype(np.complex128))
+    r = sscn.Solver(rp, psi_g)
+    del psi_g
     try:
         trace = [r.observe()]
         t0 = time.perf_counter()
