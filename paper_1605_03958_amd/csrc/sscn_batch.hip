@@ -21,22 +21,32 @@ namespace sscn {
 // used as global pointers (the compiler then emits global loads and stores).
 template <class P>
 using GP = __attribute__((address_space(1))) P *;
+// The instance table and the work list are written by the host only (at
+// admission and when the list is rebuilt) and read-only during a launch, so
+// they are read through the constant address space: with a wave-uniform
+// index the compiler loads the sweep's descriptors with scalar loads into
+// scalar registers, which leaves the vector registers to the line solve.
+#if defined(__HIP_DEVICE_COMPILE__)
+template <class P>
+using KP = const __attribute__((address_space(4))) P *;
+#else
+// the host pass only parses device code; it has no constant address space
+template <class P>
+using KP = const P *;
+#endif
 
 // ---------------------------------------------------------------------------
 // items
 // ---------------------------------------------------------------------------
 template <class T, bool CPLX, int C, bool MW>
-__device__ __forceinline__ void batch_row(const BInst &I, const BState &S, int tile, unsigned char *lds,
+__device__ __forceinline__ void batch_row(KP<BInst> Ik, const BState &S, int tile, unsigned char *lds,
                                           double *red, bool last)
 {
     using A = Alg<T, CPLX>;
     using V = typename A::V;
-    // the descriptor in registers: a reference into global memory would be
-    // reloaded after every block barrier (a memory fence), and each reload's
-    // wait would also wait for the loads issued ahead for the next line group
-    const BAxis X = I.ax[0];
+    const BAxis X = Ik->ax[0];
     const GP<const TabEntry> tab = (GP<const TabEntry>)X.lt.tab;
-    const PointParams pp = I.pp;
+    const PointParams pp = Ik->pp;
     const int G = MW ? 64 * X.wpl : 64;
     const int tid = threadIdx.x;
     const int lb = tid / G;
@@ -51,8 +61,8 @@ __device__ __forceinline__ void batch_row(const BInst &I, const BState &S, int t
     }
     const V sig = A::coef(X.sig_re, X.sig_im);
     const T scale = CPLX ? T(1) : T(S.scale);
-    const GP<V> psi = (GP<V>)I.psi;
-    const GP<double> norm_part = (GP<double>)I.norm_part;
+    const GP<V> psi = (GP<V>)Ik->psi;
+    const GP<double> norm_part = (GP<double>)Ik->norm_part;
     double nacc = 0.0;
     const long long line0 = (long long)tile * X.rep * X.lpi + lb;
     if constexpr (MW) {
@@ -92,14 +102,14 @@ __device__ __forceinline__ void batch_row(const BInst &I, const BState &S, int t
 }
 
 template <class T, bool CPLX, int C>
-__device__ __forceinline__ void batch_col(const BInst &I, int axis, int tile, unsigned char *lds, double *red,
+__device__ __forceinline__ void batch_col(KP<BInst> Ik, int axis, int tile, unsigned char *lds, double *red,
                                           bool last)
 {
     using A = Alg<T, CPLX>;
     using V = typename A::V;
-    const BAxis X = I.ax[axis];           // in registers (see batch_row)
+    const BAxis X = Ik->ax[axis];
     const GP<const TabEntry> tab = (GP<const TabEntry>)X.lt.tab;
-    const GP<double> norm_part = (GP<double>)I.norm_part;
+    const GP<double> norm_part = (GP<double>)Ik->norm_part;
     const int L = X.L, W = X.W;
     const int LPB = 64 / L;
     const int nch = W * L;
@@ -114,7 +124,7 @@ __device__ __forceinline__ void batch_col(const BInst &I, int axis, int tile, un
     V *xs0 = reinterpret_cast<V *>(tb + nch * C) + st_i * (2 * nch * LPB);
     V *xs1 = xs0 + nch * LPB;
     stage_table_from<T, CPLX>(X.lt, tab, tb, nch * C, 0, C);
-    const GP<V> psi = (GP<V>)I.psi;
+    const GP<V> psi = (GP<V>)Ik->psi;
     // this lane's line in set r, and its first point
     auto line_of = [&](int r) { return (((long long)tile * X.rep + r) * X.tpi + st_i) * LPB + li; };
     auto base_of = [&](long long line) {
@@ -530,11 +540,11 @@ __device__ __forceinline__ bool solo_fast(const BInst &I, BState &S, BState &sS,
 // dispatch
 // ---------------------------------------------------------------------------
 template <class T, bool CPLX, bool BIG>
-__device__ __forceinline__ void batch_sweep(const BInst &I, const BState &S, int pass, int tile, unsigned char *lds,
+__device__ __forceinline__ void batch_sweep(KP<BInst> I, const BState &S, int pass, int tile, unsigned char *lds,
                                             double *red)
 {
-    const bool last = pass == I.last_pass;
-    const BAxis &X = I.ax[pass];
+    const bool last = pass == I->last_pass;
+    const BAxis X = I->ax[pass];
     if (pass == BP_X) {
         if (X.wpl > 1) {
             switch (X.C) {
@@ -599,9 +609,9 @@ __global__ void __launch_bounds__(BATCH_BLOCK) k_batch_step(BatchArgs a)
         __syncthreads();
         if (threadIdx.x == 0) s_item = atomicAdd(&a.ctl->ticket, 1);
         __syncthreads();
-        const int it = s_item;
+        const int it = __builtin_amdgcn_readfirstlane(s_item);
         if (it >= total) break;
-        const BItem w = a.items[it];
+        const BItem w = ((KP<BItem>)a.items)[it];
         const BInst &I = a.inst[w.slot];
         BState &S = a.state[w.slot];
         if (S.status != BS_RUNNING) continue;
@@ -647,8 +657,9 @@ __global__ void __launch_bounds__(BATCH_BLOCK) k_batch_step(BatchArgs a)
         int pass = solo ? BP_X : w.pass;
         for (int k = 1;;) {
             if (pass <= BP_Z) {
-                if (I.elem == 1) batch_sweep<float, false, BIG>(I, S, pass, w.tile, lds_raw, red);
-                else batch_sweep<float, true, BIG>(I, S, pass, w.tile, lds_raw, red);
+                KP<BInst> Ik = (KP<BInst>)a.inst + w.slot;
+                if (I.elem == 1) batch_sweep<float, false, BIG>(Ik, S, pass, w.tile, lds_raw, red);
+                else batch_sweep<float, true, BIG>(Ik, S, pass, w.tile, lds_raw, red);
             } else if (pass == BP_OBS) {
                 if (I.elem == 1) batch_obs<float, false>(I, S, w.tile, redq);
                 else batch_obs<float, true>(I, S, w.tile, redq);
