@@ -500,6 +500,7 @@ def main():
                     help="run only one precision, the batch, the densities or the dynamics pipeline "
                          "(profiling runs)")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance batch")
+    ap.add_argument("--no-sustained", action="store_true", help="skip the 1000-step sustained run (profiling)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving loop")
     ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--serve-rate", type=float, default=SERVE_RATE, help="Poisson arrivals per second")
@@ -551,7 +552,7 @@ def main():
         kms = s.step_timed(args.steps)
         S = 16 if prec == sscn.F64 else 8
         # beside the window: a 1000-step run, the sustained rate
-        el_long = time_steps(s, 1000, 0)
+        el_long = time_steps(s, 1000, 0) if not args.no_sustained else float("nan")
         out[prec] = dict(elapsed=el, pts=p.points * args.steps / el, kernels=kms, S=S, points=p.points,
                          sustained_ms=1e3 * el_long / 1000)
         s.close()
@@ -597,17 +598,18 @@ def main():
                      "share_of_kernel_time": mean_ms * launches / sum(v[0] * v[1] for v in per_kernel.values())},
         "kernel_ms": {k: round(v, 5) for k, v in m["kernels"].items()},
         "step_hbm_frac": (6 * m["S"] * m["points"] * args.steps / m["elapsed"]) / (HBM_PEAK_GBS * 1e9),
-        "sustained_1000_steps": {"ms_per_step": m["sustained_ms"],
-                                 "ptsteps_per_s": m["points"] / (m["sustained_ms"] * 1e-3),
-                                 "step_hbm_frac": 6 * m["S"] * m["points"] / (m["sustained_ms"] * 1e-3) /
-                                 (HBM_PEAK_GBS * 1e9)},
+        "sustained_1000_steps": None if args.no_sustained else
+        {"ms_per_step": m["sustained_ms"],
+         "ptsteps_per_s": m["points"] / (m["sustained_ms"] * 1e-3),
+         "step_hbm_frac": 6 * m["S"] * m["points"] / (m["sustained_ms"] * 1e-3) / (HBM_PEAK_GBS * 1e9)},
     }
     if sscn.F32 in out and main_prec == sscn.F64:
         f = out[sscn.F32]
         res["fp32"] = {"value": f["pts"], "ms_per_step": 1e3 * f["elapsed"] / args.steps,
-                       "sustained_ms_per_step": f["sustained_ms"],
+                       "sustained_ms_per_step": None if args.no_sustained else f["sustained_ms"],
                        "speedup_vs_fp64": f["pts"] / m["pts"],
-                       "speedup_sustained": m["sustained_ms"] / f["sustained_ms"], "kernel_ms": {k: round(v, 5) for k, v in f["kernels"].items()},
+                       "speedup_sustained": None if args.no_sustained else m["sustained_ms"] / f["sustained_ms"],
+                       "kernel_ms": {k: round(v, 5) for k, v in f["kernels"].items()},
                        "state": "complex64"}
     res["copy_gbs"] = copy_bandwidth(m["S"] * m["points"])
     res["roofline"]["frac_of_copy"] = achieved / res["copy_gbs"]
