@@ -320,9 +320,8 @@ int make_plan(const sscn_problem &pb, const TileOverride *ov, Plan &P)
     // kernel, which only the COL kernel does
     if (pb.geom == SSCN_GEOM_AXI && L.kind != K_COL) return SSCN_E_UNSUPPORTED;
     P.sep_pointwise = P.ax[0].kind == K_STREAM;
-    // a one-line radial sweep that renormalises every step finalises the
-    // norm in its own (single) block
-    P.fused_norm = imag && pb.renorm_every == 1 && pb.dim == 1 && P.ax[0].kind == K_RAD && P.ax[0].grid == 1;
+    // a one-line radial sweep finalises the norm in its own (single) block
+    P.fused_norm = imag && pb.dim == 1 && L.kind == K_RAD && L.grid == 1;
     P.sep_norm = imag && L.kind == K_STREAM;
     P.pw_grid = (int)std::min<int64_t>(ceil_div(P.npts, 256), 4096);
     P.np_norm = P.sep_norm ? P.pw_grid : L.grid;
@@ -485,6 +484,7 @@ static ColArgs col_args(sscn_solver *s, int a, bool last)
     c.sig_im = X.sig_im;
     c.partial = last ? reinterpret_cast<double *>(s->ws + s->P.off_part) : nullptr;
     c.wline = (last && s->P.off_wline) ? reinterpret_cast<const double *>(s->ws + s->P.off_wline) : nullptr;
+    c.unit_scale = nullptr;
     return c;
 }
 
@@ -578,14 +578,22 @@ static hipError_t enqueue_step(sscn_solver *s, bool do_renorm, Timer *tm)
         const bool last = imag && do_renorm && a == dim - 1 && X.kind == K_COL;
         if (tm) tm->pair(a, e0, e1);
         if (X.kind == K_COL) {
-            CHK(launch_col(P.elem, X.C, last, col_args(s, a, last), X.grid, X.block, X.lds, s->st, e0, e1));
+            ColArgs c = col_args(s, a, last);
+            // a step that does not renormalise resets the pending scale in its
+            // last sweep (the x sweep has applied it) instead of a launch
+            if (imag && !do_renorm && a == dim - 1) c.unit_scale = scal;
+            CHK(launch_col(P.elem, X.C, last, c, X.grid, X.block, X.lds, s->st, e0, e1));
         } else {
             if (e0) CHK(hipEventRecord(e0, s->st));
             CHK(launch_stream(P.elem, col_args(s, a, false), X.grid, X.block, s->st));
             if (e1) CHK(hipEventRecord(e1, s->st));
         }
     }
-    if (imag && !P.fused_norm) {
+    // the norm's final sum (renormalising steps), or the scale's reset in a
+    // step that does not renormalise, unless its last sweep is a COL kernel,
+    // which resets the scale itself
+    const bool col_reset = dim > 1 && P.ax[dim - 1].kind == K_COL;
+    if (imag && (do_renorm ? !P.fused_norm : !col_reset)) {
         if (tm) tm->pair(3, e0, e1);
         if (e0) CHK(hipEventRecord(e0, s->st));
         if (do_renorm && P.sep_norm)

@@ -134,10 +134,33 @@ cn_rhs(typename Alg<T, CPLX>::V um, typename Alg<T, CPLX>::V u0, typename Alg<T,
 // ---------------------------------------------------------------------------
 // block reductions (FP64, fixed order)
 // ---------------------------------------------------------------------------
+// v taken from another lane by the data-parallel-primitive controls: each
+// 32-bit half moves with the same control; lanes of rows outside ROWS get 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_take(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over the wave's 64 lanes in a fixed order, returned to every lane.
+// The wave must be whole (all lanes active).  Quads first (swap neighbours,
+// then pairs), then 8- and 16-lane groups by mirroring within each row of 16;
+// then lane 15 of rows 0 and 2 is added into rows 1 and 3, and lane 31 into
+// rows 2 and 3, which leaves the total in lane 63.  Register moves only: no
+// LDS round trips as with shuffles.
 __device__ __forceinline__ double wave_sum(double v)
 {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-    return v;  // lane 0 holds the sum
+    v += dpp_take<0xB1, 0xF>(v);    // quad_perm [1,0,3,2]
+    v += dpp_take<0x4E, 0xF>(v);    // quad_perm [2,3,0,1]
+    v += dpp_take<0x141, 0xF>(v);   // row_half_mirror
+    v += dpp_take<0x140, 0xF>(v);   // row_mirror
+    v += dpp_take<0x142, 0xA>(v);   // row_bcast:15 into rows 1, 3
+    v += dpp_take<0x143, 0xC>(v);   // row_bcast:31 into rows 2, 3
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+    return __hiloint2double(hi, lo);
 }
 
 // Sum of v over the block, returned to thread 0; red needs blockDim/64 doubles.

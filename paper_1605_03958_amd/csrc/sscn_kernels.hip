@@ -123,6 +123,7 @@ __global__ void __launch_bounds__(1024) k_col(ColArgs a)
     stage_table<T, CPLX>(a.lt, tb, nch * C, 0, C);
     double nacc = col_tile<T, CPLX, C>(reinterpret_cast<V *>(a.psi), active, base, a.lt.n, a.stride, nch, ch,
                                        LPB, li, tb, xs0, xs1, A::coef(a.sig_re, a.sig_im), a.lt.depth, LAST);
+    if (a.unit_scale && blockIdx.x == 0 && threadIdx.x == 0) *a.unit_scale = 1.0;
     if constexpr (LAST) {
         // the axial trap weighs each z line by its radial cell weight
         if (a.wline && active) nacc *= a.wline[line % a.m1];

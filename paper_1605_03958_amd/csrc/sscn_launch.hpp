@@ -53,6 +53,7 @@ struct ColArgs {
     double sig_re, sig_im;
     double *partial;
     const double *wline;   // last sweep: weight of line l's norm terms at [l % m1] (axial trap), or null
+    double *unit_scale;    // non-null: set to 1 (a step that does not renormalise; the x sweep has read it)
 };
 
 struct PointArgs {
