@@ -643,12 +643,23 @@ __device__ __forceinline__ double col_solve(PV __restrict__ psi, bool active,
         be[k] = v;
     }
     double nacc = 0.0;
+    if (active && i0 + C <= n) {
+        // a whole chunk: one address, stepped by the stride
+        PV p = psi + (base + (long long)i0 * st);
 #pragma unroll
-    for (int k = 0; k < C; ++k) {
-        const int i = i0 + k;
-        if (active && i < n) {
-            st_elem(psi, base + (long long)i * st, be[k]);
+        for (int k = 0; k < C; ++k) {
+            st_elem(p, 0, be[k]);
             if (last) nacc += A::norm2(be[k]);
+            p += st;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < C; ++k) {
+            const int i = i0 + k;
+            if (active && i < n) {
+                st_elem(psi, base + (long long)i * st, be[k]);
+                if (last) nacc += A::norm2(be[k]);
+            }
         }
     }
     return nacc;
@@ -662,6 +673,16 @@ __device__ __forceinline__ void col_load(PV __restrict__ psi, bool active,
 {
     using A = Alg<T, CPLX>;
     const int i0 = ch * C;
+    if (active && i0 + C <= n) {
+        // a whole chunk: one address, stepped by the stride
+        PV p = psi + (base + (long long)i0 * st);
+#pragma unroll
+        for (int k = 0; k < C; ++k) {
+            u[k] = ld_elem(p, 0);
+            p += st;
+        }
+        return;
+    }
 #pragma unroll
     for (int k = 0; k < C; ++k) {
         const int i = i0 + k;
