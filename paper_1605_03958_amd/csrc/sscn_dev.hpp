@@ -39,6 +39,44 @@ __device__ __forceinline__ double fmaT(double a, double b, double c) { return __
 __device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
 // ---------------------------------------------------------------------------
+// lane moves: the value of lane i - d (up) or i + d (down) of the wave.  A
+// shift by one lane is one register move per 32 bits (the data-parallel-
+// primitive whole-wave shift); shifts of up to 4 lanes repeat it, longer
+// ones go through the LDS crossbar (ds_bpermute).  Lanes with no source
+// lane receive unspecified values: callers mask them.
+// ---------------------------------------------------------------------------
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+template <class T>
+__device__ __forceinline__ T lane_up(T v, int d)
+{
+    if (d <= 4) {
+        for (int j = 0; j < d; ++j) v = dpp_mov<0x138>(v);   // wave_shr:1
+        return v;
+    }
+    return __shfl_up(v, d, 64);
+}
+template <class T>
+__device__ __forceinline__ T lane_down(T v, int d)
+{
+    if (d <= 4) {
+        for (int j = 0; j < d; ++j) v = dpp_mov<0x130>(v);   // wave_shl:1
+        return v;
+    }
+    return __shfl_down(v, d, 64);
+}
+
+// ---------------------------------------------------------------------------
 // value algebra: real (imaginary time) or complex (real time)
 // ---------------------------------------------------------------------------
 template <class T>
@@ -63,8 +101,8 @@ struct Alg<T, false> {
     __device__ __forceinline__ static T norm2t(V a) { return a * a; }
     // coefficient from an FP64 (re, im) table entry
     __device__ __forceinline__ static V coef(double re, double) { return T(re); }
-    __device__ __forceinline__ static V shfl_up(V a, int d) { return __shfl_up(a, d, 64); }
-    __device__ __forceinline__ static V shfl_down(V a, int d) { return __shfl_down(a, d, 64); }
+    __device__ __forceinline__ static V shfl_up(V a, int d) { return lane_up(a, d); }
+    __device__ __forceinline__ static V shfl_down(V a, int d) { return lane_down(a, d); }
     __device__ __forceinline__ static bool finite(V a) { return __builtin_isfinite(a); }
 };
 
@@ -90,12 +128,8 @@ struct Alg<T, true> {
     }
     __device__ __forceinline__ static T norm2t(V a) { return fmaT(a.re, a.re, a.im * a.im); }
     __device__ __forceinline__ static V coef(double re, double im) { return V{T(re), T(im)}; }
-    __device__ __forceinline__ static V shfl_up(V a, int d) {
-        return V{__shfl_up(a.re, d, 64), __shfl_up(a.im, d, 64)};
-    }
-    __device__ __forceinline__ static V shfl_down(V a, int d) {
-        return V{__shfl_down(a.re, d, 64), __shfl_down(a.im, d, 64)};
-    }
+    __device__ __forceinline__ static V shfl_up(V a, int d) { return V{lane_up(a.re, d), lane_up(a.im, d)}; }
+    __device__ __forceinline__ static V shfl_down(V a, int d) { return V{lane_down(a.re, d), lane_down(a.im, d)}; }
     __device__ __forceinline__ static bool finite(V a) {
         return __builtin_isfinite(a.re) && __builtin_isfinite(a.im);
     }

@@ -360,7 +360,10 @@ __device__ __forceinline__ double row_solve(PV __restrict__ psi, long long line,
     V din;
     {
         V PA = Ac, PB = d;
-        for (int s = 0; s < ks; ++s) {
+        // unrolled: each step's lane distance is a constant
+#pragma unroll
+        for (int s = 0; s < 6; ++s) {
+            if (s >= ks) break;
             const int o = 1 << s;
             const V a2 = A::shfl_up(PA, o), b2 = A::shfl_up(PB, o);
             if (lane >= o) {
@@ -404,7 +407,9 @@ __device__ __forceinline__ double row_solve(PV __restrict__ psi, long long line,
     V vin;
     {
         V PA = Ac, PB = v;
-        for (int s = 0; s < ks; ++s) {
+#pragma unroll
+        for (int s = 0; s < 6; ++s) {
+            if (s >= ks) break;
             const int o = 1 << s;
             const V a2 = A::shfl_down(PA, o), b2 = A::shfl_down(PB, o);
             if (lane + o < 64) {

@@ -48,6 +48,7 @@ __device__ __forceinline__ typename Alg<T, CPLX>::V chunk_incoming(typename Alg<
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
     // inclusive scan within the wave: compose with the maps of lanes before
     // (FWD) or after (backward) this one
+#pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
         V pa, pb;
         bool take;
