@@ -68,7 +68,7 @@ __device__ __forceinline__ void batch_row(KP<BInst> Ik, const BState &S, int til
     if constexpr (MW) {
         for (int r = 0; r < X.rep; ++r) {
             const long long line = line0 + (long long)r * X.lpi;
-            nacc += row_line<T, CPLX, C, true>(psi, line, line < X.nlines, X.lt.n, tab, G, t, lane, wl, X.wpl,
+            nacc += row_line<T, CPLX, C, true, false>(psi, line, line < X.nlines, X.lt.n, tab, G, t, lane, wl, X.wpl,
                                                xs, sig, scale, T(pp.dt), T(pp.g), pp, X.lt.depth, last);
         }
     } else {
@@ -86,7 +86,7 @@ __device__ __forceinline__ void batch_row(KP<BInst> Ik, const BState &S, int til
             } else if (r > 0) {
                 row_load<T, CPLX, C>(psi, line, line < X.nlines, X.lt.n, t, u);
             }
-            nacc += row_solve<T, CPLX, C, false>(psi, line, line < X.nlines, X.lt.n,
+            nacc += row_solve<T, CPLX, C, false, false>(psi, line, line < X.nlines, X.lt.n,
                                                  static_cast<const LTab<T, CPLX> *>(tl), G, t, lane, wl, 1, xs, sig,
                                                  scale, T(pp.dt), T(pp.g), pp, X.lt.depth, last, u);
             if constexpr (PF) {
@@ -455,10 +455,10 @@ __device__ void solo_run(const BInst &I, BState &S, BState &sS, int steps, int t
         // points per thread differently (last-bit differences, measured)
         double nacc;
         if constexpr (MW)
-            nacc = row_solve<T, CPLX, C, MW>(psi, 0, active, n, &ht, G, t, lane, wl, X.wpl, xs, sig, scale, T(pp.dt),
+            nacc = row_solve<T, CPLX, C, MW, true>(psi, 0, active, n, &ht, G, t, lane, wl, X.wpl, xs, sig, scale, T(pp.dt),
                                              T(pp.g), pp, X.lt.depth, true, u, true);
         else
-            nacc = row_solve<T, CPLX, C, MW>(psi, 0, active, n, static_cast<const LTab<T, CPLX> *>(etab), G, t, lane,
+            nacc = row_solve<T, CPLX, C, MW, true>(psi, 0, active, n, static_cast<const LTab<T, CPLX> *>(etab), G, t, lane,
                                              wl, X.wpl, xs, sig, scale, T(pp.dt), T(pp.g), pp, X.lt.depth, true, u,
                                              true);
         const double nraw = block_sum_after_barrier(nacc, red);

@@ -103,6 +103,9 @@ struct Alg<T, false> {
     __device__ __forceinline__ static V coef(double re, double) { return T(re); }
     __device__ __forceinline__ static V shfl_up(V a, int d) { return lane_up(a, d); }
     __device__ __forceinline__ static V shfl_down(V a, int d) { return lane_down(a, d); }
+    // through the LDS crossbar at any distance
+    __device__ __forceinline__ static V xshfl_up(V a, int d) { return __shfl_up(a, d, 64); }
+    __device__ __forceinline__ static V xshfl_down(V a, int d) { return __shfl_down(a, d, 64); }
     __device__ __forceinline__ static bool finite(V a) { return __builtin_isfinite(a); }
 };
 
@@ -130,6 +133,12 @@ struct Alg<T, true> {
     __device__ __forceinline__ static V coef(double re, double im) { return V{T(re), T(im)}; }
     __device__ __forceinline__ static V shfl_up(V a, int d) { return V{lane_up(a.re, d), lane_up(a.im, d)}; }
     __device__ __forceinline__ static V shfl_down(V a, int d) { return V{lane_down(a.re, d), lane_down(a.im, d)}; }
+    __device__ __forceinline__ static V xshfl_up(V a, int d) {
+        return V{__shfl_up(a.re, d, 64), __shfl_up(a.im, d, 64)};
+    }
+    __device__ __forceinline__ static V xshfl_down(V a, int d) {
+        return V{__shfl_down(a.re, d, 64), __shfl_down(a.im, d, 64)};
+    }
     __device__ __forceinline__ static bool finite(V a) {
         return __builtin_isfinite(a.re) && __builtin_isfinite(a.im);
     }

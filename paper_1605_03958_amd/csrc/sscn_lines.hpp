@@ -297,7 +297,7 @@ __device__ __forceinline__ LTab<T, CPLX> row_tab(const TB *tb, int k, int G, int
 // row_line does both.  With `keep` the solution replaces u instead of being
 // stored (a caller that holds its line in registers across steps).
 // ---------------------------------------------------------------------------
-template <class T, bool CPLX, int C, bool MW, class TB, class PV>
+template <class T, bool CPLX, int C, bool MW, bool UNR = true, class TB, class PV>
 __device__ __forceinline__ double row_solve(PV __restrict__ psi, long long line,
                                             bool active, int n, const TB *tb, int G, int t, int lane, int wl,
                                             int wpl, typename Alg<T, CPLX>::V *xs, typename Alg<T, CPLX>::V sig,
@@ -326,8 +326,11 @@ __device__ __forceinline__ double row_solve(PV __restrict__ psi, long long line,
     }
 
     // ---- neighbours across chunk boundaries ----
-    V left = A::shfl_up(u[C - 1], 1);
-    V right = A::shfl_down(u[0], 1);
+    // (UNR: register moves between lanes and unrolled scans; otherwise
+    // LDS-crossbar shuffles in a loop over the scan depth, which keeps fewer
+    // registers live -- the batched kernels, which are register-bound)
+    V left = UNR ? A::shfl_up(u[C - 1], 1) : A::xshfl_up(u[C - 1], 1);
+    V right = UNR ? A::shfl_down(u[0], 1) : A::xshfl_down(u[0], 1);
     if (lane == 0) left = A::zero();
     if (lane == 63) right = A::zero();
     if constexpr (MW) {
@@ -360,18 +363,29 @@ __device__ __forceinline__ double row_solve(PV __restrict__ psi, long long line,
     V din;
     {
         V PA = Ac, PB = d;
-        // unrolled: each step's lane distance is a constant
+        if constexpr (UNR) {
+            // unrolled: each step's lane distance is a constant
 #pragma unroll
-        for (int s = 0; s < 6; ++s) {
-            if (s >= ks) break;
-            const int o = 1 << s;
-            const V a2 = A::shfl_up(PA, o), b2 = A::shfl_up(PB, o);
-            if (lane >= o) {
-                PB = A::fma(PA, b2, PB);
-                PA = A::mul(PA, a2);
+            for (int s = 0; s < 6; ++s) {
+                if (s >= ks) break;
+                const int o = 1 << s;
+                const V a2 = A::shfl_up(PA, o), b2 = A::shfl_up(PB, o);
+                if (lane >= o) {
+                    PB = A::fma(PA, b2, PB);
+                    PA = A::mul(PA, a2);
+                }
+            }
+        } else {
+            for (int s = 0; s < ks; ++s) {
+                const int o = 1 << s;
+                const V a2 = A::xshfl_up(PA, o), b2 = A::xshfl_up(PB, o);
+                if (lane >= o) {
+                    PB = A::fma(PA, b2, PB);
+                    PA = A::mul(PA, a2);
+                }
             }
         }
-        V EA = A::shfl_up(PA, 1), EB = A::shfl_up(PB, 1);
+        V EA = UNR ? A::shfl_up(PA, 1) : A::xshfl_up(PA, 1), EB = UNR ? A::shfl_up(PB, 1) : A::xshfl_up(PB, 1);
         if (lane == 0) {
             EA = A::one();
             EB = A::zero();
@@ -407,17 +421,29 @@ __device__ __forceinline__ double row_solve(PV __restrict__ psi, long long line,
     V vin;
     {
         V PA = Ac, PB = v;
+        if constexpr (UNR) {
 #pragma unroll
-        for (int s = 0; s < 6; ++s) {
-            if (s >= ks) break;
-            const int o = 1 << s;
-            const V a2 = A::shfl_down(PA, o), b2 = A::shfl_down(PB, o);
-            if (lane + o < 64) {
-                PB = A::fma(PA, b2, PB);
-                PA = A::mul(PA, a2);
+            for (int s = 0; s < 6; ++s) {
+                if (s >= ks) break;
+                const int o = 1 << s;
+                const V a2 = A::shfl_down(PA, o), b2 = A::shfl_down(PB, o);
+                if (lane + o < 64) {
+                    PB = A::fma(PA, b2, PB);
+                    PA = A::mul(PA, a2);
+                }
+            }
+        } else {
+            for (int s = 0; s < ks; ++s) {
+                const int o = 1 << s;
+                const V a2 = A::xshfl_down(PA, o), b2 = A::xshfl_down(PB, o);
+                if (lane + o < 64) {
+                    PB = A::fma(PA, b2, PB);
+                    PA = A::mul(PA, a2);
+                }
             }
         }
-        V EA = A::shfl_down(PA, 1), EB = A::shfl_down(PB, 1);
+        V EA = UNR ? A::shfl_down(PA, 1) : A::xshfl_down(PA, 1),
+          EB = UNR ? A::shfl_down(PB, 1) : A::xshfl_down(PB, 1);
         if (lane == 63) {
             EA = A::one();
             EB = A::zero();
@@ -566,7 +592,7 @@ __device__ __forceinline__ void row_store(PV __restrict__ psi, long long line, b
         if (active && i0 + k < n) st_elem(psi, base + i0 + k, v[k]);
 }
 
-template <class T, bool CPLX, int C, bool MW, class TB, class PV>
+template <class T, bool CPLX, int C, bool MW, bool UNR = true, class TB, class PV>
 __device__ __forceinline__ double row_line(PV __restrict__ psi, long long line,
                                            bool active, int n, const TB *tb, int G, int t, int lane, int wl,
                                            int wpl, typename Alg<T, CPLX>::V *xs, typename Alg<T, CPLX>::V sig,
@@ -574,8 +600,8 @@ __device__ __forceinline__ double row_line(PV __restrict__ psi, long long line,
 {
     typename Alg<T, CPLX>::V u[C];
     row_load<T, CPLX, C>(psi, line, active, n, t, u);
-    return row_solve<T, CPLX, C, MW, TB, PV>(psi, line, active, n, tb, G, t, lane, wl, wpl, xs, sig, scale, dt, g, pp,
-                                         ks, last, u);
+    return row_solve<T, CPLX, C, MW, UNR, TB, PV>(psi, line, active, n, tb, G, t, lane, wl, wpl, xs, sig, scale, dt,
+                                                  g, pp, ks, last, u);
 }
 
 // ---------------------------------------------------------------------------
