@@ -186,8 +186,9 @@ def imag256_timing(steps: int = 300):
     out = {"workload": "256^3 imaginary time, dx=0.05, dt=0.1*dx^2, g=22, renormalised every step"}
     for prec, S, name in ((sscn.F64, 8, "f64"), (sscn.F32, 4, "f32")):
         p = sscn.Problem(3, n, (dx,) * 3, (1.0, 1.5, 2.0), 22.0, 0.1 * dx * dx, sscn.IMAG, prec, 1)
+        apply_tiles(p, "single")
         s = sscn.Solver(p, psi0)
-        s.step(20)
+        s.step(100)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         s.step(steps)
@@ -212,6 +213,7 @@ def ground64_timing(steps: int = 500):
     from paper_1605_03958_amd import inputs, sscn
     dx = 0.2
     p = sscn.Problem(3, (64, 64, 64), (dx,) * 3, (1.0, 1.5, 2.0), 22.0, 0.1 * dx * dx, sscn.IMAG, sscn.F64, 1)
+    apply_tiles(p, "single")
     s = sscn.Solver(p, inputs.ho_gaussian(3, p.n, p.dx, p.omega, noise=1e-3, seed=0))
     s.step(64)
     torch.cuda.synchronize()

@@ -73,16 +73,23 @@ def _state(prob: Problem, seed: int = 0):
 # measurement
 # ---------------------------------------------------------------------------
 
-def measure_single(prob: Problem, chunks, steps: int = 20, psi0=None) -> float:
-    """Mean duration (ms) of one step's sweeps with these chunks."""
+def measure_single(prob: Problem, chunks, steps: int = 300, psi0=None, warm: int = 100) -> float:
+    """Wall-clock time (ms) per step with these chunks, over `steps` graph-
+    replayed steps after `warm` untimed ones (per-kernel event timing adds
+    its own overhead to short kernels and moved the choice by noise)."""
+    import torch
     sscn.set_tile_hint(prob, chunks)
     s = sscn.Solver(prob, _state(prob) if psi0 is None else psi0)
     try:
-        s.step(3)
-        ms = s.step_timed(steps)
+        s.step(warm)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
     finally:
         s.close()
-    return float(sum(ms[k] for k in ("x_sweep_pointwise", "y_sweep", "z_sweep_norm")))
+    return 1e3 * el / steps
 
 
 def measure_batch(prob: Problem, chunks, launches: int = 10, target_points: float = 2.0e7, psi0=None) -> float:
@@ -242,12 +249,24 @@ def cube_problems():
             for prec in (F64, F32)]
 
 
+def imag_problems():
+    """The imaginary-time workloads of the benchmark: the 64^3 FP64 ground
+    state (dx = 0.2) and its physics at 256^3 (dx = 0.05) in FP64 and FP32."""
+    from .sscn import F64
+    out = [Problem(3, (64, 64, 64), (0.2,) * 3, (1.0, 1.5, 2.0), 22.0, 0.1 * 0.2 * 0.2, IMAG, F64, 1)]
+    out += [Problem(3, (256, 256, 256), (0.05,) * 3, (1.0, 1.5, 2.0), 22.0, 0.1 * 0.05 * 0.05, IMAG, prec, 1)
+            for prec in (F64, F32)]
+    return out
+
+
 def main(argv=None):
     import argparse
     ap = argparse.ArgumentParser(description="tune tile shapes and store them in a JSON cache")
     ap.add_argument("--cache", required=True)
     ap.add_argument("--mix", action="store_true", help="the 64 shapes of the uneven batch mix (batch kernel)")
     ap.add_argument("--cube", action="store_true", help="the 256^3 workload (single-problem kernels)")
+    ap.add_argument("--imag", action="store_true",
+                    help="the 64^3 and 256^3 imaginary-time workloads (single-problem kernels)")
     ap.add_argument("--force", action="store_true")
     args = ap.parse_args(argv)
     jobs = []
@@ -260,9 +279,11 @@ def main(argv=None):
             jobs.append(("batch", p))
     if args.cube:
         jobs += [("single", p) for p in cube_problems()]
+    if args.imag:
+        jobs += [("single", p) for p in imag_problems()]
     t0 = time.perf_counter()
     for k, (target, p) in enumerate(jobs):
-        rec = tune(p, target, cache_path=args.cache, reps=2 if target == "single" else 1, force=args.force)
+        rec = tune(p, target, cache_path=args.cache, reps=3 if target == "single" else 1, force=args.force)
         print(f"[{k + 1}/{len(jobs)} {time.perf_counter() - t0:.0f}s] {target} dim={p.dim} n={p.n} "
               f"prec={p.prec}: chunks {rec['chunks']} {rec['ms']:.4f} ms (default {rec['default_ms']:.4f})",
               flush=True)
