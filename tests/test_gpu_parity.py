@@ -2,13 +2,17 @@
 the same seeded inputs.  FP64 bar: relative L2 of psi <= 1e-10 after 1000
 steps (1e-12 for the short runs below), observables to 1e-10 relative."""
 import math
+import os
 
 import numpy as np
 import pytest
 
 import oracle
-from paper_1605_03958_amd import inputs, sscn
+from paper_1605_03958_amd import autotune, inputs, sscn
 from paper_1605_03958_amd.sscn import F32, F64, IMAG, REAL, Problem
+
+TILES = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1605_03958_amd",
+                     "tiles_gfx950.json")
 
 pytestmark = pytest.mark.gpu
 
@@ -375,9 +379,15 @@ def _line_errors(flat, shape):
 
 
 def _cube256_run(prec, steps=1000):
+    """The benchmark's 256^3 workload in its launch configuration: the
+    stored tile choices for the shape apply, as in bench.py."""
     p = cube256_problem(prec)
     psi0 = inputs.thomas_fermi(3, p.n, p.dx, p.omega, 100.0, phase_sigma=0.05, seed=1)
-    s = sscn.Solver(p, psi0)
+    try:
+        autotune.apply(p, "single", cache_path=TILES)
+        s = sscn.Solver(p, psi0)
+    finally:
+        sscn.clear_tile_hints()
     s.step(steps)
     ob = s.observe()
     flat = s.state().reshape(-1)
