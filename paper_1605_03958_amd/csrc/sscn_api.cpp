@@ -1040,10 +1040,13 @@ int sscn_step_timed(sscn_solver *s, int64_t nsteps, double *ms)
 }
 
 // Enqueue the observation kernels; the 13 results land at *dobs (device).
-static hipError_t obs_enqueue(sscn_solver *s, double **dobs_out)
+// The observation kernels of the current state; the 13 results go to `dest`
+// (device-accessible; null: the workspace's slot), whose address is
+// returned in *dobs_out.
+static hipError_t obs_enqueue(sscn_solver *s, double **dobs_out, double *dest = nullptr)
 {
     const Plan &P = s->P;
-    double *dobs = reinterpret_cast<double *>(s->ws + P.off_obs);
+    double *dobs = dest ? dest : reinterpret_cast<double *>(s->ws + P.off_obs);
     *dobs_out = dobs;
     if (s->pb.geom != SSCN_GEOM_CART) {
         const sscn_problem &pb = s->pb;
@@ -1129,10 +1132,17 @@ static int run_queued(sscn_solver *s, int64_t max_steps, sscn_obs *trace, int64_
     } catch (...) {
         return SSCN_E_INVALID;
     }
-    double *stage = nullptr;
+    // the observation rows are written by the final-sum kernel straight
+    // into mapped pinned host memory (one copy command per observation
+    // otherwise: it tripled the time of an observed step at 128^3)
+    double *stage = nullptr, *dstage = nullptr;
     if (hipHostMalloc(reinterpret_cast<void **>(&stage), (size_t)kRunGroup * 13 * sizeof(double),
-                      hipHostMallocDefault) != hipSuccess)
+                      hipHostMallocMapped) != hipSuccess)
         return SSCN_E_HIP;
+    if (hipHostGetDevicePointer(reinterpret_cast<void **>(&dstage), stage, 0) != hipSuccess) {
+        (void)hipHostFree(stage);
+        return SSCN_E_HIP;
+    }
     int64_t nrow = 0, done = 0;
     int rc = SSCN_NOT_CONVERGED;
     bool stop = false;
@@ -1142,9 +1152,7 @@ static int run_queued(sscn_solver *s, int64_t max_steps, sscn_obs *trace, int64_
             int64_t k = every - (s->step % every);
             if (k > max_steps - done) k = max_steps - done;
             double *dobs = nullptr;
-            if (sscn_step(s, k) != SSCN_OK || obs_enqueue(s, &dobs) != hipSuccess ||
-                hipMemcpyAsync(stage + 13 * nq, dobs, 13 * sizeof(double), hipMemcpyDeviceToHost, s->st) !=
-                    hipSuccess) {
+            if (sscn_step(s, k) != SSCN_OK || obs_enqueue(s, &dobs, dstage + 13 * nq) != hipSuccess) {
                 (void)hipStreamSynchronize(s->st);
                 (void)hipHostFree(stage);
                 return SSCN_E_HIP;

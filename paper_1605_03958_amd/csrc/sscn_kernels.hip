@@ -257,14 +257,23 @@ __global__ void __launch_bounds__(256) k_obs_partials(ObsArgs a)
     double acc[SSCN_NOBS];
 #pragma unroll
     for (int q = 0; q < SSCN_NOBS; ++q) acc[q] = 0.0;
+    double inv2[3];                       // 1 / dx_a^2
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) inv2[ax] = ax < a.dim ? 1.0 / (a.dx[ax] * a.dx[ax]) : 0.0;
     // acc: 0 sum q, 1 sum kinetic edges, 2 sum V q, 3 sum q^2, 4..6 x_a q, 7..9 x_a^2 q
-    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < a.npts;
-         p += (long long)gridDim.x * blockDim.x) {
-        const int idx[3] = {(int)(p % nx), (int)((p / nx) % ny), (int)(p / (nx * ny))};
-        (void)nz;
+    // The grid indices of this thread's first point come from two
+    // divisions; after that each grid-stride step adds the stride's own
+    // decomposition with carries (no division per point).
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    int idx[3] = {(int)(p % nx), (int)((p / nx) % ny), (int)(p / (nx * ny))};
+    const int di = (int)(stride % nx), dj = (int)((stride / nx) % ny), dk = (int)(stride / (nx * ny));
+    (void)nz;
+    for (; p < a.npts; p += stride) {
         const V v = psi[p];
         const double q = A::norm2(v);
         double vp = 0.0, kin = 0.0;
+#pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
             if (ax >= a.dim) break;
             const double x = (double(idx[ax]) - a.cen[ax]) * a.dx[ax];
@@ -274,12 +283,25 @@ __global__ void __launch_bounds__(256) k_obs_partials(ObsArgs a)
             const V nb = (idx[ax] + 1 < a.n[ax]) ? psi[p + sx[ax]] : A::zero();
             double e = A::norm2(A::sub(nb, v));
             if (idx[ax] == 0) e += q;
-            kin += e / (a.dx[ax] * a.dx[ax]);
+            kin = fmaT(e, inv2[ax], kin);
         }
         acc[0] += q;
         acc[1] += kin;
         acc[2] = fmaT(vp, q, acc[2]);
         acc[3] = fmaT(q, q, acc[3]);
+        int c = 0;
+        idx[0] += di;
+        if (idx[0] >= a.n[0]) {
+            idx[0] -= a.n[0];
+            c = 1;
+        }
+        idx[1] += dj + c;
+        c = 0;
+        if (idx[1] >= a.n[1]) {
+            idx[1] -= a.n[1];
+            c = 1;
+        }
+        idx[2] += dk + c;
     }
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll

@@ -9,6 +9,7 @@ this module without it raises.
 from __future__ import annotations
 
 import ctypes
+import gc
 import os
 from dataclasses import dataclass, field
 
@@ -313,6 +314,32 @@ class Obs:
         return Obs(int(o.step), o.norm, o.mu, o.energy, o.ekin, o.epot, o.eint,
                    tuple(o.mean), tuple(o.msq), int(o.status))
 
+    @staticmethod
+    def rows(buf, n: int) -> list:
+        """Obs of the first n entries of a CObs array, read through one numpy
+        view."""
+        if n <= 0:
+            return []
+        a = np.ctypeslib.as_array(buf)[:n]
+        # a burst of small objects: the cyclic collector is held off for it
+        # (a full collection over a process holding torch took ~60 ms)
+        was = gc.isenabled()
+        gc.disable()
+        try:
+            return Obs._rows_of(a)
+        finally:
+            if was:
+                gc.enable()
+
+    @staticmethod
+    def _rows_of(a) -> list:
+        return [Obs(int(st), float(nm), float(mu), float(en), float(ek), float(ep), float(ei),
+                    (float(m[0]), float(m[1]), float(m[2])), (float(q[0]), float(q[1]), float(q[2])), int(sta))
+                for st, nm, mu, en, ek, ep, ei, m, q, sta in
+                zip(a["step"].tolist(), a["norm"].tolist(), a["mu"].tolist(), a["energy"].tolist(),
+                    a["ekin"].tolist(), a["epot"].tolist(), a["eint"].tolist(), a["mean"].tolist(),
+                    a["msq"].tolist(), a["status"].tolist())]
+
 
 class Solver:
     """One SSCN problem bound to torch-owned device memory on a stream.
@@ -405,7 +432,7 @@ class Solver:
         rows = ctypes.c_int64(0)
         rc = lib().sscn_run(self._h, int(max_steps), float(mu_tol), buf, cap, ctypes.byref(rows))
         _check(rc, "sscn_run", allow=(OK, NOT_CONVERGED, E_NONFINITE))
-        return rc, [Obs.from_c(buf[i]) for i in range(rows.value)]
+        return rc, Obs.rows(buf, rows.value)
 
     def set_g(self, g: float) -> None:
         _check(lib().sscn_set_g(self._h, float(g)), "sscn_set_g")
