@@ -131,7 +131,8 @@ def candidates(target: str, prob: Problem):
         if target == "single":
             out.append([0] + list(SINGLE_CHUNKS))
         elif a == 0:
-            out.append([0] + [c for c in BATCH_ROW_CHUNKS[cplx] if c * 64 >= prob.n[0]])
+            # single-wave x lines of 2D and 3D instances take at most 4 points per thread
+            out.append([0] + [c for c in BATCH_ROW_CHUNKS[cplx] if c * 64 >= prob.n[0] and (prob.dim == 1 or c <= 4)])
         else:
             # at most 16 waves x 8 lanes of chunks cover a line
             out.append([0] + [c for c in BATCH_COL_CHUNKS[cplx] if c * 128 >= prob.n[a]])

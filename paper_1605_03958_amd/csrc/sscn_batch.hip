@@ -548,6 +548,7 @@ __device__ __forceinline__ void batch_sweep(KP<BInst> I, const BState &S, int pa
     if (pass == BP_X) {
         if (X.wpl > 1) {
             switch (X.C) {
+            case 4: batch_row<T, CPLX, 4, true>(I, S, tile, lds, red, last); break;
             case 8: batch_row<T, CPLX, 8, true>(I, S, tile, lds, red, last); break;
             case 16:
                 if constexpr (BIG) batch_row<T, CPLX, 16, true>(I, S, tile, lds, red, last);

@@ -172,18 +172,29 @@ int batch_plan(const sscn_problem &pb, BPlan &B, int parts = kDefaultSplit)
             X.s1 = nx;
             X.s2 = nx * ny;
             X.stride = 1;
-            const int cmax1 = cplx ? 8 : 16;   // single-wave lines
+            // single-wave lines: up to 16 points per thread (8 complex) for
+            // a 1D line, which runs whole steps in one block (the solo
+            // kernel); up to 4 for the x lines of 2D and 3D instances, whose
+            // longer single-wave forms spill in the persistent kernel
+            // (752 B per lane at 8 points): those lines take 4 points per
+            // thread over several waves instead
+            const int cmax1 = pb.dim == 1 ? (cplx ? 8 : 16) : 4;
             int c = cmax1 + 1;
             for (int v : kRowChunks)            // fewest points per thread that cover the line
-                if (row_chunk_ok(v, cplx) && (int64_t)v * 64 >= n) {
+                if (v <= cmax1 && row_chunk_ok(v, cplx) && (int64_t)v * 64 >= n) {
                     c = v;
                     break;
                 }
-            if (hint[a] > 0 && row_chunk_ok(hint[a], cplx) && (int64_t)hint[a] * 64 >= n) c = hint[a];
+            if (hint[a] > 0 && hint[a] <= cmax1 && row_chunk_ok(hint[a], cplx) && (int64_t)hint[a] * 64 >= n)
+                c = hint[a];
             int wpl = 1;
             if (c > cmax1) {
-                c = 8;                          // multi-wave lines, 8 points per thread
-                wpl = p2ceil(cdiv(n, 64 * 8));
+                c = pb.dim == 1 ? 8 : 4;        // multi-wave lines, 8 (1D) or 4 points per thread
+                wpl = p2ceil(cdiv(n, 64 * c));
+                if (wpl > 16 && c == 4) {
+                    c = 8;
+                    wpl = p2ceil(cdiv(n, 64 * 8));
+                }
                 if (wpl > 16) {
                     c = 16;                     // ... or 16 (long 1D lines)
                     wpl = p2ceil(cdiv(n, 64 * 16));

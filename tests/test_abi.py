@@ -260,9 +260,13 @@ def test_batch_tile_hints():
     def geo(g):
         return {k: v for k, v in g.items() if k != "big"}
     try:
-        sscn.batch_set_tile_hint(p, (6, 3, 12))
+        sscn.batch_set_tile_hint(p, (2, 3, 12))
         h = sscn.batch_plan_info(p)
-        assert [h[0]["chunk"], h[1]["chunk"], h[2]["chunk"]] == [6, 3, 12]
+        assert [h[0]["chunk"], h[1]["chunk"], h[2]["chunk"]] == [2, 3, 12]
+        # x lines of 2D and 3D instances take at most 4 points per thread in
+        # one wave: a larger hint is accepted but not taken
+        sscn.batch_set_tile_hint(p, (6, 3, 12))
+        assert sscn.batch_plan_info(p)[0] == base[0]
         assert h[1]["chunk"] * h[1]["waves"] * h[1]["lanes"] >= 44
         assert sscn.batch_plan_info(q) == qbase      # other shapes untouched
         sscn.batch_set_tile_hint(p, (0, 16, 0))

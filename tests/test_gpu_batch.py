@@ -105,10 +105,13 @@ def test_batch_matches_oracle_across_tile_variants():
 
 def test_every_tile_variant_matches_the_oracle():
     """Tile hints force each points-per-thread variant of the persistent
-    kernel (x lines 1..16, y and z lines 2..16) on small 3D instances of
-    distinct shapes, in imaginary and real time: 20 steps against the
-    oracle."""
-    row = {IMAG: [1, 2, 3, 4, 6, 8, 12, 16], REAL: [1, 2, 3, 4, 6, 8]}
+    kernel on small instances of distinct shapes, in imaginary and real
+    time, 20 steps against the oracle: the x lines of 3D instances in one
+    wave (1..4 points per thread), longer x lines of 2D and 3D instances
+    over several waves (4 and 8 points per thread), the y and z lines
+    (2..16), and 1D lines in one wave with 6..16 points per thread (the solo
+    cycle of the persistent kernel: no stream here)."""
+    row = {IMAG: [1, 2, 3, 4], REAL: [1, 2, 3, 4]}
     col = {IMAG: [2, 3, 4, 5, 6, 8, 10, 12, 16], REAL: [2, 3, 4, 5, 6, 8]}
     cases = []
     i = 0
@@ -124,6 +127,23 @@ def test_every_tile_variant_matches_the_oracle():
                 sscn.batch_set_tile_hint(p, (r, cy, cz))
                 g = sscn.batch_plan_info(p)
                 assert [g[0]["chunk"], g[1]["chunk"], g[2]["chunk"]] == [r, cy, cz]
+                cases.append((p, psi0))
+                i += 1
+        # multi-wave x lines of 2D and 3D instances (no hint needed)
+        for dim, n, mode, want in ((2, (700, 40, 1), IMAG, 4), (2, (700, 40, 1), REAL, 4),
+                                   (2, (4500, 8, 1), IMAG, 8), (3, (300, 12, 10), REAL, 4)):
+            p, psi0 = make(dim, n, mode, seed=60 + i)
+            g = sscn.batch_plan_info(p)[0]
+            assert g["chunk"] == want and g["waves"] > 1, g
+            cases.append((p, psi0))
+            i += 1
+        # single-wave 1D lines of 6..16 points per thread
+        for mode, cs in ((IMAG, (6, 8, 12, 16)), (REAL, (6, 8))):
+            for c in cs:
+                p, psi0 = make(1, (64 * c - 5 - i, 1, 1), mode, seed=60 + i)
+                sscn.batch_set_tile_hint(p, (c, 0, 0))
+                g = sscn.batch_plan_info(p)[0]
+                assert g["chunk"] == c and g["waves"] == 1, g
                 cases.append((p, psi0))
                 i += 1
         got, st = run_batch(cases, 20)
