@@ -53,13 +53,16 @@ def _find(d: str, suffix: str) -> str:
     return hits[0]
 
 
-def classify(rows):
-    """Assign each sweep dispatch (in dispatch order) to x / y / z."""
+def classify(rows, match: str = ""):
+    """Assign each sweep dispatch (in dispatch order) to x / y / z; sweep
+    kernels whose name lacks `match` (another precision's) are left out."""
     out = []
     after_row = 0
     for r in sorted(rows, key=lambda r: int(r["Dispatch_Id"])):
         name = r["Kernel_Name"]
-        if "k_row" in name:
+        if ("k_row" in name or "k_col" in name) and match not in name:
+            cls = None
+        elif "k_row" in name:
             cls = "x_sweep_pointwise"
             after_row = 0
         elif "k_col" in name:
@@ -73,23 +76,33 @@ def classify(rows):
     return out
 
 
-def counter_means(path: str, counter: str):
+def _copy_top(acc):
+    """Calibration copies: those within 10 % of the largest (a run that
+    uploads states of several sizes copies each)."""
+    if acc.get("copy"):
+        top = max(acc["copy"])
+        acc["copy"] = [v for v in acc["copy"] if v >= 0.9 * top]
+
+
+def counter_means(path: str, counter: str, match: str = ""):
     rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter]
     acc = defaultdict(list)
-    for cls, r in classify(rows):
+    for cls, r in classify(rows, match):
         if cls:
             acc[cls].append(float(r["Counter_Value"]))
+    _copy_top(acc)
     return {k: sum(v) / len(v) for k, v in acc.items()}, {k: len(v) for k, v in acc.items()}
 
 
-def trace_means(path: str):
+def trace_means(path: str, match: str = ""):
     rows = list(csv.DictReader(open(path)))
     for r in rows:
         r.setdefault("Dispatch_Id", r.get("Dispatch_Id", "0"))
     acc = defaultdict(list)
-    for cls, r in classify(rows):
+    for cls, r in classify(rows, match):
         if cls:
             acc[cls].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    _copy_top(acc)
     return {k: sum(v) / len(v) for k, v in acc.items()}
 
 
@@ -179,6 +192,8 @@ def main():
     ap.add_argument("--command", default="")
     ap.add_argument("--batch", action="store_true", help="summarise the persistent batch kernel")
     ap.add_argument("--alg-bytes", type=float, default=0.0, help="algorithmic bytes per persistent launch")
+    ap.add_argument("--match", default="",
+                    help="only sweep kernels whose name contains this (one precision of a two-precision run)")
     args = ap.parse_args()
     if args.batch:
         batch_summary(args)
@@ -188,9 +203,9 @@ def main():
         return
 
     stats = list(csv.DictReader(open(_find(args.trace, "kernel_stats.csv"))))
-    dur = trace_means(_find(args.trace, "kernel_trace.csv"))
-    fetch, nf = counter_means(_find(args.fetch, "counter_collection.csv"), "FETCH_SIZE")
-    write, nw = counter_means(_find(args.write, "counter_collection.csv"), "WRITE_SIZE")
+    dur = trace_means(_find(args.trace, "kernel_trace.csv"), args.match)
+    fetch, nf = counter_means(_find(args.fetch, "counter_collection.csv"), "FETCH_SIZE", args.match)
+    write, nw = counter_means(_find(args.write, "counter_collection.csv"), "WRITE_SIZE", args.match)
     kib = 1024.0
     S = args.state_bytes
     f_fetch = S / (fetch["copy"] * kib)
@@ -206,7 +221,10 @@ def main():
     for r in stats:
         lines.append(f"| `{r['Name'][:90]}` | {r['Calls']} | {float(r['AverageNs']):.0f} | "
                      f"{float(r['Percentage']):.2f} |")
-    lines += ["", "## Per class (dispatch order within a step)", "",
+    lines += ["", "## Per class (dispatch order within a step)", ""]
+    if args.match:
+        lines += [f"Sweep kernels whose name contains `{args.match}` only.", ""]
+    lines += [
               "| class | mean duration us | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM bytes / launch "
               "(calibrated) | / algorithmic | achieved GB/s (algorithmic) |", "|---|---|---|---|---|---|---|"]
     rec = {}
