@@ -295,7 +295,8 @@ int sscn_clear_tile_hints(void);
  * along the line, 1 COL: lanes across lines, 2 one-thread-per-line
  * fallback, 3 radial line per block, -1 unused axis), points per thread,
  * waves per line group (ROW), per block (COL) or per line (radial), lanes
- * per line (COL; 1 otherwise), grid size, block
+ * per line (COL; ROW: lanes of a wave per line, 64, or 16 for lines of at
+ * most 64 points taken four to a wave; 1 otherwise), grid size, block
  * size, first index of the constant tail of the Thomas table, and the scan
  * depth (ROW: shuffle steps; COL: preceding chunks folded).  info needs
  * cap >= 24 entries. */

@@ -191,8 +191,10 @@ void table_meta(AxisPlan &X, bool fp32)
         d = (q > 1e6) ? 1000000 : std::max(1, (int)std::ceil(q));
     }
     if (X.kind == K_ROW) {
+        // Kogge-Stone steps, at most log2 of the lanes per line
+        const int lmax = (X.seg > 0 && X.seg < 64) ? __builtin_ctz((unsigned)X.seg) : 6;
         int ks = 0;
-        while ((1 << ks) < d && ks < 6) ++ks;
+        while ((1 << ks) < d && ks < lmax) ++ks;
         X.depth = ks;
     } else {
         X.depth = std::min(d, std::max(1, X.W * std::max(1, X.L)));
@@ -255,25 +257,32 @@ int make_plan(const sscn_problem &pb, const TileOverride *ov, Plan &P)
             } else if (c > cmax_row(P.S)) {
                 c = cmax_row(P.S);
                 wpl = pow2ceil(ceil_div(n, 64 * (int64_t)c));
+            } else if (n <= 64) {
+                c = 4;
             }
-            if (wpl <= 16 && c <= cmax_row(P.S) && (int64_t)c * 64 * wpl >= n) {
+            // lines of at most 64 points in chunks of 4: 16 lanes per line
+            // and four lines per wave (fewer scan steps and a quarter of the
+            // per-line instructions of one line over 64 lanes)
+            const int seg = (c == 4 && n <= 64) ? 16 : 64;
+            if (wpl <= 16 && c <= cmax_row(P.S) && (int64_t)c * seg * wpl >= n) {
                 X.kind = K_ROW;
                 X.C = c;
                 X.wpl = wpl;
-                X.lpb = std::max(1, 4 / wpl);
-                X.block = 64 * wpl * X.lpb;
+                X.seg = seg;
+                X.lpb = std::max(1, 4 / wpl) * (64 / seg);
+                X.block = 64 * wpl * std::max(1, 4 / wpl);
                 X.grid = (int)std::min<int64_t>(ceil_div(X.nlines, X.lpb), 4096);
                 // single-wave lines stage their table in LDS and move their
                 // values through a per-wave buffer of c*64 + 64 values when
-                // both fit 64 KB (k_row decides alike); multi-wave lines
-                // exchange 4 values per wave
+                // both fit 64 KB (k_row decides alike; not for short lines);
+                // multi-wave lines exchange 4 values per wave
                 if (wpl == 1) {
-                    const size_t tab = (size_t)c * 64 * ltab_bytes(P), tr = (size_t)X.lpb * (c * 64 + 64) * P.S;
-                    X.lds = (P.S >= 16 && tab + tr <= 65536) ? tab + tr : tab;
+                    const size_t tab = (size_t)c * seg * ltab_bytes(P), tr = (size_t)X.lpb * (c * 64 + 64) * P.S;
+                    X.lds = (seg == 64 && P.S >= 16 && tab + tr <= 65536) ? tab + tr : tab;
                 } else {
                     X.lds = (size_t)X.lpb * wpl * 4 * P.S;
                 }
-                X.tab_entries = (size_t)c * 64 * wpl;
+                X.tab_entries = (size_t)c * seg * wpl;
             }
         } else {
             X.m1 = (int)nx;
@@ -325,6 +334,13 @@ int make_plan(const sscn_problem &pb, const TileOverride *ov, Plan &P)
     P.sep_norm = imag && L.kind == K_STREAM;
     P.pw_grid = (int)std::min<int64_t>(ceil_div(P.npts, 256), 4096);
     P.np_norm = P.sep_norm ? P.pw_grid : L.grid;
+    // few partials: the next step's x sweep sums them itself (every wave of
+    // it reads them all), which saves the final sum's launch on the small
+    // grids that launches bound; short x lines (the k_row form that takes
+    // four lines per wave carries the code), and x not the last sweep (its
+    // blocks would read partials that others overwrite)
+    P.fold_norm = imag && pb.dim >= 2 && P.ax[0].kind == K_ROW && P.ax[0].seg < 64 && L.kind == K_COL &&
+                  P.np_norm <= 64 * kFoldWaves;
     P.obs_grid = (int)std::min<int64_t>(ceil_div(P.npts, 256), 1024);
 
     size_t off = 0;
@@ -375,7 +391,7 @@ void build_table(const sscn_problem &pb, const Plan &P, int a, std::vector<TabEn
     out.assign(X.tab_entries, TabEntry{0, 0, 0, 0});
     auto put = [&](size_t slot, int i) { out[slot] = TabEntry{ar[i], ai[i], mr[i], mi[i]}; };
     if (X.kind == K_ROW) {
-        const int G = 64 * X.wpl;
+        const int G = (X.seg > 0 && X.seg < 64) ? X.seg : 64 * X.wpl;
         for (int t = 0; t < G; ++t)
             for (int k = 0; k < X.C; ++k) {
                 const int i = t * X.C + k;
@@ -509,7 +525,11 @@ struct Timer {
     }
 };
 
-static hipError_t enqueue_step(sscn_solver *s, bool do_renorm, Timer *tm)
+// fold_in: the previous step renormalised and left its norm partials for
+// this step's x sweep (fold_norm plans, within a run of steps).  final_sum:
+// a renormalising step launches the norm's final sum (always, unless the
+// plan folds it into the next step and this step is not a run's last).
+static hipError_t enqueue_step(sscn_solver *s, bool do_renorm, bool fold_in, bool final_sum, Timer *tm)
 {
     const Plan &P = s->P;
     const sscn_problem &pb = s->pb;
@@ -534,6 +554,7 @@ static hipError_t enqueue_step(sscn_solver *s, bool do_renorm, Timer *tm)
             r.lt = line_tab(s, 0);
             r.nlines = (int32_t)X.nlines;
             r.wpl = X.wpl;
+            r.seg = X.seg;
             r.lpb = X.lpb;
             r.v16 = P.S <= 8 && (X.n % (int)(16 / P.S) == 0) && (reinterpret_cast<uintptr_t>(s->psi) % 16 == 0);
             r.sig_re = X.sig_re;
@@ -541,6 +562,9 @@ static hipError_t enqueue_step(sscn_solver *s, bool do_renorm, Timer *tm)
             r.pp = point_params(s);
             r.scale = scal;
             r.partial = last ? part : nullptr;
+            r.fold = fold_in ? part : nullptr;
+            r.fold_np = P.np_norm;
+            r.fold_dvol = inner_dvol(pb);
             CHK(launch_row(P.elem, X.C, last, r, X.grid, X.block, X.lds, s->st, e0, e1));
         } else if (X.kind == K_RAD) {
             const bool rlast = imag && do_renorm && dim == 1;
@@ -593,7 +617,7 @@ static hipError_t enqueue_step(sscn_solver *s, bool do_renorm, Timer *tm)
     // step that does not renormalise, unless its last sweep is a COL kernel,
     // which resets the scale itself
     const bool col_reset = dim > 1 && P.ax[dim - 1].kind == K_COL;
-    if (imag && (do_renorm ? !P.fused_norm : !col_reset)) {
+    if (imag && (do_renorm ? !P.fused_norm && final_sum : !col_reset)) {
         if (tm) tm->pair(3, e0, e1);
         if (e0) CHK(hipEventRecord(e0, s->st));
         if (do_renorm && P.sep_norm)
@@ -610,7 +634,9 @@ static hipError_t enqueue_step(sscn_solver *s, bool do_renorm, Timer *tm)
 // steps with one call.  A call of n steps replays the graphs of its binary
 // decomposition into runs of 32, 16, ..., 1 steps, so every length is
 // replayed, not only multiples of 32.  The replayed kernels and arguments are
-// those the direct path would launch, so results are the same.
+// those the direct path would launch, except that a plan that folds the
+// norm's final sum into the next step ends every run with it (the folded
+// factor is bitwise the one the final sum writes), so results are the same.
 constexpr int kGraphLog = 5;                 // longest run: 32 steps
 constexpr size_t kMaxGraphs = 192;           // renormalisation patterns x lengths
 
@@ -639,9 +665,13 @@ static hipError_t capture_run(sscn_solver *s, int64_t after_step, int lg, hipGra
     hipError_t e = hipStreamBeginCapture(s->st, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return e;
     hipError_t le = hipSuccess;
-    for (int64_t k = 1; k <= (int64_t(1) << lg) && le == hipSuccess; ++k) {
+    const int64_t len = int64_t(1) << lg;
+    bool prev_renorm = false;
+    for (int64_t k = 1; k <= len && le == hipSuccess; ++k) {
         const int64_t step = after_step + k;
-        le = enqueue_step(s, imag && (step % s->pb.renorm_every == 0), nullptr);
+        const bool renorm = imag && (step % s->pb.renorm_every == 0);
+        le = enqueue_step(s, renorm, s->P.fold_norm && prev_renorm, !s->P.fold_norm || k == len, nullptr);
+        prev_renorm = renorm;
     }
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(s->st, &g);
@@ -713,13 +743,17 @@ static hipError_t enqueue_steps(sscn_solver *s, int64_t nsteps, Timer *tm)
         nsteps -= int64_t(1) << lg;
         last_renorm = imag && (s->step % s->pb.renorm_every == 0);
     }
+    // direct launches: the rest of the call is one run
+    bool prev_renorm = false;
     for (int64_t t = 0; t < nsteps; ++t) {
         const int64_t step = s->step + 1;
         const bool do_renorm = imag && (step % s->pb.renorm_every == 0);
-        hipError_t e = enqueue_step(s, do_renorm, tm);
+        hipError_t e = enqueue_step(s, do_renorm, s->P.fold_norm && prev_renorm,
+                                    !s->P.fold_norm || t == nsteps - 1, tm);
         if (e != hipSuccess) return e;
         s->step = step;
         last_renorm = do_renorm;
+        prev_renorm = do_renorm;
     }
     if (imag && last_renorm) {
         hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -841,7 +875,7 @@ int sscn_plan_info(const sscn_problem *pb, int32_t *info, int32_t cap)
         o[0] = used ? X.kind : -1;
         o[1] = used ? X.C : 0;
         o[2] = used ? ((X.kind == K_ROW || X.kind == K_RAD) ? X.wpl : X.W) : 0;
-        o[3] = used ? (X.kind == K_COL ? X.L : 1) : 0;
+        o[3] = used ? (X.kind == K_COL ? X.L : (X.kind == K_ROW ? X.seg : 1)) : 0;
         o[4] = used ? X.grid : 0;
         o[5] = used ? X.block : 0;
         o[6] = used ? X.i_conv : 0;

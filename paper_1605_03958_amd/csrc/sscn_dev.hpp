@@ -222,4 +222,20 @@ __device__ __forceinline__ double block_sum(double v, double *red)
     return s;
 }
 
+// The renormalisation factor 1/sqrt(dvol * sum) over np <= 64 * kFoldWaves
+// partials, formed by one whole wave in k_norm_final's order (partial i on
+// thread i of its 1024-thread block, the 64-lane wave sums added in wave
+// order, zero sums left out: adding +0 changes nothing), so every wave of
+// another kernel obtains bitwise the factor k_norm_final would write.
+// p[w] holds partial w*64 + lane, zero past np.
+constexpr int kFoldWaves = 4;
+__device__ __forceinline__ double fold_scale(const double (&p)[kFoldWaves], int np, double dvol)
+{
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < kFoldWaves; ++w)
+        if (w * 64 < np) s += wave_sum(p[w]);
+    return 1.0 / sqrt(dvol * s);
+}
+
 }  // namespace sscn

@@ -9,6 +9,9 @@
 //           emits one FP64 partial of sum |psi|^2 per block.
 //   k_norm_final  fixed-order sum of those partials -> renormalisation
 //           factor kept on the device and applied by the next k_row load.
+//           With few partials (small grids) the next step's k_row forms the
+//           factor itself, bitwise alike, and k_norm_final only ends a run
+//           of steps: one launch less per step.
 // Fallbacks for lines too long to keep in registers: k_pointwise (separate
 // pointwise substep), k_stream (one thread per line, exact Thomas with the
 // forward intermediates stored in place) and k_norm_partials.
@@ -20,11 +23,12 @@ namespace sscn {
 
 // ===========================================================================
 // ROW: x lines, G = 64 * wpl threads per line, C points per thread.
-// Single-wave lines (MW = false) stage the lane-major table (C * 64 entries)
+// Single-wave lines (MW = false) stage the lane-major table (C * G entries)
 // in LDS; multi-wave lines (MW = true, long 1D lines) read it from global
-// memory and exchange 4 values per wave through LDS.
+// memory and exchange 4 values per wave through LDS.  SEG < 64: lines of at
+// most SEG * C points, G = SEG lanes each, 64/SEG lines per wave.
 // ===========================================================================
-template <class T, bool CPLX, int C, bool LAST, bool MW>
+template <class T, bool CPLX, int C, bool LAST, bool MW, int SEG = 64>
 __global__ void __launch_bounds__(MW ? 1024 : 256) k_row(RowArgs a)
 {
     using A = Alg<T, CPLX>;
@@ -32,7 +36,7 @@ __global__ void __launch_bounds__(MW ? 1024 : 256) k_row(RowArgs a)
     extern __shared__ unsigned char lds_raw[];
     __shared__ double red[16];
 
-    const int G = MW ? 64 * a.wpl : 64;
+    const int G = MW ? 64 * a.wpl : SEG;
     const int tid = threadIdx.x;
     const int lb = tid / G;
     const int t = tid - lb * G;
@@ -41,50 +45,99 @@ __global__ void __launch_bounds__(MW ? 1024 : 256) k_row(RowArgs a)
     LTab<T, CPLX> *tl = reinterpret_cast<LTab<T, CPLX> *>(lds_raw);
     V *xs = reinterpret_cast<V *>(lds_raw) + lb * a.wpl * 4;
     const V sig = A::coef(a.sig_re, a.sig_im);
-    const T scale = CPLX ? T(1) : T(*a.scale);
+    // the pending renormalisation factor: from memory, or (short lines of
+    // small grids) formed from the previous step's norm partials once this
+    // wave's first line is loaded (their loads overlap the line's)
+    T scale = T(1);
+    double fp[kFoldWaves];
+    bool need = false;
+    if constexpr (!CPLX) {
+        if (SEG < 64 && a.fold) {
+#pragma unroll
+            for (int w = 0; w < kFoldWaves; ++w)
+                fp[w] = (w * 64 + lane < a.fold_np) ? a.fold[w * 64 + lane] : 0.0;
+            need = true;
+        } else {
+            scale = T(*a.scale);
+        }
+    }
     const T dt = T(a.pp.dt), g = T(a.pp.g);
     V *psi = reinterpret_cast<V *>(a.psi);
     double nacc = 0.0;
 
-    if constexpr (!MW) {
-        stage_table<T, CPLX>(a.lt, tl, C * G, G, C);
-        __syncthreads();
-    }
     // single-wave lines move their values through a per-wave LDS buffer
     // after the table (row_load_tr), so every global access is coalesced,
     // when table and buffers fit 64 KB (the host sizes the LDS alike)
-    constexpr bool TR = sizeof(V) >= 16 &&
+    constexpr bool TR = SEG == 64 && sizeof(V) >= 16 &&
                         (size_t)C * 64 * sizeof(LTab<T, CPLX>) + 4 * ((size_t)C * 64 + 64) * sizeof(V) <= 65536;
     V *buf = reinterpret_cast<V *>(tl + C * G) + lb * (C * 64 + 64);
     // 4- and 8-byte values move as 16-byte groups where the line length and
     // the state's alignment allow (a.v16)
     constexpr bool V16 = sizeof(V) <= 8 && C % (16 / sizeof(V)) == 0;
-    for (long long gb = (long long)blockIdx.x * a.lpb; gb < a.nlines;
-         gb += (long long)gridDim.x * a.lpb) {
-        const long long line = gb + lb;
-        const bool active = line < a.nlines;
-        if constexpr (MW) {
-            nacc += row_line<T, CPLX, C, true>(psi, line, active, a.lt.n, a.lt.tab, G, t, lane, wl, a.wpl, xs,
-                                               sig, scale, dt, g, a.pp, a.lt.depth, LAST);
-        } else if constexpr (V16) {
-            V u[C];
-            if (a.v16) row_load_v16<T, CPLX, C>(psi, line, active, a.lt.n, t, u);
-            else row_load<T, CPLX, C>(psi, line, active, a.lt.n, t, u);
-            nacc += row_solve<T, CPLX, C, false>(psi, line, active, a.lt.n, static_cast<const LTab<T, CPLX> *>(tl),
-                                                 G, t, lane, wl, 1, xs, sig, scale, dt, g, a.pp, a.lt.depth, LAST, u,
-                                                 true);
-            if (a.v16) row_store_v16<T, CPLX, C>(psi, line, active, a.lt.n, t, u);
-            else row_store<T, CPLX, C>(psi, line, active, a.lt.n, t, u);
-        } else if constexpr (TR) {
-            V u[C];
-            row_load_tr<T, CPLX, C>(psi, line, active, a.lt.n, lane, buf, u);
-            nacc += row_solve<T, CPLX, C, false>(psi, line, active, a.lt.n, static_cast<const LTab<T, CPLX> *>(tl),
-                                                 G, t, lane, wl, 1, xs, sig, scale, dt, g, a.pp, a.lt.depth, LAST, u,
-                                                 true);
-            row_store_tr<T, CPLX, C>(psi, line, active, a.lt.n, lane, buf, u);
-        } else {
-            nacc += row_line<T, CPLX, C, false>(psi, line, active, a.lt.n, static_cast<const LTab<T, CPLX> *>(tl),
-                                                G, t, lane, wl, 1, xs, sig, scale, dt, g, a.pp, a.lt.depth, LAST);
+    const long long gstep = (long long)gridDim.x * a.lpb;
+    if constexpr (MW) {
+        for (long long gb = (long long)blockIdx.x * a.lpb; gb < a.nlines; gb += gstep) {
+            const long long line = gb + lb;
+            if (need) {
+                scale = T(fold_scale(fp, a.fold_np, a.fold_dvol));
+                need = false;
+            }
+            nacc += row_line<T, CPLX, C, true>(psi, line, line < a.nlines, a.lt.n, a.lt.tab, G, t, lane, wl, a.wpl,
+                                               xs, sig, scale, dt, g, a.pp, a.lt.depth, LAST);
+        }
+    } else {
+        auto load = [&](long long line, bool active, V (&u)[C]) {
+            if constexpr (V16) {
+                if (a.v16) row_load_v16<T, CPLX, C>(psi, line, active, a.lt.n, t, u);
+                else row_load<T, CPLX, C>(psi, line, active, a.lt.n, t, u);
+            } else if constexpr (TR) {
+                row_load_tr<T, CPLX, C>(psi, line, active, a.lt.n, lane, buf, u);
+            } else {
+                row_load<T, CPLX, C>(psi, line, active, a.lt.n, t, u);
+            }
+        };
+        // short lines (small grids: a block has one line group): the first
+        // line's values are loaded before the table is staged, so that the
+        // two memory latencies overlap.  Longer lines keep a plain loop (the
+        // early load measured slower there)
+        const long long gb0 = (long long)blockIdx.x * a.lpb;
+        V u[C];
+        bool loaded = false;
+        if constexpr (SEG < 64) {
+            if (gb0 < a.nlines) {
+                load(gb0 + lb, gb0 + lb < a.nlines, u);
+                loaded = true;
+            }
+        }
+        stage_table<T, CPLX>(a.lt, tl, C * G, G, C);
+        __syncthreads();
+        for (long long gb = gb0; gb < a.nlines; gb += gstep) {
+            const long long line = gb + lb;
+            const bool active = line < a.nlines;
+            if constexpr (SEG < 64) {
+                if (!loaded) load(line, active, u);
+                loaded = false;
+            } else {
+                load(line, active, u);
+            }
+            if (need) {
+                scale = T(fold_scale(fp, a.fold_np, a.fold_dvol));
+                need = false;
+            }
+            const LTab<T, CPLX> *tc = tl;
+            if constexpr (V16) {
+                nacc += row_solve<T, CPLX, C, false, true, SEG>(psi, line, active, a.lt.n, tc, G, t, lane, wl, 1, xs, sig,
+                                                     scale, dt, g, a.pp, a.lt.depth, LAST, u, true);
+                if (a.v16) row_store_v16<T, CPLX, C>(psi, line, active, a.lt.n, t, u);
+                else row_store<T, CPLX, C>(psi, line, active, a.lt.n, t, u);
+            } else if constexpr (TR) {
+                nacc += row_solve<T, CPLX, C, false, true, SEG>(psi, line, active, a.lt.n, tc, G, t, lane, wl, 1, xs, sig,
+                                                     scale, dt, g, a.pp, a.lt.depth, LAST, u, true);
+                row_store_tr<T, CPLX, C>(psi, line, active, a.lt.n, lane, buf, u);
+            } else {
+                nacc += row_solve<T, CPLX, C, false, true, SEG>(psi, line, active, a.lt.n, tc, G, t, lane, wl, 1, xs, sig,
+                                                     scale, dt, g, a.pp, a.lt.depth, LAST, u);
+            }
         }
     }
     if constexpr (LAST) {
@@ -120,9 +173,14 @@ __global__ void __launch_bounds__(1024) k_col(ColArgs a)
     const bool active = line < a.nlines;
     long long base = 0;
     if (active) base = (line % a.m1) * a.s1 + (line / a.m1) * a.s2;
+    // the values are loaded before the table is staged, so that the two
+    // memory latencies overlap; col_solve synchronises the block before it
+    // reads the table
+    V u[C];
+    col_load<T, CPLX, C>(reinterpret_cast<V *>(a.psi), active, base, a.lt.n, a.stride, ch, u);
     stage_table<T, CPLX>(a.lt, tb, nch * C, 0, C);
-    double nacc = col_tile<T, CPLX, C>(reinterpret_cast<V *>(a.psi), active, base, a.lt.n, a.stride, nch, ch,
-                                       LPB, li, tb, xs0, xs1, A::coef(a.sig_re, a.sig_im), a.lt.depth, LAST);
+    double nacc = col_solve<T, CPLX, C>(reinterpret_cast<V *>(a.psi), active, base, a.lt.n, a.stride, nch, ch, LPB,
+                                        li, tb, xs0, xs1, A::coef(a.sig_re, a.sig_im), a.lt.depth, LAST, u);
     if (a.unit_scale && blockIdx.x == 0 && threadIdx.x == 0) *a.unit_scale = 1.0;
     if constexpr (LAST) {
         // the axial trap weighs each z line by its radial cell weight
@@ -510,6 +568,18 @@ static void row_launch_c(bool last, const RowArgs &a, int grid, int block, size_
                          hipEvent_t e0, hipEvent_t e1)
 {
     const bool mw = a.wpl > 1;
+    if constexpr (C == 4) {
+        // lines of at most 64 points: 16 lanes each, four per wave
+        if (a.seg == 16 && !mw) {
+            if (last)
+                hipExtLaunchKernelGGL((k_row<T, CPLX, C, true, false, 16>), dim3(grid), dim3(block), lds, st, e0, e1, 0,
+                                      a);
+            else
+                hipExtLaunchKernelGGL((k_row<T, CPLX, C, false, false, 16>), dim3(grid), dim3(block), lds, st, e0, e1,
+                                      0, a);
+            return;
+        }
+    }
     if (last && mw)
         hipExtLaunchKernelGGL((k_row<T, CPLX, C, true, true>), dim3(grid), dim3(block), lds, st, e0, e1, 0, a);
     else if (last)

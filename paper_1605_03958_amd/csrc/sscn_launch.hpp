@@ -30,12 +30,18 @@ struct RowArgs {
     LineTab lt;            // tab lane-major: entry (k, t) at [k * 64 * wpl + t]
     int32_t nlines;        // n_y * n_z
     int32_t wpl;           // waves per line (power of two, <= 16)
+    int32_t seg;           // lanes per line within a wave: 64, or 16 (lines of <= 64 points, C = 4)
     int32_t lpb;           // lines per block
     int32_t v16;           // 1: 16-byte groups of 4- or 8-byte values (line length a multiple, psi aligned)
     double sig_re, sig_im; // CN coefficient s
     PointParams pp;
     const double *scale;   // pending renormalisation factor (imaginary time)
     double *partial;       // norm partial per block when this is the last sweep
+    // non-null: the factor is not in *scale but formed from the previous
+    // step's fold_np (<= 64 * kFoldWaves) norm partials, as k_norm_final would
+    const double *fold;
+    int32_t fold_np;
+    double fold_dvol;
 };
 
 // y or z sweep (COL geometry) and the one-thread-per-line fallback.

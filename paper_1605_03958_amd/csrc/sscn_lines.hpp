@@ -296,8 +296,11 @@ __device__ __forceinline__ LTab<T, CPLX> row_tab(const TB *tb, int k, int G, int
 // caller can issue the next line's loads before solving the current one;
 // row_line does both.  With `keep` the solution replaces u instead of being
 // stored (a caller that holds its line in registers across steps).
+// SEG < 64: a wave holds 64/SEG lines of SEG lanes each (t = lane % SEG,
+// G = SEG); the scans stop at the segment's ends, so short lines take fewer
+// scan steps and fewer lanes' worth of per-line work.
 // ---------------------------------------------------------------------------
-template <class T, bool CPLX, int C, bool MW, bool UNR = true, class TB, class PV>
+template <class T, bool CPLX, int C, bool MW, bool UNR = true, int SEG = 64, class TB, class PV>
 __device__ __forceinline__ double row_solve(PV __restrict__ psi, long long line,
                                             bool active, int n, const TB *tb, int G, int t, int lane, int wl,
                                             int wpl, typename Alg<T, CPLX>::V *xs, typename Alg<T, CPLX>::V sig,
@@ -306,6 +309,9 @@ __device__ __forceinline__ double row_solve(PV __restrict__ psi, long long line,
 {
     using A = Alg<T, CPLX>;
     using V = typename A::V;
+    static_assert(SEG == 64 || (!MW && SEG >= 1 && SEG < 64 && (SEG & (SEG - 1)) == 0), "segment of a wave");
+    constexpr int LOGS = SEG >= 64 ? 6 : SEG >= 32 ? 5 : SEG >= 16 ? 4 : SEG >= 8 ? 3 : SEG >= 4 ? 2 : SEG >= 2 ? 1 : 0;
+    const int sl = lane & (SEG - 1);   // lane within the line's segment
     const int i0 = t * C;
     const long long base = line * (long long)n;
 
@@ -331,8 +337,8 @@ __device__ __forceinline__ double row_solve(PV __restrict__ psi, long long line,
     // registers live -- the batched kernels, which are register-bound)
     V left = UNR ? A::shfl_up(u[C - 1], 1) : A::xshfl_up(u[C - 1], 1);
     V right = UNR ? A::shfl_down(u[0], 1) : A::xshfl_down(u[0], 1);
-    if (lane == 0) left = A::zero();
-    if (lane == 63) right = A::zero();
+    if (sl == 0) left = A::zero();
+    if (sl == SEG - 1) right = A::zero();
     if constexpr (MW) {
         if (lane == 0) xs[wl * 4 + 0] = u[0];
         if (lane == 63) xs[wl * 4 + 1] = u[C - 1];
@@ -366,11 +372,11 @@ __device__ __forceinline__ double row_solve(PV __restrict__ psi, long long line,
         if constexpr (UNR) {
             // unrolled: each step's lane distance is a constant
 #pragma unroll
-            for (int s = 0; s < 6; ++s) {
+            for (int s = 0; s < LOGS; ++s) {
                 if (s >= ks) break;
                 const int o = 1 << s;
                 const V a2 = A::shfl_up(PA, o), b2 = A::shfl_up(PB, o);
-                if (lane >= o) {
+                if (sl >= o) {
                     PB = A::fma(PA, b2, PB);
                     PA = A::mul(PA, a2);
                 }
@@ -379,14 +385,14 @@ __device__ __forceinline__ double row_solve(PV __restrict__ psi, long long line,
             for (int s = 0; s < ks; ++s) {
                 const int o = 1 << s;
                 const V a2 = A::xshfl_up(PA, o), b2 = A::xshfl_up(PB, o);
-                if (lane >= o) {
+                if (sl >= o) {
                     PB = A::fma(PA, b2, PB);
                     PA = A::mul(PA, a2);
                 }
             }
         }
         V EA = UNR ? A::shfl_up(PA, 1) : A::xshfl_up(PA, 1), EB = UNR ? A::shfl_up(PB, 1) : A::xshfl_up(PB, 1);
-        if (lane == 0) {
+        if (sl == 0) {
             EA = A::one();
             EB = A::zero();
         }
@@ -423,11 +429,11 @@ __device__ __forceinline__ double row_solve(PV __restrict__ psi, long long line,
         V PA = Ac, PB = v;
         if constexpr (UNR) {
 #pragma unroll
-            for (int s = 0; s < 6; ++s) {
+            for (int s = 0; s < LOGS; ++s) {
                 if (s >= ks) break;
                 const int o = 1 << s;
                 const V a2 = A::shfl_down(PA, o), b2 = A::shfl_down(PB, o);
-                if (lane + o < 64) {
+                if (sl + o < SEG) {
                     PB = A::fma(PA, b2, PB);
                     PA = A::mul(PA, a2);
                 }
@@ -436,7 +442,7 @@ __device__ __forceinline__ double row_solve(PV __restrict__ psi, long long line,
             for (int s = 0; s < ks; ++s) {
                 const int o = 1 << s;
                 const V a2 = A::xshfl_down(PA, o), b2 = A::xshfl_down(PB, o);
-                if (lane + o < 64) {
+                if (sl + o < SEG) {
                     PB = A::fma(PA, b2, PB);
                     PA = A::mul(PA, a2);
                 }
@@ -444,7 +450,7 @@ __device__ __forceinline__ double row_solve(PV __restrict__ psi, long long line,
         }
         V EA = UNR ? A::shfl_down(PA, 1) : A::xshfl_down(PA, 1),
           EB = UNR ? A::shfl_down(PB, 1) : A::xshfl_down(PB, 1);
-        if (lane == 63) {
+        if (sl == SEG - 1) {
             EA = A::one();
             EB = A::zero();
         }
@@ -600,7 +606,7 @@ __device__ __forceinline__ double row_line(PV __restrict__ psi, long long line,
 {
     typename Alg<T, CPLX>::V u[C];
     row_load<T, CPLX, C>(psi, line, active, n, t, u);
-    return row_solve<T, CPLX, C, MW, UNR, TB, PV>(psi, line, active, n, tb, G, t, lane, wl, wpl, xs, sig, scale, dt,
+    return row_solve<T, CPLX, C, MW, UNR, 64, TB, PV>(psi, line, active, n, tb, G, t, lane, wl, wpl, xs, sig, scale, dt,
                                                   g, pp, ks, last, u);
 }
 

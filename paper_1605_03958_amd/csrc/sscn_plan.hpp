@@ -21,6 +21,7 @@ struct AxisPlan {
     int n;
     int C;        // points per thread
     int wpl;      // ROW: waves per line
+    int seg;      // ROW: lanes per line within a wave (64, or 16: four short lines per wave)
     int lpb;      // ROW: lines per block
     int W;        // COL: waves per block
     int L;        // COL: lanes per line (chunks per line = W * L)
@@ -45,6 +46,7 @@ struct Plan {
     AxisPlan ax[3];
     bool sep_pointwise, sep_norm;
     bool fused_norm;       // the last sweep's single block also finalises the norm
+    bool fold_norm;        // the next step's x sweep forms the factor from the partials
     int pw_grid, np_norm, obs_grid;
     int dens_blocks;       // row blocks of the n_1D-along-x partial sums
     size_t off_scal, off_obs, off_part, off_obspart, off_dens, ws_bytes;

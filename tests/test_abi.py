@@ -102,6 +102,26 @@ def test_plan_geometries():
     assert info[1] is None
     p = Problem(1, (300000, 1, 1), (0.1,), (1,), 1.0, 1e-3, IMAG, F64, 1)
     assert sscn.plan_info(p)[0]["kind"] == "stream"
+    # x lines of at most 64 points: chunks of 4 over 16 lanes, four lines
+    # per wave (16 per 256-thread block), scans of at most 4 steps
+    for nx in (1, 5, 63, 64):
+        for prec in (F64, F32):
+            for mode in (IMAG, REAL):
+                p = Problem(3, (nx, 64, 64), (0.2,) * 3, (1, 1.5, 2), 22.0, 0.004, mode, prec, 1 if mode == IMAG else 0)
+                q = sscn.plan_info(p)[0]
+                assert (q["kind"], q["chunk"], q["lanes"], q["block"]) == ("row", 4, 16, 256), (nx, prec, mode)
+                assert q["grid"] == 64 * 64 // 16 and q["depth"] <= 4
+    p = Problem(3, (65, 64, 64), (0.2,) * 3, (1, 1.5, 2), 22.0, 0.004, IMAG, F64, 1)
+    q = sscn.plan_info(p)[0]
+    assert (q["chunk"], q["lanes"]) == (2, 64)
+    # a tile hint of another chunk length keeps 64 lanes per line
+    p = Problem(3, (64, 64, 64), (0.2,) * 3, (1, 1.5, 2), 22.0, 0.004, IMAG, F64, 1)
+    try:
+        sscn.set_tile_hint(p, (1, 0, 0))
+        q = sscn.plan_info(p)[0]
+        assert (q["chunk"], q["lanes"], q["grid"]) == (1, 64, 64 * 64 // 4)
+    finally:
+        sscn.clear_tile_hints()
     p = Problem(2, (64, 700, 1), (0.1, 0.1), (1, 1), 1.0, 1e-3, REAL, F64, 0)
     assert sscn.plan_info(p)[1]["kind"] == "col" and sscn.plan_info(p)[1]["lanes"] == 4
     p = Problem(2, (64, 5000, 1), (0.1, 0.1), (1, 1), 1.0, 1e-3, REAL, F64, 0)

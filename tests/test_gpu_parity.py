@@ -474,10 +474,14 @@ def test_checkpoint_and_resume_is_bitwise(mode, prec):
 def test_graph_replay_equals_direct_launches():
     """Runs of steps replayed from captured graphs give bitwise the state
     of direct launches: imaginary time with renormalisation every 3 steps
-    (runs start at every phase), real time with a quench between runs, and a
-    solver on the legacy default stream (always direct)."""
+    (runs start at every phase) and every step (the x sweep forms the factor
+    from the previous step's partials inside a run, the final-sum kernel
+    ends each run: one-step runs never fold), real time with a quench between
+    runs, and a solver on the legacy default stream (always direct)."""
     import torch
-    for mode, every in ((IMAG, 3), (REAL, 0)):
+    p1 = Problem(3, (20, 24, 18), (0.2, 0.2, 0.2), (1.0, 1.5, 2.0), 8.0, 0.004, IMAG, F64, 1)
+    assert sscn.plan_info(p1)[0]["lanes"] == 16
+    for mode, every in ((IMAG, 3), (IMAG, 1), (REAL, 0)):
         p = Problem(3, (20, 24, 18), (0.2, 0.2, 0.2), (1.0, 1.5, 2.0), 8.0, 0.004 if mode == IMAG else 0.0008,
                     mode, F64, every)
         if mode == IMAG:
