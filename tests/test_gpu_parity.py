@@ -124,6 +124,32 @@ def test_tile_hints_give_the_same_result(chunks):
     assert rel_l2(got, ref) <= 1e-12
 
 
+@pytest.mark.parametrize("nx,chunk,lanes", [(37, 4, 16), (64, 4, 16), (2, 4, 16), (65, 2, 64)])
+@pytest.mark.parametrize("mode,prec", [(IMAG, F64), (REAL, F64), (IMAG, F32), (REAL, F32)])
+def test_x_lines_shorter_than_a_wave(nx, chunk, lanes, mode, prec):
+    """x lines of at most 64 points over 16 lanes (four lines per wave),
+    ragged lengths included, and the 64-lane form just above, against the
+    oracle."""
+    p = Problem(3, (nx, 12, 10), (0.05, 0.3, 0.3), (1.0, 1.5, 2.0), 9.0,
+                0.1 * 0.05 ** 2 if mode == IMAG else 0.02 * 0.05 ** 2, mode, prec, 1 if mode == IMAG else 0)
+    psi0 = initial(p, 13)
+    try:
+        if chunk != 4:
+            sscn.set_tile_hint(p, (chunk, 0, 0))
+        q = sscn.plan_info(p)[0]
+        assert (q["kind"], q["chunk"], q["lanes"]) == ("row", chunk, lanes)
+        s = sscn.Solver(p, psi0)
+        s.step(25)
+        got = s.state()
+        s.close()
+    finally:
+        sscn.clear_tile_hints()
+    ref = oracle.run(oprob(p), psi0, 25).psi
+    err = rel_l2(got, ref)
+    print(f"case nx={nx} chunk={chunk} mode={mode} prec={prec}: rel-L2 {err:.2e}", flush=True)
+    assert err <= (1e-12 if prec == F64 else 1e-5)
+
+
 def test_ground64_1000_steps():
     """64^3 imaginary time, g = 22, FP64: rel-L2 <= 1e-10 after 500 and 1000
     steps, mu and E to 1e-10."""
