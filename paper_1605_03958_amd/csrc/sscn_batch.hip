@@ -496,6 +496,9 @@ __device__ __forceinline__ bool solo_fast(const BInst &I, BState &S, BState &sS,
         if (X.wpl > 1) {
             switch (X.C) {
             case 8: SOLO(false, 8, true); return true;
+            case 12:
+                if constexpr (BIG) { SOLO(false, 12, true); return true; }
+                return false;
             case 16:
                 if constexpr (BIG) { SOLO(false, 16, true); return true; }
                 return false;
@@ -550,6 +553,9 @@ __device__ __forceinline__ void batch_sweep(KP<BInst> I, const BState &S, int pa
             switch (X.C) {
             case 4: batch_row<T, CPLX, 4, true>(I, S, tile, lds, red, last); break;
             case 8: batch_row<T, CPLX, 8, true>(I, S, tile, lds, red, last); break;
+            case 12:
+                if constexpr (BIG && !CPLX) batch_row<T, CPLX, 12, true>(I, S, tile, lds, red, last);
+                break;
             case 16:
                 if constexpr (BIG) batch_row<T, CPLX, 16, true>(I, S, tile, lds, red, last);
                 break;
@@ -594,8 +600,9 @@ __device__ __forceinline__ void batch_sweep(KP<BInst> I, const BState &S, int pa
     }
 }
 
-// BIG adds the variants for 1D lines longer than 8192 points (16 points per
-// thread over the whole block), whose registers the other paths do not need.
+// BIG adds the variants for 1D lines longer than 8192 points (12 or 16
+// points per thread over the whole block), whose registers the other paths
+// do not need.
 template <bool BIG>
 __global__ void __launch_bounds__(BATCH_BLOCK) k_batch_step(BatchArgs a)
 {

@@ -196,8 +196,11 @@ int batch_plan(const sscn_problem &pb, BPlan &B, int parts = kDefaultSplit)
                     wpl = p2ceil(cdiv(n, 64 * 8));
                 }
                 if (wpl > 16) {
-                    c = 16;                     // ... or 16 (long 1D lines)
-                    wpl = p2ceil(cdiv(n, 64 * 16));
+                    // ... or, long 1D lines, 12 (real, when 16 waves of 12
+                    // cover the line: fewer points per thread and fewer
+                    // waves past the line end than 16) or 16
+                    c = (!cplx && n <= (int64_t)16 * 64 * 12) ? 12 : 16;
+                    wpl = p2ceil(cdiv(n, 64 * c));
                     B.big = true;
                 }
                 if (wpl > 16) return SSCN_E_UNSUPPORTED;
