@@ -14,10 +14,14 @@
 
 namespace sscn {
 
+// FP32: the hardware base-2 exponential of x log2(e) (within about 2 ulp
+// for the arguments of the pointwise substep); the library form spends a
+// dozen instructions per point on range reduction and rounding below the
+// FP32 state's own rounding.
 template <class T>
 __device__ __forceinline__ T dev_exp(T x)
 {
-    if constexpr (sizeof(T) == 8) return exp(x); else return expf(x);
+    if constexpr (sizeof(T) == 8) return exp(x); else return __expf(x);
 }
 
 template <class T>
@@ -130,10 +134,14 @@ apply_point(typename Alg<T, CPLX>::V u, T scale, T vpot, T dt, T g)
     }
 }
 
+// Grid coordinate (i - cen) dx: FP64 for FP64 states; FP32 for FP32 ones
+// (i - cen is a multiple of 1/2 below 2^23, exact in FP32, so only dx and
+// the product round).
 template <class T>
 __device__ __forceinline__ T coord(int i, double cen, double dx)
 {
-    return T((double(i) - cen) * dx);
+    if constexpr (sizeof(T) == 4) return (T(i) - T(cen)) * T(dx);
+    else return T((double(i) - cen) * dx);
 }
 
 // A Thomas table entry as the sweeps use it.  FP64: (alpha, m).  FP32: each
