@@ -327,39 +327,62 @@ __global__ void __launch_bounds__(256) k_obs_partials(ObsArgs a)
     int idx[3] = {(int)(p % nx), (int)((p / nx) % ny), (int)(p / (nx * ny))};
     const int di = (int)(stride % nx), dj = (int)((stride / nx) % ny), dk = (int)(stride / (nx * ny));
     (void)nz;
-    for (; p < a.npts; p += stride) {
-        const V v = psi[p];
-        const double q = A::norm2(v);
-        double vp = 0.0, kin = 0.0;
+    // U grid-stride points per pass: all their loads (the point and its
+    // three forward neighbours) are issued before any is used, so a pass
+    // waits for memory once; the sums take the points in the same order as
+    // one point per pass
+    constexpr int U = 4;
+    for (; p < a.npts; p += U * stride) {
+        V v[U], nb[U][3];
+        int id[U][3];
 #pragma unroll
-        for (int ax = 0; ax < 3; ++ax) {
-            if (ax >= a.dim) break;
-            const double x = (double(idx[ax]) - a.cen[ax]) * a.dx[ax];
-            vp = fmaT(a.w2h[ax] * x, x, vp);
-            acc[4 + ax] = fmaT(x, q, acc[4 + ax]);
-            acc[7 + ax] = fmaT(x * x, q, acc[7 + ax]);
-            const V nb = (idx[ax] + 1 < a.n[ax]) ? psi[p + sx[ax]] : A::zero();
-            double e = A::norm2(A::sub(nb, v));
-            if (idx[ax] == 0) e += q;
-            kin = fmaT(e, inv2[ax], kin);
+        for (int u = 0; u < U; ++u) {
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) id[u][ax] = idx[ax];
+            int c = 0;
+            idx[0] += di;
+            if (idx[0] >= a.n[0]) {
+                idx[0] -= a.n[0];
+                c = 1;
+            }
+            idx[1] += dj + c;
+            c = 0;
+            if (idx[1] >= a.n[1]) {
+                idx[1] -= a.n[1];
+                c = 1;
+            }
+            idx[2] += dk + c;
         }
-        acc[0] += q;
-        acc[1] += kin;
-        acc[2] = fmaT(vp, q, acc[2]);
-        acc[3] = fmaT(q, q, acc[3]);
-        int c = 0;
-        idx[0] += di;
-        if (idx[0] >= a.n[0]) {
-            idx[0] -= a.n[0];
-            c = 1;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const long long pu = p + (long long)u * stride;
+            const bool in = pu < a.npts;
+            v[u] = in ? psi[pu] : A::zero();
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax)
+                nb[u][ax] = (in && ax < a.dim && id[u][ax] + 1 < a.n[ax]) ? psi[pu + sx[ax]] : A::zero();
         }
-        idx[1] += dj + c;
-        c = 0;
-        if (idx[1] >= a.n[1]) {
-            idx[1] -= a.n[1];
-            c = 1;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (p + (long long)u * stride >= a.npts) break;
+            const double q = A::norm2(v[u]);
+            double vp = 0.0, kin = 0.0;
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) {
+                if (ax >= a.dim) break;
+                const double x = (double(id[u][ax]) - a.cen[ax]) * a.dx[ax];
+                vp = fmaT(a.w2h[ax] * x, x, vp);
+                acc[4 + ax] = fmaT(x, q, acc[4 + ax]);
+                acc[7 + ax] = fmaT(x * x, q, acc[7 + ax]);
+                double e = A::norm2(A::sub(nb[u][ax], v[u]));
+                if (id[u][ax] == 0) e += q;
+                kin = fmaT(e, inv2[ax], kin);
+            }
+            acc[0] += q;
+            acc[1] += kin;
+            acc[2] = fmaT(vp, q, acc[2]);
+            acc[3] = fmaT(q, q, acc[3]);
         }
-        idx[2] += dk + c;
     }
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
