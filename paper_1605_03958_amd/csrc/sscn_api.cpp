@@ -295,7 +295,7 @@ int make_plan(const sscn_problem &pb, const TileOverride *ov, Plan &P)
             // at 128 bytes or more.  A sweep of fewer than 256 blocks (one
             // per CU) takes more lanes per line, up to Lmax: fewer lines
             // and waves per block, more blocks (small grids)
-            const int lmax = std::max(1, std::min(4, (int)(P.S / 2)));
+            const int lmax = std::max(1, std::min(8, (int)(P.S / 2)));
             int c = 4;
             while (c < 64 && ceil_div(n, c) > 16 * lmax) c *= 2;
             c = std::min<int64_t>(c, pow2ceil(ceil_div(n, 16)));

@@ -122,8 +122,11 @@ def test_plan_geometries():
         assert (q["chunk"], q["lanes"], q["grid"]) == (1, 64, 64 * 64 // 4)
     finally:
         sscn.clear_tile_hints()
+    # (complex128: up to 8 lanes, a 128-byte row segment, when the sweep
+    # would launch fewer than 256 blocks)
     p = Problem(2, (64, 700, 1), (0.1, 0.1), (1, 1), 1.0, 1e-3, REAL, F64, 0)
-    assert sscn.plan_info(p)[1]["kind"] == "col" and sscn.plan_info(p)[1]["lanes"] == 4
+    assert sscn.plan_info(p)[1]["kind"] == "col" and sscn.plan_info(p)[1]["lanes"] == 8
+    assert sscn.plan_info(p)[1]["chunk"] == 8 and sscn.plan_info(p)[1]["grid"] == 8
     p = Problem(2, (64, 5000, 1), (0.1, 0.1), (1, 1), 1.0, 1e-3, REAL, F64, 0)
     assert sscn.plan_info(p)[1]["kind"] == "stream"
 

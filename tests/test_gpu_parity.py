@@ -60,6 +60,8 @@ SMALL = [
     (3, (17, 33, 9), (0.3, 0.2, 0.4), (1.2, 1.0, 2.0)),
     (3, (64, 48, 40), (0.2, 0.25, 0.3), (1.0, 1.5, 2.0)),
     (3, (65, 70, 33), (0.2, 0.2, 0.3), (1.0, 1.5, 2.0)),
+    (2, (48, 700, 1), (0.2, 0.02), (1.0, 1.5)),   # long y lines over 8 lanes (complex128)
+    (2, (32, 2000, 1), (0.2, 0.01), (1.0, 1.5)),  # 2000-point y lines: 16 waves x 8 lanes x 16 (complex128)
 ]
 
 
