@@ -204,6 +204,10 @@ void table_meta(AxisPlan &X, bool fp32)
 // Bytes of one staged table entry: (alpha, m) in FP64, hi/lo pairs in FP32.
 static size_t ltab_bytes(const Plan &P) { return (P.elem == 1 || P.elem == 3) ? 4 * P.S : 2 * P.S; }
 
+// Dynamic LDS of one COL block at most (the table and the two exchange
+// arrays; a gfx950 workgroup may take up to 160 KB).
+constexpr size_t kColLdsMax = 160 * 1024 - 1024;
+
 // Largest chunk length per thread kept in registers, by element size.
 static int cmax_row(size_t S) { return S >= 16 ? 8 : (S >= 8 ? 16 : 32); }
 static int cmax_col(size_t S) { return S >= 16 ? 16 : (S >= 8 ? 32 : 64); }
@@ -299,19 +303,24 @@ int make_plan(const sscn_problem &pb, const TileOverride *ov, Plan &P)
             int c = 4;
             while (c < 64 && ceil_div(n, c) > 16 * lmax) c *= 2;
             c = std::min<int64_t>(c, pow2ceil(ceil_div(n, 16)));
+            // a line longer than 16 waves x Lmax lanes x the longest chunk
+            // takes the longest chunk and up to 8 lanes (row segments down
+            // to 64 bytes) rather than the one-thread-per-line form
+            if (c > cmax_col(P.S)) c = cmax_col(P.S);
             if (ov && ov->col_c[a] > 0) c = ov->col_c[a];
             const int64_t K = ceil_div(n, c);           // chunks per line
             int L = pow2ceil(ceil_div(K, 16));          // lanes per line
             while (L < lmax && L < K && ceil_div(X.nlines, 64 / L) < 256) L *= 2;
             const int64_t W = ceil_div(K, L);
-            if (c <= cmax_col(P.S) && L <= 8) {
+            const size_t lds = (size_t)W * L * c * ltab_bytes(P) + (size_t)2 * W * 64 * P.S;
+            if (c <= cmax_col(P.S) && L <= 8 && lds <= kColLdsMax) {
                 X.kind = K_COL;
                 X.C = c;
                 X.W = (int)W;
                 X.L = L;
                 X.block = 64 * (int)W;
                 X.grid = (int)ceil_div(X.nlines, 64 / L);
-                X.lds = (size_t)W * L * c * ltab_bytes(P) + (size_t)2 * W * 64 * P.S;
+                X.lds = lds;
                 X.tab_entries = (size_t)W * L * c;
             }
         }

@@ -152,6 +152,28 @@ def test_x_lines_shorter_than_a_wave(nx, chunk, lanes, mode, prec):
     assert err <= (1e-12 if prec == F64 else 1e-5)
 
 
+@pytest.mark.parametrize("n,mode,prec,lanes", [(3000, IMAG, F64, 8), (4096, IMAG, F64, 8), (3000, REAL, F32, 8),
+                                                (6000, IMAG, F32, 8), (2000, REAL, F64, 8)])
+def test_long_column_lines_take_more_lanes(n, mode, prec, lanes):
+    """y lines longer than 16 waves x the 128-byte-segment lane count cover
+    (2048 points) take the longest chunk and up to 8 lanes instead of the
+    one-thread-per-line form; against the oracle."""
+    p = Problem(2, (16, n, 1), (0.2, 0.01), (1.0, 1.5), 6.0,
+                0.1 * 0.01 ** 2 if mode == IMAG else 0.02 * 0.01 ** 2, mode, prec, 1 if mode == IMAG else 0)
+    q = sscn.plan_info(p)[1]
+    assert q["kind"] == "col" and q["lanes"] == lanes
+    assert q["chunk"] * q["waves"] * q["lanes"] >= n
+    psi0 = initial(p, 17)
+    s = sscn.Solver(p, psi0)
+    s.step(25)
+    got = s.state()
+    s.close()
+    ref = oracle.run(oprob(p), psi0, 25).psi
+    err = rel_l2(got, ref)
+    print(f"case n={n} mode={mode} prec={prec}: rel-L2 {err:.2e}", flush=True)
+    assert err <= (1e-12 if prec == F64 else 1e-5)
+
+
 def test_ground64_1000_steps():
     """64^3 imaginary time, g = 22, FP64: rel-L2 <= 1e-10 after 500 and 1000
     steps, mu and E to 1e-10."""
