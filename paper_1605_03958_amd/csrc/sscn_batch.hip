@@ -542,24 +542,34 @@ __device__ __forceinline__ bool solo_fast(const BInst &I, BState &S, BState &sS,
 // ---------------------------------------------------------------------------
 // dispatch
 // ---------------------------------------------------------------------------
-template <class T, bool CPLX, bool BIG>
-__device__ __forceinline__ void batch_sweep(KP<BInst> I, const BState &S, int pass, int tile, unsigned char *lds,
+// FULL: every x-line form; otherwise only those of 2D and 3D instances (at
+// most 4 points per thread: one wave, or 4 per thread over several waves),
+// which leaves the kernel far fewer registers to spill.  Returns false when
+// the item's form is not in this kernel.
+template <class T, bool CPLX, bool BIG, bool FULL>
+__device__ __forceinline__ bool batch_sweep(KP<BInst> I, const BState &S, int pass, int tile, unsigned char *lds,
                                             double *red)
 {
     const bool last = pass == I->last_pass;
     const BAxis X = I->ax[pass];
+    bool done = true;
     if (pass == BP_X) {
         if (X.wpl > 1) {
             switch (X.C) {
             case 4: batch_row<T, CPLX, 4, true>(I, S, tile, lds, red, last); break;
-            case 8: batch_row<T, CPLX, 8, true>(I, S, tile, lds, red, last); break;
+            case 8:
+                if constexpr (FULL) batch_row<T, CPLX, 8, true>(I, S, tile, lds, red, last);
+                else done = false;
+                break;
             case 12:
-                if constexpr (BIG && !CPLX) batch_row<T, CPLX, 12, true>(I, S, tile, lds, red, last);
+                if constexpr (FULL && BIG && !CPLX) batch_row<T, CPLX, 12, true>(I, S, tile, lds, red, last);
+                else done = false;
                 break;
             case 16:
-                if constexpr (BIG) batch_row<T, CPLX, 16, true>(I, S, tile, lds, red, last);
+                if constexpr (FULL && BIG) batch_row<T, CPLX, 16, true>(I, S, tile, lds, red, last);
+                else done = false;
                 break;
-            default: break;
+            default: done = false; break;
             }
         } else {
             switch (X.C) {
@@ -567,15 +577,23 @@ __device__ __forceinline__ void batch_sweep(KP<BInst> I, const BState &S, int pa
             case 2: batch_row<T, CPLX, 2, false>(I, S, tile, lds, red, last); break;
             case 3: batch_row<T, CPLX, 3, false>(I, S, tile, lds, red, last); break;
             case 4: batch_row<T, CPLX, 4, false>(I, S, tile, lds, red, last); break;
-            case 6: batch_row<T, CPLX, 6, false>(I, S, tile, lds, red, last); break;
-            case 8: batch_row<T, CPLX, 8, false>(I, S, tile, lds, red, last); break;
+            case 6:
+                if constexpr (FULL) batch_row<T, CPLX, 6, false>(I, S, tile, lds, red, last);
+                else done = false;
+                break;
+            case 8:
+                if constexpr (FULL) batch_row<T, CPLX, 8, false>(I, S, tile, lds, red, last);
+                else done = false;
+                break;
             case 12:
-                if constexpr (!CPLX) batch_row<T, CPLX, 12, false>(I, S, tile, lds, red, last);
+                if constexpr (FULL && !CPLX) batch_row<T, CPLX, 12, false>(I, S, tile, lds, red, last);
+                else done = false;
                 break;
             case 16:
-                if constexpr (!CPLX) batch_row<T, CPLX, 16, false>(I, S, tile, lds, red, last);
+                if constexpr (FULL && !CPLX) batch_row<T, CPLX, 16, false>(I, S, tile, lds, red, last);
+                else done = false;
                 break;
-            default: break;
+            default: done = false; break;
             }
         }
     } else {
@@ -594,16 +612,21 @@ __device__ __forceinline__ void batch_sweep(KP<BInst> I, const BState &S, int pa
             break;
         case 16:
             if constexpr (BIG && !CPLX) batch_col<T, CPLX, 16>(I, pass, tile, lds, red, last);
+            else done = false;
             break;
-        default: break;
+        default: done = false; break;
         }
     }
+    return done;
 }
 
 // BIG adds the variants for 1D lines longer than 8192 points (12 or 16
-// points per thread over the whole block), whose registers the other paths
-// do not need.
-template <bool BIG>
+// points per thread over the whole block) and y/z chunks of 16, whose
+// registers the other paths do not need.  FULL adds the x-line forms of 1D
+// instances (and the solo cycle); the host launches the other form when the
+// list holds only 2D and 3D items with at most 4 points per thread on x
+// (an item outside the form sets error bit 2 instead of running).
+template <bool BIG, bool FULL>
 __global__ void __launch_bounds__(BATCH_BLOCK) k_batch_step(BatchArgs a)
 {
     extern __shared__ unsigned char lds_raw[];
@@ -624,6 +647,10 @@ __global__ void __launch_bounds__(BATCH_BLOCK) k_batch_step(BatchArgs a)
         BState &S = a.state[w.slot];
         if (S.status != BS_RUNNING) continue;
         const bool solo = w.pass == BP_SOLO;
+        if (!FULL && solo) {
+            if (threadIdx.x == 0) atomicOr(&a.ctl->error, 4);
+            continue;
+        }
 
         // wait until the instance's previous pass has completed (bounded)
         const int dep = solo ? -1 : I.dep[w.pass];
@@ -666,8 +693,9 @@ __global__ void __launch_bounds__(BATCH_BLOCK) k_batch_step(BatchArgs a)
         for (int k = 1;;) {
             if (pass <= BP_Z) {
                 KP<BInst> Ik = (KP<BInst>)a.inst + w.slot;
-                if (I.elem == 1) batch_sweep<float, false, BIG>(Ik, S, pass, w.tile, lds_raw, red);
-                else batch_sweep<float, true, BIG>(Ik, S, pass, w.tile, lds_raw, red);
+                const bool ok = I.elem == 1 ? batch_sweep<float, false, BIG, FULL>(Ik, S, pass, w.tile, lds_raw, red)
+                                            : batch_sweep<float, true, BIG, FULL>(Ik, S, pass, w.tile, lds_raw, red);
+                if (!ok && threadIdx.x == 0) atomicOr(&a.ctl->error, 4);
             } else if (pass == BP_OBS) {
                 if (I.elem == 1) batch_obs<float, false>(I, S, w.tile, redq);
                 else batch_obs<float, true>(I, S, w.tile, redq);
@@ -767,10 +795,12 @@ __global__ void k_batch_unit(double *scale)
     if (threadIdx.x == 0) *scale = 1.0;
 }
 
-hipError_t launch_batch_step(const BatchArgs &a, bool big, int grid, size_t lds, hipStream_t st)
+hipError_t launch_batch_step(const BatchArgs &a, bool big, bool full, int grid, size_t lds, hipStream_t st)
 {
-    if (big) hipLaunchKernelGGL(k_batch_step<true>, dim3(grid), dim3(BATCH_BLOCK), lds, st, a);
-    else hipLaunchKernelGGL(k_batch_step<false>, dim3(grid), dim3(BATCH_BLOCK), lds, st, a);
+    if (big && full) hipLaunchKernelGGL((k_batch_step<true, true>), dim3(grid), dim3(BATCH_BLOCK), lds, st, a);
+    else if (big) hipLaunchKernelGGL((k_batch_step<true, false>), dim3(grid), dim3(BATCH_BLOCK), lds, st, a);
+    else if (full) hipLaunchKernelGGL((k_batch_step<false, true>), dim3(grid), dim3(BATCH_BLOCK), lds, st, a);
+    else hipLaunchKernelGGL((k_batch_step<false, false>), dim3(grid), dim3(BATCH_BLOCK), lds, st, a);
     return hipGetLastError();
 }
 
@@ -784,8 +814,11 @@ hipError_t launch_batch_solo(const BatchArgs &a, bool big, int grid, size_t lds,
 
 hipError_t batch_step_occupancy(bool big, size_t lds, int *blocks_per_cu)
 {
-    if (big) return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batch_step<true>, BATCH_BLOCK, lds);
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batch_step<false>, BATCH_BLOCK, lds);
+    // (the forms with every x-line variant: the others take no more
+    // registers or LDS)
+    if (big)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batch_step<true, true>, BATCH_BLOCK, lds);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batch_step<false, true>, BATCH_BLOCK, lds);
 }
 
 hipError_t launch_batch_scale(int elem, void *psi, int64_t npts, double *scale, hipStream_t st)

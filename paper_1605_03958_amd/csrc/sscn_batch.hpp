@@ -113,7 +113,8 @@ struct BCtl {
     int32_t ticket;
     int32_t exited;
     int32_t total_items;
-    int32_t error;         // bit 0: a bounded wait gave up; bit 1: a solo line had no register-resident form
+    int32_t error;         // bit 0: a bounded wait gave up; bit 1: a solo line had no register-resident form;
+                           // bit 2: an item's form was not in the launched kernel form
     int32_t max_slots;
     int32_t solo_min;      // steps a solo item takes before it may stop early
     int32_t reg_epoch;     // persistent launches completed since the work list was uploaded
@@ -129,7 +130,7 @@ struct BatchArgs {
     int32_t spin_limit;
 };
 
-hipError_t launch_batch_step(const BatchArgs &a, bool big, int grid, size_t lds, hipStream_t st);
+hipError_t launch_batch_step(const BatchArgs &a, bool big, bool full, int grid, size_t lds, hipStream_t st);
 hipError_t launch_batch_solo(const BatchArgs &a, bool big, int grid, size_t lds, hipStream_t st, int steps,
                              int target);
 hipError_t batch_step_occupancy(bool big, size_t lds, int *blocks_per_cu);

@@ -336,6 +336,7 @@ struct sscn_batch {
     bool dirty;
     int mode;                       // MODE_* of the current work list
     int32_t n_fast;                 // solo items at the head of the list that the solo kernel runs
+    bool full;                      // the persistent kernel's list needs its form with every x-line variant
     hipStream_t st2;                // second stream of MODE_SPLIT (null without a caller stream)
     hipEvent_t ev_fork, ev_join;
     int32_t total;
@@ -431,6 +432,14 @@ static hipError_t upload_items(sscn_batch *b)
     else b->mode = MODE_UNION;
     // the persistent kernel's list: without the fast solo items in SPLIT
     *b->h_total = b->mode == MODE_SPLIT ? b->total - b->n_fast : b->total;
+    // its kernel form: every x-line variant when the list holds a 1D or solo
+    // item or an x line of more than 4 points per thread, else the form
+    // without them (fewer spilled registers)
+    b->full = false;
+    for (int k = b->mode == MODE_SPLIT ? b->n_fast : 0; k < b->total && !b->full; ++k) {
+        const BInst &I = b->h_inst[b->h_items[k].slot];
+        if (I.solo || I.dim == 1 || I.ax[0].C > 4) b->full = true;
+    }
     b->h_total[3] = 0;                                     // the launch count restarts with the list
     b->reg_launched = 0;
     if (b->total > 0) {
@@ -565,6 +574,7 @@ int sscn_batch_create(int32_t max_slots, int64_t max_items, void *d_ctl, size_t 
     b->dirty = true;
     b->mode = MODE_UNION;
     b->n_fast = 0;
+    b->full = true;
     b->reg_launched = 0;
     b->st2 = nullptr;
     b->ev_fork = b->ev_join = nullptr;
@@ -791,7 +801,7 @@ int sscn_batch_step(sscn_batch *b, int32_t nsteps)
         const int grid = solo ? items : std::max(1, std::min(cap, items));
         auto launch = [&]() {
             return solo ? launch_batch_solo(a, big, grid, kBatchLds, b->st, BATCH_SOLO_ONLY, -1)
-                        : launch_batch_step(a, big, grid, kBatchLds, b->st);
+                        : launch_batch_step(a, big, b->full, grid, kBatchLds, b->st);
         };
         if (split) {
             // the solo kernel on the second stream, once for the whole call:
@@ -811,7 +821,8 @@ int sscn_batch_step(sscn_batch *b, int32_t nsteps)
                 if (launch() != hipSuccess) return SSCN_E_HIP;
         } else {
             // replayed from a graph per (steps, launch shape, list offset)
-            const auto key = std::make_pair(nsteps, (int64_t)(4 * grid + (big ? 2 : 0) + (solo ? 1 : 0)) * 65536 +
+            const auto key = std::make_pair(nsteps, (int64_t)(8 * grid + (b->full ? 4 : 0) + (big ? 2 : 0) + (solo ? 1 : 0)) *
+                                                            65536 +
                                                         (split ? b->n_fast : 0));
             auto it = b->graphs.find(key);
             if (it == b->graphs.end() && b->graphs.size() >= 16) {
