@@ -337,6 +337,7 @@ struct sscn_batch {
     int mode;                       // MODE_* of the current work list
     int32_t n_fast;                 // solo items at the head of the list that the solo kernel runs
     bool full;                      // the persistent kernel's list needs its form with every x-line variant
+    bool big_step, big_solo;        // its items (and the fast solo items) need the BIG forms
     hipStream_t st2;                // second stream of MODE_SPLIT (null without a caller stream)
     hipEvent_t ev_fork, ev_join;
     int32_t total;
@@ -365,13 +366,6 @@ static bool solo_fast_ok(const BInst &I)
 }
 static BInst *dinst(sscn_batch *b) { return reinterpret_cast<BInst *>(b->ctl + b->lay.inst); }
 static BState *dstate(sscn_batch *b) { return reinterpret_cast<BState *>(b->ctl + b->lay.state); }
-
-static bool batch_big(const sscn_batch *b)
-{
-    for (int i = 0; i < b->max_slots; ++i)
-        if (b->used[i] && b->plan[i].big) return true;
-    return false;
-}
 
 // Work list in dependency order: every pass of every slot before the next pass.
 static int64_t count_items(const sscn_batch *b)
@@ -439,6 +433,13 @@ static hipError_t upload_items(sscn_batch *b)
     for (int k = b->mode == MODE_SPLIT ? b->n_fast : 0; k < b->total && !b->full; ++k) {
         const BInst &I = b->h_inst[b->h_items[k].slot];
         if (I.solo || I.dim == 1 || I.ax[0].C > 4) b->full = true;
+    }
+    // the BIG forms, for each kernel only where its own items need them
+    b->big_step = b->big_solo = false;
+    for (int k = 0; k < b->total; ++k) {
+        if (!b->plan[b->h_items[k].slot].big) continue;
+        if (k < b->n_fast) b->big_solo = true;
+        if (b->mode != MODE_SPLIT || k >= b->n_fast) b->big_step = true;
     }
     b->h_total[3] = 0;                                     // the launch count restarts with the list
     b->reg_launched = 0;
@@ -575,6 +576,7 @@ int sscn_batch_create(int32_t max_slots, int64_t max_items, void *d_ctl, size_t 
     b->mode = MODE_UNION;
     b->n_fast = 0;
     b->full = true;
+    b->big_step = b->big_solo = false;
     b->reg_launched = 0;
     b->st2 = nullptr;
     b->ev_fork = b->ev_join = nullptr;
@@ -782,9 +784,9 @@ int sscn_batch_step(sscn_batch *b, int32_t nsteps)
     if (!b || nsteps < 0) return SSCN_E_INVALID;
     if (b->dirty && upload_items(b) != hipSuccess) return SSCN_E_HIP;
     if (nsteps > 0 && b->total > 0) {
-        const bool big = batch_big(b);
         const bool solo = b->mode == MODE_SOLO_ONLY;
         const bool split = b->mode == MODE_SPLIT;
+        const bool big = solo ? b->big_solo : b->big_step;   // the form this call's graph launches
         // the launches on the caller's stream: the persistent kernel over the
         // list (in SPLIT, the part after the fast solo items, with a grid that
         // leaves the solo blocks' CUs free), or the solo kernel alone.  No
@@ -811,7 +813,7 @@ int sscn_batch_step(sscn_batch *b, int32_t nsteps)
             b->reg_launched += nsteps;
             const int steps = (int)std::min<int64_t>(1 << 30, (int64_t)nsteps * BATCH_SOLO_MAX);
             if (hipEventRecord(b->ev_fork, b->st) != hipSuccess || hipStreamWaitEvent(b->st2, b->ev_fork, 0) != hipSuccess ||
-                launch_batch_solo(a_solo, big, b->n_fast, kBatchLds, b->st2, steps, (int32_t)b->reg_launched) !=
+                launch_batch_solo(a_solo, b->big_solo, b->n_fast, kBatchLds, b->st2, steps, (int32_t)b->reg_launched) !=
                     hipSuccess ||
                 hipEventRecord(b->ev_join, b->st2) != hipSuccess)
                 return SSCN_E_HIP;
