@@ -497,7 +497,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp32", action="store_true")
-    ap.add_argument("--only", choices=["cube", "fp64", "fp32", "batch", "batch_active", "densities", "dynamics", "sym"],
+    ap.add_argument("--only", choices=["cube", "fp64", "fp32", "batch", "batch_active", "densities", "dynamics", "sym",
+                                       "ground64"],
                     default=None,
                     help="run only the two 256^3 legs (cube), one precision, the batch, the densities or the "
                          "dynamics pipeline (profiling runs)")
@@ -534,6 +535,9 @@ def main():
         return
     if args.only == "sym":
         print(json.dumps({"symmetric": sym_timing()}), flush=True)
+        return
+    if args.only == "ground64":
+        print(json.dumps({"ground64": ground64_timing()}), flush=True)
         return
     out = {}
     # the complex64 leg runs first: the GPU then enters the complex128 leg,
