@@ -451,6 +451,7 @@ struct sscn_solver {
     // which of their steps renormalise; their kernel arguments hold g
     std::map<int64_t, hipGraphExec_t> graphs;
     bool graphs_off;          // capture failed once on this stream: launch directly
+    bool pending;             // inside sscn_run: the last renormalisation factor is not yet applied to psi
     int static_dev;           // sscn_create_noalloc: the device whose static workspace it holds, else -1
 };
 
@@ -735,7 +736,26 @@ static hipError_t prepare_graphs(sscn_solver *s, int64_t nsteps)
     return hipSuccess;
 }
 
-static hipError_t enqueue_steps(sscn_solver *s, int64_t nsteps, Timer *tm)
+// A pending renormalisation factor applied to psi (and the factor reset).
+static hipError_t finalize_state(sscn_solver *s, Timer *tm)
+{
+    if (!s->pending) return hipSuccess;
+    s->pending = false;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (tm) tm->pair(4, e0, e1);
+    hipError_t e = hipSuccess;
+    if (e0 && (e = hipEventRecord(e0, s->st)) != hipSuccess) return e;
+    if ((e = launch_scale_state(s->P.elem, s->psi, s->P.npts, scal_ptr(s), s->P.pw_grid, 256, s->st)) != hipSuccess)
+        return e;
+    if ((e = launch_set_unit_scale(scal_ptr(s), s->st)) != hipSuccess) return e;
+    if (e1 && (e = hipEventRecord(e1, s->st)) != hipSuccess) return e;
+    return hipSuccess;
+}
+
+// finalize: apply a pending renormalisation factor to psi at the end (every
+// public call that returns a state); sscn_run's observations take it in
+// their loads instead and the run applies it once at its end.
+static hipError_t enqueue_steps(sscn_solver *s, int64_t nsteps, Timer *tm, bool finalize = true)
 {
     if (nsteps <= 0) return hipSuccess;
     const bool imag = s->pb.mode == SSCN_IMAG;
@@ -764,18 +784,10 @@ static hipError_t enqueue_steps(sscn_solver *s, int64_t nsteps, Timer *tm)
         last_renorm = do_renorm;
         prev_renorm = do_renorm;
     }
-    if (imag && last_renorm) {
-        hipEvent_t e0 = nullptr, e1 = nullptr;
-        if (tm) tm->pair(4, e0, e1);
-        hipError_t e = hipSuccess;
-        if (e0 && (e = hipEventRecord(e0, s->st)) != hipSuccess) return e;
-        if ((e = launch_scale_state(s->P.elem, s->psi, s->P.npts, scal_ptr(s), s->P.pw_grid, 256, s->st)) !=
-            hipSuccess)
-            return e;
-        if ((e = launch_set_unit_scale(scal_ptr(s), s->st)) != hipSuccess) return e;
-        if (e1 && (e = hipEventRecord(e1, s->st)) != hipSuccess) return e;
-    }
-    return hipSuccess;
+    // the steps consumed any earlier factor (in the first x sweep's load);
+    // the last one leaves a new one when it renormalised
+    s->pending = imag && last_renorm;
+    return finalize ? finalize_state(s, tm) : hipSuccess;
 }
 
 // ---------------------------------------------------------------------------
@@ -1126,6 +1138,7 @@ static hipError_t obs_enqueue(sscn_solver *s, double **dobs_out, double *dest = 
     }
     oa.npts = P.npts;
     oa.partial = reinterpret_cast<double *>(s->ws + P.off_obspart);
+    oa.scale = s->pending ? scal_ptr(s) : nullptr;
     hipError_t e = launch_obs_partials(P.elem, oa, P.obs_grid, 256, s->st);
     if (e == hipSuccess) e = launch_obs_final(oa.partial, P.obs_grid, dv, s->g, dobs, s->st);
     return e;
@@ -1195,7 +1208,8 @@ static int run_queued(sscn_solver *s, int64_t max_steps, sscn_obs *trace, int64_
             int64_t k = every - (s->step % every);
             if (k > max_steps - done) k = max_steps - done;
             double *dobs = nullptr;
-            if (sscn_step(s, k) != SSCN_OK || obs_enqueue(s, &dobs, dstage + 13 * nq) != hipSuccess) {
+            if (enqueue_steps(s, k, nullptr, s->pb.geom != SSCN_GEOM_CART) != hipSuccess ||
+                obs_enqueue(s, &dobs, dstage + 13 * nq) != hipSuccess) {
                 (void)hipStreamSynchronize(s->st);
                 (void)hipHostFree(stage);
                 return SSCN_E_HIP;
@@ -1220,6 +1234,7 @@ static int run_queued(sscn_solver *s, int64_t max_steps, sscn_obs *trace, int64_
         }
     }
     (void)hipHostFree(stage);
+    if (finalize_state(s, nullptr) != hipSuccess) return SSCN_E_HIP;
     if (rows) *rows = std::min(nrow, trace_cap);
     return rc;
 }
@@ -1231,6 +1246,7 @@ int sscn_run(sscn_solver *s, int64_t max_steps, double mu_tol, sscn_obs *trace, 
     if (trace_cap < 0 || (trace_cap > 0 && !trace)) return SSCN_E_INVALID;
     if (mu_tol == 0.0) return run_queued(s, max_steps, trace, trace_cap, rows);
     const int64_t every = s->pb.observe_every;
+    const bool fin_each = s->pb.geom != SSCN_GEOM_CART;   // symmetric traps: finalize every interval
     int64_t nrow = 0, done = 0;
     bool have_prev = false;
     double prev = 0.0;
@@ -1239,7 +1255,9 @@ int sscn_run(sscn_solver *s, int64_t max_steps, double mu_tol, sscn_obs *trace, 
         // advance to the next observation step (global step multiple of `every`)
         int64_t k = every - (s->step % every);
         if (k > max_steps - done) k = max_steps - done;
-        if (sscn_step(s, k) != SSCN_OK) return SSCN_E_HIP;
+        // (Cartesian problems leave the renormalisation pending between
+        // observations: the observation kernel applies it to its loads)
+        if (enqueue_steps(s, k, nullptr, fin_each) != hipSuccess) return SSCN_E_HIP;
         done += k;
         sscn_obs o;
         int r = sscn_observe(s, &o);
@@ -1258,6 +1276,7 @@ int sscn_run(sscn_solver *s, int64_t max_steps, double mu_tol, sscn_obs *trace, 
         prev = o.mu;
         have_prev = true;
     }
+    if (finalize_state(s, nullptr) != hipSuccess) return SSCN_E_HIP;
     if (rows) *rows = std::min(nrow, trace_cap);
     return rc;
 }

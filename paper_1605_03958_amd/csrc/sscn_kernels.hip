@@ -325,6 +325,10 @@ __global__ void __launch_bounds__(256) k_obs_partials(ObsArgs a)
     const long long stride = (long long)gridDim.x * blockDim.x;
     long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     int idx[3] = {(int)(p % nx), (int)((p / nx) % ny), (int)(p / (nx * ny))};
+    // a state whose renormalisation is still pending: every value is taken
+    // times the factor, as the pass that applies it would store it
+    const bool scaled = !CPLX && a.scale != nullptr;
+    const T sc = scaled ? T(*a.scale) : T(1);
     const int di = (int)(stride % nx), dj = (int)((stride / nx) % ny), dk = (int)(stride / (nx * ny));
     (void)nz;
     // U grid-stride points per pass: all their loads (the point and its
@@ -361,6 +365,11 @@ __global__ void __launch_bounds__(256) k_obs_partials(ObsArgs a)
 #pragma unroll
             for (int ax = 0; ax < 3; ++ax)
                 nb[u][ax] = (in && ax < a.dim && id[u][ax] + 1 < a.n[ax]) ? psi[pu + sx[ax]] : A::zero();
+            if (scaled) {
+                v[u] = A::scal(sc, v[u]);
+#pragma unroll
+                for (int ax = 0; ax < 3; ++ax) nb[u][ax] = A::scal(sc, nb[u][ax]);
+            }
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {

@@ -93,6 +93,7 @@ struct ObsArgs {
     double dx[3], cen[3], w2h[3];
     int64_t npts;
     double *partial;       // 12 doubles per block
+    const double *scale;   // non-null: a pending renormalisation factor applied to every loaded value
 };
 hipError_t launch_obs_partials(int elem, const ObsArgs &a, int grid, int block, hipStream_t st);
 // out[0..15]: norm, mu, E, K, P, I, <x>, <y>, <z>, <x^2>, <y^2>, <z^2>, finite flag

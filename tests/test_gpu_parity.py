@@ -342,15 +342,19 @@ def test_nonfinite_state_reported():
 
 
 @pytest.mark.parametrize("mode", [IMAG, REAL])
-def test_run_without_convergence_test_equals_observing_by_hand(mode):
-    """mu_tol = 0 queues the observations without waits; the rows are those
-    of stepping to each observation step and observing, bit for bit
-    (observe_every = 7 and a cap between observations)."""
+@pytest.mark.parametrize("tol", [0.0, 1e-300])
+def test_run_without_convergence_test_equals_observing_by_hand(mode, tol):
+    """mu_tol = 0 queues the observations without waits, a tolerance never
+    met observes and tests after every interval; either way (with the
+    renormalisation left pending between observations and applied in the
+    observation's loads) the rows and the final state are those of stepping
+    to each observation step and observing, bit for bit (observe_every = 7
+    and a cap between observations)."""
     p = Problem(3, (40, 36, 30), (0.25, 0.25, 0.3), (1.0, 1.5, 2.0), 10.0,
                 0.01 if mode == IMAG else 0.002, mode, F64, 1 if mode == IMAG else 0, 7)
     psi0 = initial(p, 5)
     a = sscn.Solver(p, psi0)
-    rc, rows = a.run(103, 0.0)
+    rc, rows = a.run(103, tol)
     assert rc == sscn.NOT_CONVERGED
     b = sscn.Solver(p, psi0)
     want, done = [], 0
